@@ -1,0 +1,190 @@
+/*
+ * rad.h -- C ABI of librad, the MI355X (gfx950) radiation-integral library.
+ *
+ * The library evaluates, on one GPU, the radiation integrals of Nielsen,
+ * "GPU accelerated simulation of channeling radiation of relativistic
+ * particles" (arXiv:1910.10391), Sec. II:
+ *
+ *   classical (eq. (integralrad1)-(integralrad2)), in the Sec. II small-angle
+ *   expansion:  d2I/(d hw dOmega) = alpha/(4 pi^2) |A(k)|^2,
+ *     A(kappa) = int f(t, n) exp(i kappa psi(t, n)) dt,  k = hw / (hbar c),
+ *     psi = (1/(2 gamma^2) + theta^2/2) t - dz - n_x x - n_y y;
+ *   spin-0, substitution model (eq. (Lindhard_substi)):
+ *     alpha/(4 pi^2) (E* / E) |A(k*)|^2,  k* = k E / (E - hw),  E* = E - hw;
+ *   spin-1/2, BCK model (eq. (cue)-(Iterm)):
+ *     alpha/(4 pi^2) [ (E*^2 + E^2)/(2 E^2) |A(k*)|^2 + hw^2/(2 E^2 gamma^2) |J(k*)|^2 ],
+ *     J(kappa) = int (n . beta_dot)/(1 - n . beta)^2 exp(i kappa psi) dt,
+ *     with n . beta_dot expanded as n_x a_x + n_y a_y + a_z;
+ *   sections (Sec. II, end): a trajectory is cut into segments with the energy
+ *   fixed at each segment's entry; the spectrum of the trajectory is the sum
+ *   of the segment spectra;
+ *   dI/d hw (Sec. IV): the sum of the cube over the angular cells.
+ *
+ * Conventions shared by every call:
+ *   - Units: c = 1, t and lengths in metres, velocities are beta, accelerations
+ *     are d(beta)/dt in 1/m, photon and particle energies in eV.  Output spectra
+ *     are d2I/(d hw dOmega), dimensionless.
+ *   - Cube layout: [n_w][n_y][n_x], row-major (x fastest), FP64.
+ *   - Pointers marked DEVICE are GPU global-memory pointers on the current HIP
+ *     device (e.g. torch's data_ptr()); HOST pointers are CPU memory.  The
+ *     caller owns every buffer.  A grid handle owns only its own device copy of
+ *     the grid.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
+ *     calls are asynchronous on it and make no host synchronisation.
+ *   - Workspaces are caller-provided device memory; compute calls allocate no
+ *     device memory.
+ *   - Errors: every call returns a status and never aborts or throws across the
+ *     ABI.  Arguments are validated before any launch; on error nothing is
+ *     launched and rad_last_error() holds a message (thread-local).
+ *   - A photon energy hw >= E is kinematically forbidden in the quantum
+ *     spectra: those entries are 0, not an error.
+ *   - Results are bitwise reproducible run to run (fixed-order reductions, no
+ *     floating-point atomics).
+ */
+#ifndef RAD_H
+#define RAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rad_grid rad_grid; /* opaque, immutable after setup */
+
+typedef enum {
+    RAD_OK = 0,
+    RAD_EINVAL = 1,       /* invalid argument (null pointer, bad size, bad value) */
+    RAD_ENOMEM = 2,       /* workspace too small, or device allocation failed in setup */
+    RAD_EDEVICE = 3,      /* HIP runtime error (no device, launch failure) */
+    RAD_EUNSUPPORTED = 4  /* valid request the library does not implement */
+} rad_status;
+
+typedef enum { RAD_CLASSICAL = 1, RAD_SPIN0 = 2, RAD_SPINHALF = 4 } rad_kind; /* bitmask */
+
+typedef enum {
+    RAD_FP64 = 0,  /* FP64 throughout */
+    RAD_MIXED = 1  /* FP64 phase, range reduction and accumulation; FP32 integrand and sincos */
+} rad_precision;
+
+/*
+ * One trajectory segment (the paper's section, Sec. II), columns as DEVICE
+ * pointers, each n FP64 values (structure of arrays), in the small-angle
+ * variables of Sec. II: dz = z - beta0 t, dvz = v_z - beta0 with
+ * beta0 = 1 - 1/(2 gamma^2).
+ */
+typedef struct {
+    int64_t n;               /* samples, >= 2 */
+    const double *t;         /* time (= path length, c = 1) [m], increasing */
+    const double *x, *y;     /* transverse position [m] */
+    const double *dz;        /* z - beta0 t [m] */
+    const double *vx, *vy;   /* transverse beta */
+    const double *dvz;       /* v_z - beta0 */
+    const double *ax, *ay, *az; /* d(beta)/dt [1/m] */
+    const double *w;         /* quadrature weights [m], or NULL for the trapezoid rule from t */
+    double gamma;            /* Lorentz factor of the expansion reference (> 0) */
+    double energy_eV;        /* particle energy E at segment entry (> 0; quantum kinds only) */
+} rad_segment;
+
+/*
+ * Build a grid handle: photon energies hw_eV[n_w] (> 0), directions
+ * thx[n_x] = n_x and thy[n_y] = n_y [rad] (HOST arrays, copied).  The angle
+ * integral uses cell widths half-way between neighbours (a single point has
+ * width 1).  Allocates device memory; may synchronise `stream`.
+ * Errors: RAD_EINVAL for null pointers, sizes < 1 or non-finite values;
+ * RAD_ENOMEM / RAD_EDEVICE on allocation or copy failure.
+ */
+rad_status rad_setup_grid(const double *hw_eV, int n_w, const double *thx, int n_x,
+                          const double *thy, int n_y, void *stream, rad_grid **out);
+
+/* Release a grid handle (NULL is ignored).  The caller must not free it while
+ * calls that use it are still running on a stream. */
+void rad_free_grid(rad_grid *grid);
+
+/* Grid sizes (any pointer may be NULL). */
+rad_status rad_grid_dims(const rad_grid *grid, int *n_w, int *n_x, int *n_y);
+
+/*
+ * Workspace bytes that rad_classical / rad_quantum need for any segment with
+ * n <= max_n samples and the given kinds (RAD_CLASSICAL for rad_classical, a
+ * subset of RAD_SPIN0|RAD_SPINHALF for rad_quantum) and precision.  0 on
+ * invalid arguments.
+ */
+size_t rad_workspace_bytes(const rad_grid *grid, int64_t max_n, int kinds, rad_precision prec);
+
+/* Workspace bytes rad_batch needs for exactly this list of segments (HOST array)
+ * and n_out outputs.  0 on invalid arguments. */
+size_t rad_batch_workspace_bytes(const rad_grid *grid, const rad_segment *segs, int n_segs,
+                                 int n_out, int kinds, rad_precision prec);
+
+/*
+ * Classical spectrum of one segment (Sec. II eq. (integralrad1)).
+ * out: DEVICE [n_w][n_y][n_x] FP64, overwritten.  ws: DEVICE workspace of
+ * ws_bytes >= rad_workspace_bytes(grid, seg->n, RAD_CLASSICAL, prec).
+ * Errors: RAD_EINVAL (null pointers, n < 2, gamma <= 0), RAD_ENOMEM (ws too
+ * small), RAD_EDEVICE (launch failure).
+ */
+rad_status rad_classical(const rad_grid *grid, const rad_segment *seg, rad_precision prec,
+                         double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Semi-classical spectra of one segment: kinds is a non-empty subset of
+ * RAD_SPIN0 | RAD_SPINHALF (Sec. II eq. (Lindhard_substi) and eq. (cue)).
+ * out: DEVICE [popcount(kinds)][n_w][n_y][n_x], spin-0 first, overwritten.
+ * Needs seg->energy_eV > 0.  Errors as rad_classical.
+ */
+rad_status rad_quantum(const rad_grid *grid, const rad_segment *seg, int kinds, rad_precision prec,
+                       double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Many segments in one call (uneven lengths), summed per output: segment s is
+ * added to output out_index[s] (HOST array, 0 <= out_index[s] < n_out); the
+ * sum runs in segment order, so it is deterministic (Sec. II, sections).
+ * kinds: any non-empty subset of RAD_CLASSICAL | RAD_SPIN0 | RAD_SPINHALF.
+ * out: DEVICE [n_out][popcount(kinds)][n_w][n_y][n_x], kinds in the order
+ * classical, spin-0, spin-1/2; overwritten (outputs with no segment are 0).
+ * ws_bytes >= rad_batch_workspace_bytes(grid, segs, n_segs, kinds, prec).
+ */
+rad_status rad_batch(const rad_grid *grid, const rad_segment *segs, int n_segs,
+                     const int *out_index, int n_out, int kinds, rad_precision prec, double *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Angle integral (Sec. IV): dIdw[c][i] = sum_{jy,jx} cube[c][i][jy][jx] dthx[jx] dthy[jy]
+ * for n_cubes consecutive DEVICE cubes; dIdw is DEVICE [n_cubes][n_w].
+ */
+rad_status rad_angle_integrate(const rad_grid *grid, const double *cube, int n_cubes, double *dIdw,
+                               void *stream);
+
+/* Static text of a status code. */
+const char *rad_status_string(rad_status status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rad_last_error(void);
+
+/*
+ * Tuning knobs of the amplitude kernel (process-wide).  A variant fixes the
+ * direction tile each lane owns and the resident blocks per CU it is compiled
+ * for; `with_j` selects the integral set that also carries J (spin-1/2).
+ * Every variant computes the same sums; only the speed differs.
+ * rad_tune_set_variant: RAD_EINVAL for an unknown variant.
+ */
+rad_status rad_tune_set_variant(int with_j, int variant);
+rad_status rad_tune_get_variant(int with_j, int *variant);
+int rad_tune_num_variants(void);
+
+/*
+ * Kernel timing for benchmarks: when enabled, every launch of the amplitude
+ * kernel is bracketed by HIP events on the caller's stream.  rad_profile_read
+ * waits for the recorded events and returns the summed kernel time [ms] and
+ * the number of launches since the last reset.
+ */
+rad_status rad_profile_enable(int on);
+rad_status rad_profile_read(double *kernel_ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAD_H */

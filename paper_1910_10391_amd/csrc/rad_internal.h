@@ -1,0 +1,79 @@
+// Internal data structures shared by the host library and the kernels of librad.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rad {
+
+// CODATA 2018
+constexpr double kHbarC_eVm = 1.973269804e-7;   // hbar c [eV m]
+constexpr double kAlpha = 7.2973525693e-3;      // fine-structure constant
+constexpr double kPi = 3.14159265358979323846;
+
+// Kernel tile shape: each lane owns one photon energy and a TX x TY block of
+// directions; a wave is 64 photon energies; a block is 4 waves.
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSlots = 64;   // time-steps x direction-tiles staged in LDS per pass
+
+// Amplitude-kernel variants: direction tile TX x TY and minimum resident blocks per CU.
+enum Variant { kVar44x2 = 0, kVar43x2 = 1, kVar44x1 = 2, kVar42x2 = 3, kNumVariants = 4 };
+constexpr int kVarTX[kNumVariants] = {4, 4, 4, 4};
+constexpr int kVarTY[kNumVariants] = {4, 3, 4, 2};
+
+enum Column { C_T = 0, C_X, C_Y, C_DZ, C_VX, C_VY, C_DVZ, C_AX, C_AY, C_AZ, C_NCOL };
+
+// One segment as the kernels see it.
+struct SegDesc {
+    const double *col[C_NCOL];
+    const double *w;       // nullable -> trapezoid
+    int64_t n;
+    double c0;             // 1 / (2 gamma^2)
+    double gamma;
+    double energy;         // eV
+    int64_t part_off;      // offset (in double2) of this segment's partial amplitudes in the set
+    int32_t n_chunks;
+    int32_t chunk_len;
+    int64_t block_begin;   // first block of this segment in the amplitude launch
+};
+
+// One amplitude launch: one "set" (classical kappa = k, or quantum kappa = k*).
+struct AmpLaunch {
+    const SegDesc *segs;   // in launch (longest-first) order
+    int n_segs;
+    int64_t n_blocks;
+    const double *hw;      // [n_w] eV
+    const double *k;       // [n_w] 1/m
+    const double *thx;     // [n_x]
+    const double *thy;     // [n_y]
+    int n_w, n_x, n_y;
+    int n_tx, n_ty;        // direction tiles along x, y
+    int wg;                // waves per block spread over photon energies (1, 2, 4)
+    int nt;                // direction tiles per block (4 / wg)
+    int n_groups;          // ceil(n_tx * n_ty / nt)
+    int n_wblocks;         // ceil(n_w / (64 wg))
+    int quantum;           // 0: kappa = k; 1: kappa = k E/(E - hw)
+    int comps;             // 2 (A_x, A_y) or 3 (A_x, A_y, J)
+    double2 *part;         // partial amplitudes [seg][chunk][comp][n][w]
+};
+
+// Finalize: per output, the segments that feed it, in segment order.
+struct FinLaunch {
+    const int *out_seg_begin;   // [n_out + 1]
+    const int *out_seg_list;    // segment ids (index into cls/qsegs) in order
+    const SegDesc *cls;         // classical-set descriptors by segment id (or null)
+    const SegDesc *qs;          // quantum-set descriptors by segment id (or null)
+    const double2 *part_c;      // classical partials
+    const double2 *part_q;      // quantum partials
+    int comps_q;                // 2 or 3
+    const double *hw, *thx, *thy;
+    int n_w, n_x, n_y;
+    int n_out;
+    int kinds;
+    int n_kinds;
+    double *out;                // [n_out][n_kinds][n_w][n_y][n_x]
+};
+
+}  // namespace rad

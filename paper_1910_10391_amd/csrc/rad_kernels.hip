@@ -1,0 +1,374 @@
+// Radiation-integral kernels for gfx950 (CDNA4).
+//
+// amp_kernel   : complex amplitudes A_x, A_y (and J) of one time chunk of a
+//                segment for 64*wg photon energies x nt direction tiles.
+// fin_kernel   : fixed-order sum over chunks and segments, |A|^2, the
+//                classical / spin-0 / spin-1/2 weights, written to the cube.
+// angle_kernel : dI/d hw, the weighted sum of each cube row over directions.
+//
+// Method (Nielsen, arXiv:1910.10391, Sec. II): for every photon energy and
+// direction n = (thx, thy), sum over time samples
+//     A += w f(t, n) exp(i kappa psi(t, n)),   J += w Q(t, n) exp(i kappa psi(t, n)),
+// with the small-angle expansion of Sec. II:
+//     D   = 1/(2g^2) + th^2/2 - dvz - thx vx - thy vy,   G = w / D^2,
+//     C   = 1/(2g^2) - th^2/2 - dvz,
+//     f_x = [(az + thy ay)(thx - vx) - (thy (thy - vy) + C) ax] G,
+//     f_y = [(az + thx ax)(thy - vy) - (thx (thx - vx) + C) ay] G,
+//     Q   = (thx ax + thy ay + az) G,
+//     psi = (1/(2g^2) + th^2/2) t - dz - thx x - thy y.
+// f_z is not accumulated: thx f_x + thy f_y + f_z = 0 identically, so
+// A_z = -(thx A_x + thy A_y) is formed in fin_kernel.
+//
+// Work decomposition (one block = 4 waves = 256 lanes):
+//   * a lane owns one photon energy (kappa in a register) and a TX x TY tile of
+//     directions, with TX*TY complex accumulators per component in VGPRs;
+//   * the integrand f, Q (shared by every photon energy) and the two parts of
+//     the phase are computed once per (time step, direction) by the whole
+//     block into LDS, then read by each wave as a broadcast (one address);
+//   * the phase separates, psi = Px(t, thx) + Py(t, thy) with
+//     Px = 1/(2g^2) t - dz + thx (thx t/2 - x), Py = thy (thy t/2 - y), so a lane
+//     evaluates TX + TY phase factors per time step and forms the TX*TY
+//     factors exp(i kappa psi) = exp(i kappa Px) exp(i kappa Py) by complex
+//     products;
+//   * a long segment is cut into time chunks whose FP64 partial amplitudes are
+//     summed in chunk order by fin_kernel.
+#include <hip/hip_runtime.h>
+
+#include "rad_internal.h"
+#include "rad_math.h"
+
+namespace rad {
+
+// Phase factor of a lane: FP64 polynomial on half turns, or FP32 hardware
+// sin/cos on revolutions (mixed precision).  `kh` is kappa/pi (FP64 form) or
+// kappa/(2 pi) (mixed form).
+template <bool MIXED>
+__device__ __forceinline__ void lane_cis(double kh, double part, double &c, double &s)
+{
+    if constexpr (MIXED) {
+        float cf, sf;
+        cis_revolutions_f32(kh * part, cf, sf);
+        c = (double)cf;
+        s = (double)sf;
+    } else {
+        cis_halfturns(kh * part, c, s);
+    }
+}
+
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+__global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
+{
+    constexpr int NP = TX * TY;
+    __shared__ double2 s_fxy[kSlots * NP];
+    __shared__ double s_fq[WITHJ ? kSlots * NP : 1];
+    __shared__ double s_px[kSlots * TX];
+    __shared__ double s_py[kSlots * TY];
+    __shared__ int s_seg;
+
+    // segment of this block: last s with block_begin <= blockIdx.x
+    const int64_t b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = L.n_segs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.segs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+        }
+        s_seg = lo;
+    }
+    __syncthreads();
+    const SegDesc &S = L.segs[s_seg];
+    const int64_t n = S.n;
+    const double c0 = S.c0;
+    const double energy = S.energy;
+    const double *__restrict__ ct = S.col[C_T];
+    const double *__restrict__ cx = S.col[C_X];
+    const double *__restrict__ cy = S.col[C_Y];
+    const double *__restrict__ cdz = S.col[C_DZ];
+    const double *__restrict__ cvx = S.col[C_VX];
+    const double *__restrict__ cvy = S.col[C_VY];
+    const double *__restrict__ cdvz = S.col[C_DVZ];
+    const double *__restrict__ cax = S.col[C_AX];
+    const double *__restrict__ cay = S.col[C_AY];
+    const double *__restrict__ caz = S.col[C_AZ];
+    const double *__restrict__ cw = S.w;
+
+    int64_t local = b - S.block_begin;
+    const int wb = (int)(local % L.n_wblocks);
+    local /= L.n_wblocks;
+    const int grp = (int)(local % L.n_groups);
+    const int chunk = (int)(local / L.n_groups);
+    const int64_t k_begin = (int64_t)chunk * S.chunk_len;
+    const int64_t k_end = min(n, k_begin + (int64_t)S.chunk_len);
+
+    const int nt = L.nt, wg = L.wg;
+    const int T = kSlots / nt;
+    const int n_tiles = L.n_tx * L.n_ty;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int tl = wave / wg;
+    const int iw = (wb * wg + wave % wg) * kWave + lane;
+    const int gtile = grp * nt + tl;
+
+    double kappa = 0.0;
+    if (iw < L.n_w) {
+        const double k = L.k[iw];
+        if (!L.quantum) {
+            kappa = k;
+        } else {
+            const double hw = L.hw[iw];
+            kappa = hw < energy ? k * energy / (energy - hw) : 0.0;
+        }
+    }
+    const double kh = MIXED ? kappa * (0.5 / kPi) : kappa * (1.0 / kPi);
+
+    double axr[NP], axi[NP], ayr[NP], ayi[NP], jr[WITHJ ? NP : 1], ji[WITHJ ? NP : 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        axr[p] = axi[p] = ayr[p] = ayi[p] = 0.0;
+        if constexpr (WITHJ) jr[p] = ji[p] = 0.0;
+    }
+
+    for (int64_t k0 = k_begin; k0 < k_end; k0 += T) {
+        __syncthreads();
+        // ---- stage: integrand and phase parts for kSlots (t, tile) pairs
+        for (int i = threadIdx.x; i < kSlots * NP; i += kBlock) {
+            const int slot = i / NP, p = i % NP;
+            const int tloc = slot / nt, tile = slot % nt;
+            const int64_t k = k0 + tloc;
+            const int gt = grp * nt + tile;
+            const int jx = (gt % L.n_tx) * TX + p % TX;
+            const int jy = (gt / L.n_tx) * TY + p / TX;
+            double fx = 0.0, fy = 0.0, fq = 0.0;
+            if (k < k_end && gt < n_tiles && jx < L.n_x && jy < L.n_y) {
+                const double thx = L.thx[jx], thy = L.thy[jy];
+                const double vx = cvx[k], vy = cvy[k], dvz = cdvz[k];
+                const double ax = cax[k], ay = cay[k], az = caz[k];
+                const double w = cw ? cw[k]
+                                    : 0.5 * (ct[k + 1 < n ? k + 1 : n - 1] - ct[k > 0 ? k - 1 : 0]);
+                const double th2h = 0.5 * (thx * thx + thy * thy);
+                const double D = ((c0 + th2h) - dvz) - thx * vx - thy * vy;
+                const double C = (c0 - th2h) - dvz;
+                if constexpr (MIXED) {
+                    // FP32 integrand; D and C are formed in FP64 (they are
+                    // small differences) and rounded once.
+                    const float Df = (float)D, Cf = (float)C;
+                    const float G = (float)w / (Df * Df);
+                    const float tx = (float)thx, ty = (float)thy;
+                    const float vxf = (float)vx, vyf = (float)vy;
+                    const float axf = (float)ax, ayf = (float)ay, azf = (float)az;
+                    fx = (double)(((azf + ty * ayf) * (tx - vxf) - (ty * (ty - vyf) + Cf) * axf) * G);
+                    fy = (double)(((azf + tx * axf) * (ty - vyf) - (tx * (tx - vxf) + Cf) * ayf) * G);
+                    fq = (double)((tx * axf + ty * ayf + azf) * G);
+                } else {
+                    const double G = w / (D * D);
+                    fx = ((az + thy * ay) * (thx - vx) - (thy * (thy - vy) + C) * ax) * G;
+                    fy = ((az + thx * ax) * (thy - vy) - (thx * (thx - vx) + C) * ay) * G;
+                    fq = (thx * ax + thy * ay + az) * G;
+                }
+            }
+            s_fxy[i] = make_double2(fx, fy);
+            if constexpr (WITHJ) s_fq[i] = fq;
+        }
+        for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
+            const int slot = i / (TX + TY), j = i % (TX + TY);
+            const int tloc = slot / nt, tile = slot % nt;
+            const int64_t k = k0 + tloc;
+            const int gt = grp * nt + tile;
+            double v = 0.0;
+            if (k < k_end && gt < n_tiles) {
+                const double t = ct[k];
+                if (j < TX) {
+                    const int jx = (gt % L.n_tx) * TX + j;
+                    const double thx = jx < L.n_x ? L.thx[jx] : 0.0;
+                    v = (c0 * t - cdz[k]) + thx * (0.5 * thx * t - cx[k]);
+                } else {
+                    const int jy = (gt / L.n_tx) * TY + (j - TX);
+                    const double thy = jy < L.n_y ? L.thy[jy] : 0.0;
+                    v = thy * (0.5 * thy * t - cy[k]);
+                }
+            }
+            if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
+        }
+        __syncthreads();
+        // ---- accumulate: every lane, its photon energy, its direction tile
+        const int tn = (int)min<int64_t>((int64_t)T, k_end - k0);
+        for (int tloc = 0; tloc < tn; ++tloc) {
+            const int slot = tloc * nt + tl;
+            double xr[TX], xi[TX];
+#pragma unroll
+            for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
+#pragma unroll
+            for (int jy = 0; jy < TY; ++jy) {
+                double yr, yi;
+                lane_cis<MIXED>(kh, s_py[slot * TY + jy], yr, yi);
+#pragma unroll
+                for (int jx = 0; jx < TX; ++jx) {
+                    const int p = jy * TX + jx;
+                    const double er = xr[jx] * yr - xi[jx] * yi;
+                    const double ei = xr[jx] * yi + xi[jx] * yr;
+                    const double2 f = s_fxy[slot * NP + p];
+                    axr[p] = __builtin_fma(f.x, er, axr[p]);
+                    axi[p] = __builtin_fma(f.x, ei, axi[p]);
+                    ayr[p] = __builtin_fma(f.y, er, ayr[p]);
+                    ayi[p] = __builtin_fma(f.y, ei, ayi[p]);
+                    if constexpr (WITHJ) {
+                        const double q = s_fq[slot * NP + p];
+                        jr[p] = __builtin_fma(q, er, jr[p]);
+                        ji[p] = __builtin_fma(q, ei, ji[p]);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- partial amplitudes of this chunk: part[seg][chunk][comp][n][w]
+    if (iw >= L.n_w || gtile >= n_tiles) return;
+    const int64_t n_n = (int64_t)L.n_x * L.n_y;
+    const int64_t base = S.part_off + (int64_t)chunk * L.comps * n_n * L.n_w;
+    const int tx0 = (gtile % L.n_tx) * TX, ty0 = (gtile / L.n_tx) * TY;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int jx = tx0 + p % TX, jy = ty0 + p / TX;
+        if (jx >= L.n_x || jy >= L.n_y) continue;
+        const int64_t nn = (int64_t)jy * L.n_x + jx;
+        L.part[base + (0 * n_n + nn) * L.n_w + iw] = make_double2(axr[p], axi[p]);
+        L.part[base + (1 * n_n + nn) * L.n_w + iw] = make_double2(ayr[p], ayi[p]);
+        if constexpr (WITHJ) L.part[base + (2 * n_n + nn) * L.n_w + iw] = make_double2(jr[p], ji[p]);
+    }
+}
+
+__device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
+                                           int comps, int comp, int64_t n_n, int n_w, int64_t nn,
+                                           int iw, double &re, double &im)
+{
+    re = 0.0;
+    im = 0.0;
+    const int64_t stride = (int64_t)comps * n_n * n_w;
+    const double2 *p = part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw;
+    for (int c = 0; c < d.n_chunks; ++c) {
+        const double2 v = p[(int64_t)c * stride];
+        re += v.x;
+        im += v.y;
+    }
+}
+
+__global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
+{
+    const int64_t n_n = (int64_t)F.n_x * F.n_y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int o = blockIdx.y;
+    if (i >= n_n * F.n_w) return;
+    const int iw = (int)(i % F.n_w);
+    const int64_t nn = i / F.n_w;
+    const int jx = (int)(nn % F.n_x), jy = (int)(nn / F.n_x);
+    const double thx = F.thx[jx], thy = F.thy[jy], hw = F.hw[iw];
+    const double pref = kAlpha / (4.0 * kPi * kPi);
+    double sc = 0.0, s0 = 0.0, sh = 0.0;
+    for (int e = F.out_seg_begin[o]; e < F.out_seg_begin[o + 1]; ++e) {
+        const int s = F.out_seg_list[e];
+        if (F.kinds & 1) {
+            const SegDesc &d = F.cls[s];
+            double xr, xi, yr, yi;
+            sum_chunks(F.part_c, d, 2, 0, n_n, F.n_w, nn, iw, xr, xi);
+            sum_chunks(F.part_c, d, 2, 1, n_n, F.n_w, nn, iw, yr, yi);
+            const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
+            sc += pref * (xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi);
+        }
+        if (F.kinds & 6) {
+            const SegDesc &d = F.qs[s];
+            const double E = d.energy;
+            if (hw < E) {
+                double xr, xi, yr, yi;
+                sum_chunks(F.part_q, d, F.comps_q, 0, n_n, F.n_w, nn, iw, xr, xi);
+                sum_chunks(F.part_q, d, F.comps_q, 1, n_n, F.n_w, nn, iw, yr, yi);
+                const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
+                const double S = xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi;
+                const double Es = E - hw;
+                if (F.kinds & 2) s0 += pref * (Es / E) * S;
+                if (F.kinds & 4) {
+                    double jr_, ji_;
+                    sum_chunks(F.part_q, d, F.comps_q, 2, n_n, F.n_w, nn, iw, jr_, ji_);
+                    const double SJ = jr_ * jr_ + ji_ * ji_;
+                    sh += pref * ((Es * Es + E * E) / (2.0 * E * E) * S +
+                                  hw * hw / (2.0 * E * E * d.gamma * d.gamma) * SJ);
+                }
+            }
+        }
+    }
+    const int64_t cube = n_n * F.n_w;
+    const int64_t dst = (int64_t)iw * n_n + nn;
+    double *out = F.out + (int64_t)o * F.n_kinds * cube;
+    int kk = 0;
+    if (F.kinds & 1) out[(kk++) * cube + dst] = sc;
+    if (F.kinds & 2) out[(kk++) * cube + dst] = s0;
+    if (F.kinds & 4) out[(kk++) * cube + dst] = sh;
+}
+
+// dIdw[c][i] = sum_{jy, jx} cube[c][i][jy][jx] wx[jx] wy[jy]; one block per (i, c),
+// a fixed strided partial sum per thread and a fixed tree: deterministic.
+__global__ __launch_bounds__(256) void angle_kernel(const double *__restrict__ cube,
+                                                    const double *__restrict__ wx,
+                                                    const double *__restrict__ wy, int n_x,
+                                                    int n_y, int n_w, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x, c = blockIdx.y;
+    const int64_t n_n = (int64_t)n_x * n_y;
+    const double *row = cube + ((int64_t)c * n_w + i) * n_n;
+    double acc = 0.0;
+    for (int64_t p = threadIdx.x; p < n_n; p += blockDim.x) {
+        const int jx = (int)(p % n_x), jy = (int)(p / n_x);
+        acc += row[p] * wx[jx] * wy[jy];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)c * n_w + i] = red[0];
+}
+
+// ---------------------------------------------------------------- launchers
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+static hipError_t launch_amp_t(const AmpLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL((amp_kernel<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)L.n_blocks),
+                       dim3(kBlock), 0, st, L);
+    return hipGetLastError();
+}
+
+template <bool WITHJ, bool MIXED>
+static hipError_t launch_amp_v(const AmpLaunch &L, int variant, hipStream_t st)
+{
+    switch (variant) {
+    case kVar44x2: return launch_amp_t<4, 4, WITHJ, MIXED, 2>(L, st);
+    case kVar43x2: return launch_amp_t<4, 3, WITHJ, MIXED, 2>(L, st);
+    case kVar44x1: return launch_amp_t<4, 4, WITHJ, MIXED, 1>(L, st);
+    case kVar42x2: return launch_amp_t<4, 2, WITHJ, MIXED, 2>(L, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, hipStream_t st)
+{
+    if (withj) return mixed ? launch_amp_v<true, true>(L, variant, st) : launch_amp_v<true, false>(L, variant, st);
+    return mixed ? launch_amp_v<false, true>(L, variant, st) : launch_amp_v<false, false>(L, variant, st);
+}
+
+hipError_t launch_fin(const FinLaunch &F, hipStream_t st)
+{
+    const int64_t items = (int64_t)F.n_x * F.n_y * F.n_w;
+    const unsigned gx = (unsigned)((items + 255) / 256);
+    hipLaunchKernelGGL(fin_kernel, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
+                        int n_w, int n_cubes, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(angle_kernel, dim3((unsigned)n_w, (unsigned)n_cubes), dim3(256), 0, st, cube,
+                       wx, wy, n_x, n_y, n_w, out);
+    return hipGetLastError();
+}
+
+}  // namespace rad

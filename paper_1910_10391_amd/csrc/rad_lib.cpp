@@ -1,0 +1,660 @@
+// librad: host side of the C ABI declared in include/rad.h.
+//
+// Validates every argument on the host (including that device buffers lie
+// inside a device allocation large enough for what the kernels touch), plans
+// the launch (time chunks, block counts, longest-segment-first order), writes
+// the segment descriptors into the caller's workspace and launches:
+//   amp_kernel (one launch per integral set: kappa = k and/or kappa = k*),
+//   fin_kernel (fixed-order reduction and spectrum weights),
+//   angle_kernel (rad_angle_integrate).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rad.h"
+#include "rad_internal.h"
+
+namespace rad {
+hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, hipStream_t st);
+hipError_t launch_fin(const FinLaunch &F, hipStream_t st);
+hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
+                        int n_w, int n_cubes, double *out, hipStream_t st);
+}  // namespace rad
+
+using namespace rad;
+
+struct rad_grid {
+    int n_w = 0, n_x = 0, n_y = 0;
+    int device = 0;
+    double *d_hw = nullptr, *d_k = nullptr, *d_thx = nullptr, *d_thy = nullptr;
+    double *d_wx = nullptr, *d_wy = nullptr;
+    std::vector<double> hw, thx, thy;
+    // pinned staging for descriptor uploads, reused after its last copy completed
+    std::mutex mu;
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
+    bool stage_pending = false;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rad_status fail(rad_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+rad_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RAD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ---- profiling
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pending;
+double g_prof_ms = 0.0;
+int64_t g_prof_launches = 0;
+
+// The device allocation that holds [p, p + bytes) must exist.
+rad_status check_dev_range(const void *p, size_t bytes, const char *name)
+{
+    if (!p) return fail(RAD_EINVAL, "%s is NULL", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RAD_EINVAL, "%s (%p) is not a device allocation", name, p);
+    }
+    const char *b = (const char *)base, *q = (const char *)p;
+    if (q < b || q + bytes > b + size)
+        return fail(RAD_EINVAL, "%s: %zu bytes at %p exceed its device allocation", name, bytes, p);
+    return RAD_OK;
+}
+
+// Kernel variant per integral set: [0] without J, [1] with J.
+std::mutex g_var_mu;
+int g_variant[2] = {kVar44x2, kVar44x2};
+
+int variant_for(bool withj)
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    return g_variant[withj ? 1 : 0];
+}
+
+struct Tile {
+    int variant, wg, nt, n_tx, n_ty, n_groups, n_wblocks;
+    int64_t base_blocks;
+};
+
+// Block shape for a grid and kernel variant; both integral sets of a call use
+// the same chunking, so the tile counts of the larger direction tile decide it.
+Tile plan_tile(const rad_grid *g, int variant)
+{
+    Tile t;
+    t.variant = variant;
+    t.wg = g->n_w > 128 ? 4 : (g->n_w > 64 ? 2 : 1);
+    t.nt = kWavesPerBlock / t.wg;
+    t.n_tx = (g->n_x + kVarTX[variant] - 1) / kVarTX[variant];
+    t.n_ty = (g->n_y + kVarTY[variant] - 1) / kVarTY[variant];
+    const int tiles = t.n_tx * t.n_ty;
+    t.n_groups = (tiles + t.nt - 1) / t.nt;
+    t.n_wblocks = (g->n_w + kWave * t.wg - 1) / (kWave * t.wg);
+    t.base_blocks = (int64_t)t.n_groups * t.n_wblocks;
+    return t;
+}
+
+constexpr int64_t kTargetBlocks = 2048;  // 256 CUs x 2 resident blocks x 4 rounds
+constexpr int64_t kMinChunk = 128;
+
+// chunks per segment when the launch has `n_segs` segments
+int64_t chunk_factor(const Tile &t, int64_t n_segs)
+{
+    const int64_t have = n_segs * t.base_blocks;
+    if (have >= kTargetBlocks) return 1;
+    return (kTargetBlocks + have - 1) / have;
+}
+
+void plan_chunks(int64_t n, int64_t c, int32_t &n_chunks, int32_t &chunk_len)
+{
+    int64_t len = (n + c - 1) / c;
+    len = (len + 63) / 64 * 64;
+    len = std::max(len, kMinChunk);
+    len = std::min(len, n);
+    chunk_len = (int32_t)len;
+    n_chunks = (int32_t)((n + len - 1) / len);
+}
+
+int popcount3(int k) { return (k & 1) + ((k >> 1) & 1) + ((k >> 2) & 1); }
+
+struct Layout {
+    size_t off_amp_c, off_amp_q, off_id_c, off_id_q, off_begin, off_list, off_part_c, off_part_q;
+    size_t desc_bytes;  // bytes of the descriptor region (uploaded)
+    size_t total;
+    int comps_q;
+};
+
+Layout layout(const rad_grid *g, int n_segs, int n_out, int kinds, int64_t sum_chunks)
+{
+    Layout L{};
+    const size_t sd = sizeof(SegDesc) * (size_t)n_segs;
+    size_t o = 0;
+    L.off_amp_c = o; o = align_up(o + sd);
+    L.off_amp_q = o; o = align_up(o + sd);
+    L.off_id_c = o; o = align_up(o + sd);
+    L.off_id_q = o; o = align_up(o + sd);
+    L.off_begin = o; o = align_up(o + sizeof(int) * (size_t)(n_out + 1));
+    L.off_list = o; o = align_up(o + sizeof(int) * (size_t)n_segs);
+    L.desc_bytes = o;
+    const size_t cube2 = (size_t)g->n_w * g->n_x * g->n_y * sizeof(double2);
+    L.comps_q = (kinds & RAD_SPINHALF) ? 3 : 2;
+    L.off_part_c = o;
+    if (kinds & RAD_CLASSICAL) o = align_up(o + (size_t)sum_chunks * 2 * cube2);
+    L.off_part_q = o;
+    if (kinds & (RAD_SPIN0 | RAD_SPINHALF)) o = align_up(o + (size_t)sum_chunks * L.comps_q * cube2);
+    L.total = o;
+    return L;
+}
+
+rad_status check_grid(const rad_grid *g)
+{
+    if (!g) return fail(RAD_EINVAL, "grid is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(RAD_EDEVICE, "no HIP device");
+    if (dev != g->device)
+        return fail(RAD_EINVAL, "grid was built on device %d, current device is %d", g->device, dev);
+    return RAD_OK;
+}
+
+rad_status check_segment(const rad_segment *s, int idx, bool quantum)
+{
+    if (!s) return fail(RAD_EINVAL, "segment %d is NULL", idx);
+    if (s->n < 2) return fail(RAD_EINVAL, "segment %d: n = %lld < 2", idx, (long long)s->n);
+    if (s->n > ((int64_t)1 << 40)) return fail(RAD_EINVAL, "segment %d: n too large", idx);
+    if (!(std::isfinite(s->gamma) && s->gamma > 0.0))
+        return fail(RAD_EINVAL, "segment %d: gamma must be finite and > 0", idx);
+    if (quantum && !(std::isfinite(s->energy_eV) && s->energy_eV > 0.0))
+        return fail(RAD_EINVAL, "segment %d: energy_eV must be finite and > 0", idx);
+    const double *cols[C_NCOL] = {s->t, s->x, s->y, s->dz, s->vx, s->vy, s->dvz, s->ax, s->ay, s->az};
+    static const char *names[C_NCOL] = {"t", "x", "y", "dz", "vx", "vy", "dvz", "ax", "ay", "az"};
+    const size_t bytes = (size_t)s->n * sizeof(double);
+    for (int c = 0; c < C_NCOL; ++c) {
+        rad_status st = check_dev_range(cols[c], bytes, names[c]);
+        if (st != RAD_OK) return fail(st, "segment %d: %s", idx, g_err.c_str());
+    }
+    if (s->w) {
+        rad_status st = check_dev_range(s->w, bytes, "w");
+        if (st != RAD_OK) return fail(st, "segment %d: %s", idx, g_err.c_str());
+    }
+    return RAD_OK;
+}
+
+// Shared driver of rad_classical, rad_quantum and rad_batch.
+rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index, int n_out,
+               int kinds, rad_precision prec, double *out, void *ws, size_t ws_bytes,
+               hipStream_t st)
+{
+    rad_status rs = check_grid(g);
+    if (rs != RAD_OK) return rs;
+    if (kinds <= 0 || kinds > 7) return fail(RAD_EINVAL, "kinds must be a non-empty subset of 1|2|4");
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    if (!segs || n_segs <= 0) return fail(RAD_EINVAL, "no segments");
+    if (!out_index) return fail(RAD_EINVAL, "out_index is NULL");
+    if (n_out <= 0) return fail(RAD_EINVAL, "n_out must be > 0");
+    const bool quantum = (kinds & (RAD_SPIN0 | RAD_SPINHALF)) != 0;
+    for (int s = 0; s < n_segs; ++s) {
+        if (out_index[s] < 0 || out_index[s] >= n_out)
+            return fail(RAD_EINVAL, "out_index[%d] = %d outside [0, %d)", s, out_index[s], n_out);
+        rs = check_segment(&segs[s], s, quantum);
+        if (rs != RAD_OK) return rs;
+    }
+    const bool withj = (kinds & RAD_SPINHALF) != 0;
+    const Tile tile_c = plan_tile(g, variant_for(false));
+    const Tile tile_q = plan_tile(g, variant_for(withj));
+    const Tile &tile = (kinds & RAD_CLASSICAL) ? tile_c : tile_q;   // sets the chunking
+    const int64_t cf = chunk_factor(tile, n_segs);
+    std::vector<int32_t> nch(n_segs), clen(n_segs);
+    int64_t sum_chunks = 0;
+    for (int s = 0; s < n_segs; ++s) {
+        plan_chunks(segs[s].n, cf, nch[s], clen[s]);
+        sum_chunks += nch[s];
+    }
+    const Layout lay = layout(g, n_segs, n_out, kinds, sum_chunks);
+    if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
+    if (ws_bytes < lay.total)
+        return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, lay.total);
+    const int n_kinds = popcount3(kinds);
+    const size_t cube = (size_t)g->n_w * g->n_x * g->n_y;
+    rs = check_dev_range(ws, lay.total, "workspace");
+    if (rs != RAD_OK) return rs;
+    rs = check_dev_range(out, (size_t)n_out * n_kinds * cube * sizeof(double), "out");
+    if (rs != RAD_OK) return rs;
+
+    // launch order: longest segment first (the dispatcher hands out blocks in order)
+    std::vector<int> order(n_segs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return segs[a].n > segs[b].n; });
+
+    char *wsb = (char *)ws;
+    double2 *part_c = (double2 *)(wsb + lay.off_part_c);
+    double2 *part_q = (double2 *)(wsb + lay.off_part_q);
+    std::vector<char> host(lay.desc_bytes, 0);
+    SegDesc *amp_c = (SegDesc *)(host.data() + lay.off_amp_c);
+    SegDesc *amp_q = (SegDesc *)(host.data() + lay.off_amp_q);
+    SegDesc *id_c = (SegDesc *)(host.data() + lay.off_id_c);
+    SegDesc *id_q = (SegDesc *)(host.data() + lay.off_id_q);
+    int *begin = (int *)(host.data() + lay.off_begin);
+    int *list = (int *)(host.data() + lay.off_list);
+
+    std::vector<int64_t> part_off_c(n_segs), part_off_q(n_segs);
+    {
+        int64_t oc = 0, oq = 0;
+        for (int s = 0; s < n_segs; ++s) {
+            part_off_c[s] = oc;
+            part_off_q[s] = oq;
+            oc += (int64_t)nch[s] * 2 * (int64_t)cube;
+            oq += (int64_t)nch[s] * lay.comps_q * (int64_t)cube;
+        }
+    }
+    int64_t blocks_c = 0, blocks_q = 0;
+    for (int r = 0; r < n_segs; ++r) {
+        const int s = order[r];
+        SegDesc d{};
+        const rad_segment &sg = segs[s];
+        const double *cols[C_NCOL] = {sg.t, sg.x, sg.y, sg.dz, sg.vx, sg.vy, sg.dvz, sg.ax, sg.ay, sg.az};
+        for (int c = 0; c < C_NCOL; ++c) d.col[c] = cols[c];
+        d.w = sg.w;
+        d.n = sg.n;
+        d.gamma = sg.gamma;
+        d.c0 = 1.0 / (2.0 * sg.gamma * sg.gamma);
+        d.energy = sg.energy_eV;
+        d.n_chunks = nch[s];
+        d.chunk_len = clen[s];
+        SegDesc dc = d, dq = d;
+        dc.block_begin = blocks_c;
+        dq.block_begin = blocks_q;
+        blocks_c += (int64_t)nch[s] * tile_c.base_blocks;
+        blocks_q += (int64_t)nch[s] * tile_q.base_blocks;
+        dc.part_off = part_off_c[s];
+        dq.part_off = part_off_q[s];
+        amp_c[r] = dc;
+        amp_q[r] = dq;
+        id_c[s] = dc;
+        id_q[s] = dq;
+    }
+    if (std::max(blocks_c, blocks_q) >= ((int64_t)1 << 31) - 1)
+        return fail(RAD_EUNSUPPORTED, "launch of %lld blocks", (long long)std::max(blocks_c, blocks_q));
+    // outputs -> segments in segment order
+    {
+        std::vector<int> cnt(n_out + 1, 0);
+        for (int s = 0; s < n_segs; ++s) cnt[out_index[s] + 1]++;
+        for (int o = 0; o < n_out; ++o) cnt[o + 1] += cnt[o];
+        for (int o = 0; o <= n_out; ++o) begin[o] = cnt[o];
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (int s = 0; s < n_segs; ++s) list[fill[out_index[s]]++] = s;
+    }
+
+    // upload descriptors through the grid's pinned staging buffer
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->stage_pending) {
+            hipError_t e = hipEventSynchronize(g->stage_done);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            g->stage_pending = false;
+        }
+        if (g->stage_bytes < lay.desc_bytes) {
+            if (g->stage) (void)hipHostFree(g->stage);
+            g->stage = nullptr;
+            g->stage_bytes = 0;
+            hipError_t e = hipHostMalloc(&g->stage, lay.desc_bytes, hipHostMallocDefault);
+            if (e != hipSuccess) return fail(RAD_ENOMEM, "pinned staging of %zu bytes", lay.desc_bytes);
+            g->stage_bytes = lay.desc_bytes;
+        }
+        if (!g->stage_done) {
+            hipError_t e = hipEventCreateWithFlags(&g->stage_done, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+        std::memcpy(g->stage, host.data(), lay.desc_bytes);
+        hipError_t e = hipMemcpyAsync(ws, g->stage, lay.desc_bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        e = hipEventRecord(g->stage_done, st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        g->stage_pending = true;
+    }
+
+    AmpLaunch L{};
+    L.n_segs = n_segs;
+    L.hw = g->d_hw;
+    L.k = g->d_k;
+    L.thx = g->d_thx;
+    L.thy = g->d_thy;
+    L.n_w = g->n_w;
+    L.n_x = g->n_x;
+    L.n_y = g->n_y;
+    auto set_tile = [&](const Tile &t, int64_t nb) {
+        L.n_blocks = nb;
+        L.n_tx = t.n_tx;
+        L.n_ty = t.n_ty;
+        L.wg = t.wg;
+        L.nt = t.nt;
+        L.n_groups = t.n_groups;
+        L.n_wblocks = t.n_wblocks;
+    };
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    if (prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return fail(RAD_EDEVICE, "hipEventCreate for profiling");
+        (void)hipEventRecord(ev0, st);
+    }
+    const bool mixed = prec == RAD_MIXED;
+    if (kinds & RAD_CLASSICAL) {
+        set_tile(tile_c, blocks_c);
+        L.segs = (const SegDesc *)(wsb + lay.off_amp_c);
+        L.quantum = 0;
+        L.comps = 2;
+        L.part = part_c;
+        hipError_t e = launch_amp(L, tile_c.variant, false, mixed, st);
+        if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
+    }
+    if (quantum) {
+        set_tile(tile_q, blocks_q);
+        L.segs = (const SegDesc *)(wsb + lay.off_amp_q);
+        L.quantum = 1;
+        L.comps = lay.comps_q;
+        L.part = part_q;
+        hipError_t e = launch_amp(L, tile_q.variant, lay.comps_q == 3, mixed, st);
+        if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
+    }
+    if (prof) {
+        (void)hipEventRecord(ev1, st);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_pending.emplace_back(ev0, ev1);
+    }
+
+    FinLaunch F{};
+    F.out_seg_begin = (const int *)(wsb + lay.off_begin);
+    F.out_seg_list = (const int *)(wsb + lay.off_list);
+    F.cls = (const SegDesc *)(wsb + lay.off_id_c);
+    F.qs = (const SegDesc *)(wsb + lay.off_id_q);
+    F.part_c = part_c;
+    F.part_q = part_q;
+    F.comps_q = lay.comps_q;
+    F.hw = g->d_hw;
+    F.thx = g->d_thx;
+    F.thy = g->d_thy;
+    F.n_w = g->n_w;
+    F.n_x = g->n_x;
+    F.n_y = g->n_y;
+    F.n_out = n_out;
+    F.kinds = kinds;
+    F.n_kinds = n_kinds;
+    F.out = out;
+    hipError_t e = launch_fin(F, st);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+    return RAD_OK;
+}
+
+size_t workspace_for(const rad_grid *g, const std::vector<int64_t> &ns, int n_out, int kinds, bool bound)
+{
+    const bool withj = (kinds & RAD_SPINHALF) != 0;
+    const Tile tile = plan_tile(g, (kinds & RAD_CLASSICAL) ? variant_for(false) : variant_for(withj));
+    const int64_t cf = chunk_factor(tile, (int64_t)ns.size());
+    int64_t sum = 0;
+    for (int64_t n : ns) {
+        if (bound) {
+            sum += std::min<int64_t>(cf, (n + kMinChunk - 1) / kMinChunk);
+        } else {
+            int32_t c, l;
+            plan_chunks(n, cf, c, l);
+            sum += c;
+        }
+    }
+    return layout(g, (int)ns.size(), n_out, kinds, sum).total;
+}
+
+std::vector<double> cell_widths(const std::vector<double> &th)
+{
+    const size_t n = th.size();
+    std::vector<double> w(n, 1.0);
+    if (n < 2) return w;
+    for (size_t i = 1; i + 1 < n; ++i) w[i] = 0.5 * (th[i + 1] - th[i - 1]);
+    w[0] = th[1] - th[0];
+    w[n - 1] = th[n - 1] - th[n - 2];
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rad_status_string(rad_status s)
+{
+    switch (s) {
+    case RAD_OK: return "ok";
+    case RAD_EINVAL: return "invalid argument";
+    case RAD_ENOMEM: return "out of memory / workspace too small";
+    case RAD_EDEVICE: return "HIP device error";
+    case RAD_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *rad_last_error(void) { return g_err.c_str(); }
+
+rad_status rad_setup_grid(const double *hw_eV, int n_w, const double *thx, int n_x, const double *thy,
+                          int n_y, void *stream, rad_grid **out)
+{
+    if (!out) return fail(RAD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!hw_eV || !thx || !thy) return fail(RAD_EINVAL, "grid arrays must not be NULL");
+    if (n_w < 1 || n_x < 1 || n_y < 1) return fail(RAD_EINVAL, "grid sizes must be >= 1");
+    if ((int64_t)n_w * n_x * n_y > ((int64_t)1 << 31))
+        return fail(RAD_EINVAL, "grid of %lld points is too large", (long long)n_w * n_x * n_y);
+    for (int i = 0; i < n_w; ++i)
+        if (!(std::isfinite(hw_eV[i]) && hw_eV[i] > 0.0)) return fail(RAD_EINVAL, "hw_eV[%d] must be finite and > 0", i);
+    for (int i = 0; i < n_x; ++i)
+        if (!std::isfinite(thx[i]) || std::fabs(thx[i]) >= 1.0) return fail(RAD_EINVAL, "thx[%d] invalid", i);
+    for (int i = 0; i < n_y; ++i)
+        if (!std::isfinite(thy[i]) || std::fabs(thy[i]) >= 1.0) return fail(RAD_EINVAL, "thy[%d] invalid", i);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(RAD_EDEVICE, "no HIP device");
+    rad_grid *g = new rad_grid();
+    g->n_w = n_w;
+    g->n_x = n_x;
+    g->n_y = n_y;
+    g->device = dev;
+    g->hw.assign(hw_eV, hw_eV + n_w);
+    g->thx.assign(thx, thx + n_x);
+    g->thy.assign(thy, thy + n_y);
+    std::vector<double> k(n_w);
+    for (int i = 0; i < n_w; ++i) k[i] = hw_eV[i] / kHbarC_eVm;
+    const std::vector<double> wx = cell_widths(g->thx), wy = cell_widths(g->thy);
+    struct { double **dst; const double *src; size_t n; } arrs[] = {
+        {&g->d_hw, hw_eV, (size_t)n_w}, {&g->d_k, k.data(), (size_t)n_w},
+        {&g->d_thx, thx, (size_t)n_x},  {&g->d_thy, thy, (size_t)n_y},
+        {&g->d_wx, wx.data(), (size_t)n_x}, {&g->d_wy, wy.data(), (size_t)n_y}};
+    for (auto &a : arrs) {
+        hipError_t e = hipMalloc((void **)a.dst, a.n * sizeof(double));
+        if (e != hipSuccess) {
+            rad_free_grid(g);
+            return fail(RAD_ENOMEM, "hipMalloc for the grid: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpyAsync(*a.dst, a.src, a.n * sizeof(double), hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            rad_free_grid(g);
+            return hip_fail(e, "grid upload");
+        }
+    }
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        rad_free_grid(g);
+        return hip_fail(e, "grid upload");
+    }
+    *out = g;
+    return RAD_OK;
+}
+
+void rad_free_grid(rad_grid *g)
+{
+    if (!g) return;
+    if (g->stage_pending && g->stage_done) (void)hipEventSynchronize(g->stage_done);
+    if (g->stage_done) (void)hipEventDestroy(g->stage_done);
+    if (g->stage) (void)hipHostFree(g->stage);
+    for (double *p : {g->d_hw, g->d_k, g->d_thx, g->d_thy, g->d_wx, g->d_wy})
+        if (p) (void)hipFree(p);
+    delete g;
+}
+
+rad_status rad_grid_dims(const rad_grid *g, int *n_w, int *n_x, int *n_y)
+{
+    if (!g) return fail(RAD_EINVAL, "grid is NULL");
+    if (n_w) *n_w = g->n_w;
+    if (n_x) *n_x = g->n_x;
+    if (n_y) *n_y = g->n_y;
+    return RAD_OK;
+}
+
+size_t rad_workspace_bytes(const rad_grid *g, int64_t max_n, int kinds, rad_precision prec)
+{
+    if (!g || max_n < 2 || kinds <= 0 || kinds > 7) return 0;
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    return workspace_for(g, {max_n}, 1, kinds, true);
+}
+
+size_t rad_batch_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int n_out,
+                                 int kinds, rad_precision prec)
+{
+    if (!g || !segs || n_segs <= 0 || n_out <= 0 || kinds <= 0 || kinds > 7) return 0;
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    std::vector<int64_t> ns(n_segs);
+    for (int s = 0; s < n_segs; ++s) {
+        if (segs[s].n < 2) return 0;
+        ns[s] = segs[s].n;
+    }
+    return workspace_for(g, ns, n_out, kinds, false);
+}
+
+rad_status rad_classical(const rad_grid *g, const rad_segment *seg, rad_precision prec, double *out,
+                         void *ws, size_t ws_bytes, void *stream)
+{
+    const int zero = 0;
+    return run(const_cast<rad_grid *>(g), seg, 1, &zero, 1, RAD_CLASSICAL, prec, out, ws, ws_bytes,
+               (hipStream_t)stream);
+}
+
+rad_status rad_quantum(const rad_grid *g, const rad_segment *seg, int kinds, rad_precision prec,
+                       double *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (kinds <= 0 || (kinds & ~(RAD_SPIN0 | RAD_SPINHALF)))
+        return fail(RAD_EINVAL, "rad_quantum kinds must be a non-empty subset of RAD_SPIN0|RAD_SPINHALF");
+    const int zero = 0;
+    return run(const_cast<rad_grid *>(g), seg, 1, &zero, 1, kinds, prec, out, ws, ws_bytes,
+               (hipStream_t)stream);
+}
+
+rad_status rad_batch(const rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index,
+                     int n_out, int kinds, rad_precision prec, double *out, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    return run(const_cast<rad_grid *>(g), segs, n_segs, out_index, n_out, kinds, prec, out, ws,
+               ws_bytes, (hipStream_t)stream);
+}
+
+rad_status rad_angle_integrate(const rad_grid *g, const double *cube, int n_cubes, double *dIdw,
+                               void *stream)
+{
+    rad_status rs = check_grid(g);
+    if (rs != RAD_OK) return rs;
+    if (n_cubes <= 0) return fail(RAD_EINVAL, "n_cubes must be > 0");
+    const size_t cb = (size_t)g->n_w * g->n_x * g->n_y * sizeof(double);
+    rs = check_dev_range(cube, cb * n_cubes, "cube");
+    if (rs != RAD_OK) return rs;
+    rs = check_dev_range(dIdw, (size_t)n_cubes * g->n_w * sizeof(double), "dIdw");
+    if (rs != RAD_OK) return rs;
+    hipError_t e = launch_angle(cube, g->d_wx, g->d_wy, g->n_x, g->n_y, g->n_w, n_cubes, dIdw,
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "angle kernel launch");
+    return RAD_OK;
+}
+
+rad_status rad_tune_set_variant(int with_j, int variant)
+{
+    if (variant < 0 || variant >= kNumVariants) return fail(RAD_EINVAL, "variant %d unknown", variant);
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_variant[with_j ? 1 : 0] = variant;
+    return RAD_OK;
+}
+
+rad_status rad_tune_get_variant(int with_j, int *variant)
+{
+    if (!variant) return fail(RAD_EINVAL, "variant is NULL");
+    *variant = variant_for(with_j != 0);
+    return RAD_OK;
+}
+
+int rad_tune_num_variants(void) { return kNumVariants; }
+
+rad_status rad_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return RAD_OK;
+}
+
+rad_status rad_profile_read(double *kernel_ms, int64_t *launches, int reset)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        pend.swap(g_prof_pending);
+    }
+    double ms = 0.0;
+    for (auto &pr : pend) {
+        float m = 0.0f;
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&m, pr.first, pr.second);
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+        if (e != hipSuccess) return hip_fail(e, "profiling events");
+        ms += m;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_ms += ms;
+    g_prof_launches += (int64_t)pend.size();
+    if (kernel_ms) *kernel_ms = g_prof_ms;
+    if (launches) *launches = g_prof_launches;
+    if (reset) {
+        g_prof_ms = 0.0;
+        g_prof_launches = 0;
+    }
+    return RAD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+"""The C-ABI library loads on the CPU and exports every function include/rad.h declares.
+
+No compute call is made here (there is no GPU in the CPU suite); only calls
+that the header defines to fail validation before touching a device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rad.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rad_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1910_10391_amd import rad
+    if not os.path.exists(rad.LIB_PATH):
+        from paper_1910_10391_amd import build
+        build.build()
+    return rad.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rad_setup_grid", "rad_classical", "rad_quantum", "rad_batch",
+                     "rad_workspace_bytes", "rad_batch_workspace_bytes", "rad_angle_integrate",
+                     "rad_free_grid", "rad_status_string", "rad_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for s in range(5):
+        assert lib.rad_status_string(s)
+    assert b"unknown" in lib.rad_status_string(99)
+
+
+def test_validation_before_device(lib):
+    D = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_double * 2)(1.0, 2.0)
+    # sizes < 1, NULL arrays and non-finite values are rejected before any HIP call
+    assert lib.rad_setup_grid(arr, 0, arr, 1, arr, 1, None, ctypes.byref(h)) == 1
+    assert lib.rad_setup_grid(None, 2, arr, 1, arr, 1, None, ctypes.byref(h)) == 1
+    bad = (ctypes.c_double * 1)(float("nan"))
+    assert lib.rad_setup_grid(bad, 1, arr, 1, arr, 1, None, ctypes.byref(h)) == 1
+    assert b"hw_eV" in lib.rad_last_error()
+    assert lib.rad_workspace_bytes(None, 100, 1, 0) == 0
+    assert lib.rad_batch_workspace_bytes(None, None, 0, 1, 1, 0) == 0
+    assert lib.rad_tune_set_variant(0, 99) == 1
+    assert lib.rad_tune_num_variants() >= 1
