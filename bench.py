@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the radiation-integral hot path on one MI355X.
+
+Workload (one "step" = one pass of the whole path over one batch): 256
+positrons at 10 GeV channeled in a planar harmonic+quartic well (depth 20 eV,
+width 1.92 A), 100 um, with multiple scattering and radiative loss, 4e4..1.2e5
+samples per trajectory; spin-1/2 (BCK) spectrum on 512 log-spaced photon
+energies in 0.5..200 MeV x 32 x 32 directions within 5/gamma; FP64.  Inputs are
+seeded, synthetic and resident in HBM before the timed region.
+
+Prints one JSON line: evals/s (one eval = one (t, w, n) term), trajectories/s,
+the mixed-precision form's speed-up and error on the same workload, the
+roofline of the amplitude kernel (HIP events on the library's stream) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = ("(t·ω·n) integrand evals/s and trajectories/s; "
+          "mixed vs FP64 at stated rel err")
+
+# MI355X: 256 CUs x 64 FP64 lanes x 2 flops (FMA) x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # VALU lane-instructions per second, 1e12
+# FP64 flops per (t, w, n) eval of the amplitude kernel as built (4x4 direction
+# tile, 8 phase factors per time step; FMA = 2): phase factors 8 x 36 / 16,
+# complex product 6, accumulation 2 per complex component.
+FLOPS_PER_EVAL = {"spinhalf": 36.0, "classical": 32.0}
+# VALU instructions per eval in the compiled hot loop (365 per 16 evals with J,
+# 332 without), counted from the gfx950 assembly of this build.
+VALU_PER_EVAL = {"spinhalf": 365.0 / 16.0, "classical": 332.0 / 16.0}
+# HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
+# (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
+# for the kernel sources they were measured on (sha256 prefix below).
+KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
+                  "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
+MEASURED_TRAFFIC = {"sources_sha256": "a5538fbd0ded16d9", "particles": 256, "bytes_per_launch": 2.119e10}
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--particles", type=int, default=256)
+    p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run one device copy of known size first (counter scale factor)")
+    return p.parse_args()
+
+
+def build_workload(n_particles):
+    from paper_1910_10391_amd.synth import channeling, presets
+    cfg = presets.positron_config()
+    trs = channeling.generate(cfg, n_particles, threads=min(16, os.cpu_count() or 1))
+    segs = [tr[0] for tr in trs]
+    grid = presets.positron_grid()
+    return cfg, segs, grid
+
+
+def sample_points(segs, grid):
+    """The bounded sample: 2 shortest + 2 longest trajectories, every 8th photon
+    energy, an 8 x 8 strided subset of directions."""
+    order = np.argsort([s["t"].size for s in segs], kind="stable")
+    traj = sorted(set([int(order[0]), int(order[1]), int(order[-1]), int(order[-2])]))
+    iw = np.arange(0, len(grid.hw_eV), 8)
+    ix = np.arange(0, len(grid.thx), max(1, len(grid.thx) // 8))
+    iy = np.arange(0, len(grid.thy), max(1, len(grid.thy) // 8))
+    return traj, iw, ix, iy
+
+
+def cpu_baseline(segs, grid, traj, iw, ix, iy):
+    import oracle
+    hw, thx, thy = grid.hw_eV[iw], grid.thx[ix], grid.thy[iy]
+    threads = oracle.max_threads()
+    evals = 0
+    ref = {}
+    t0 = time.perf_counter()
+    for p in traj:
+        ref[p] = oracle.spectrum(segs[p], hw, thx, thy, oracle.KIND_SPINHALF)[4]
+        evals += segs[p]["t"].size * hw.size * thx.size * thy.size
+    dt = time.perf_counter() - t0
+    return ref, evals / dt, dt, threads, evals
+
+
+def rel_metrics(got, ref):
+    d = got - ref
+    m1 = float(np.linalg.norm(d) / np.linalg.norm(ref))
+    rows = np.sqrt(np.sum(ref ** 2, axis=(-2, -1)))
+    m2 = float(np.max(np.sqrt(np.sum(d ** 2, axis=(-2, -1)))[rows > 0] / rows[rows > 0]))
+    return m1, m2
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU sharding is a "
+              "design note only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1910_10391_amd import rad
+
+    t_gen = time.perf_counter()
+    cfg, segs, g = build_workload(args.particles)
+    t_gen = time.perf_counter() - t_gen
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    ds = rad.DeviceSegments(segs, device=dev)
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    n_w, n_y, n_x = grid.shape
+    n_samples = int(sum(ds.n))
+    evals = n_samples * n_w * n_x * n_y
+    idx = list(range(len(segs)))
+    kinds = rad.SPINHALF
+    ws = torch.empty(rad.batch_workspace_bytes(grid, ds, len(segs), kinds, rad.FP64),
+                     dtype=torch.uint8, device=dev)
+    out = torch.empty((len(segs), 1) + grid.shape, dtype=torch.float64, device=dev)
+    print("bench: %d trajectories, %d samples, grid %s, %.3e evals/step, workspace %.2f GB, "
+          "inputs generated in %.1f s" % (len(segs), n_samples, grid.shape, evals, ws.numel() / 1e9,
+                                          t_gen), file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)    # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step(prec, o):
+        rad.batch(grid, ds, idx, len(segs), kinds, precision=prec, out=o, workspace=ws)
+
+    # ---- FP64, the headline
+    for _ in range(args.warmup):
+        step(rad.FP64, out)
+    torch.cuda.synchronize()
+    rad.profile_enable(True)
+    rad.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rad.FP64, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kern_ms, launches = rad.profile_read(reset=True)
+    rad.profile_enable(False)
+    print("bench: fp64 %.3f s/step, amplitude kernel %.3f ms/launch over %d launches" %
+          (dt, kern_ms / max(launches, 1), launches), file=sys.stderr, flush=True)
+    kern_s = kern_ms / 1e3 / max(launches, 1)
+    value = evals / dt
+
+    # ---- mixed precision on the same workload
+    mixed = None
+    out_mx = None
+    if not args.no_mixed:
+        out_mx = torch.empty_like(out)
+        step(rad.MIXED, out_mx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_mx = max(1, min(args.steps, 2))
+        for _ in range(n_mx):
+            step(rad.MIXED, out_mx)
+        torch.cuda.synchronize()
+        dt_mx = (time.perf_counter() - t0) / n_mx
+        mixed = {"value": evals / dt_mx, "unit": "evals/s", "ms_per_step": dt_mx * 1e3,
+                 "speedup_vs_fp64": dt / dt_mx}
+        print("bench: mixed %.3f s/step (x%.2f)" % (dt_mx, dt / dt_mx), file=sys.stderr, flush=True)
+
+    # ---- CPU oracle on the bounded sample, and parity of both forms there
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        traj, iw, ix, iy = sample_points(segs, g)
+        ref, rate, cpu_dt, threads, cevals = cpu_baseline(segs, g, traj, iw, ix, iy)
+        cpu = {"value": rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": "%d trajectories (2 shortest, 2 longest) x every 8th of %d photon "
+                         "energies x 8x8 strided directions, spin-1/2, %.3e evals in %.1f s; "
+                         "host %s, nproc %d" % (len(traj), n_w, cevals, cpu_dt, cpu_model(),
+                                                os.cpu_count() or 0),
+               "trajectories_per_s_extrapolated": rate / (evals / len(segs))}
+        got = out[:, 0].cpu().numpy()
+        sel = np.ix_(iw, iy, ix)
+        m64 = [rel_metrics(got[p][sel], ref[p]) for p in traj]
+        parity = {"fp64_M1_max": max(m[0] for m in m64), "fp64_M2_max": max(m[1] for m in m64),
+                  "sample_trajectories": traj}
+        if out_mx is not None:
+            gm = out_mx[:, 0].cpu().numpy()
+            mmx = [rel_metrics(gm[p][sel], ref[p]) for p in traj]
+            parity["mixed_M1_max"] = max(m[0] for m in mmx)
+            parity["mixed_M2_max"] = max(m[1] for m in mmx)
+            mixed["rel_err_M1"] = parity["mixed_M1_max"]
+            mixed["rel_err_M2"] = parity["mixed_M2_max"]
+
+    flops = FLOPS_PER_EVAL["spinhalf"] * evals
+    achieved = flops / kern_s / 1e12
+    traffic = None
+    if (kernel_sources_sha() == MEASURED_TRAFFIC["sources_sha256"]
+            and len(segs) == MEASURED_TRAFFIC["particles"]):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": "amp_kernel<4,4,J,fp64>", "kernel_ms": kern_s * 1e3,
+                "valu_issue_frac": VALU_PER_EVAL["spinhalf"] * evals / kern_s / 1e12 / VALU_PEAK_TOPS}
+    res = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "positron_spinhalf: %d e+ at 10 GeV, planar harmonic+quartic well "
+                               "(20 eV, 1.92 A), 100 um, MS + radiative loss, %d..%d samples; "
+                               "spin-1/2, 512 log hw 0.5-200 MeV x 32x32 within 5/gamma"
+                               % (len(segs), min(ds.n), max(ds.n)),
+                   "trajectories": len(segs), "samples": n_samples, "grid": list(grid.shape),
+                   "kinds": "spin-1/2", "precision": "fp64"},
+        "trajectories_per_s": len(segs) / dt,
+        "mixed": mixed,
+        "parity": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
