@@ -32,19 +32,29 @@ METRIC = ("(t·ω·n) integrand evals/s and trajectories/s; "
 # MI355X: 256 CUs x 64 FP64 lanes x 2 flops (FMA) x 2.4 GHz
 FP64_PEAK_TFLOPS = 78.6
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # VALU lane-instructions per second, 1e12
-# FP64 flops per (t, w, n) eval of the amplitude kernel as built (4x4 direction
-# tile, 8 phase factors per time step; FMA = 2): phase factors 8 x 36 / 16,
-# complex product 6, accumulation 2 per complex component.
-FLOPS_PER_EVAL = {"spinhalf": 36.0, "classical": 32.0}
-# VALU instructions per eval in the compiled hot loop (365 per 16 evals with J,
-# 332 without), counted from the gfx950 assembly of this build.
-VALU_PER_EVAL = {"spinhalf": 365.0 / 16.0, "classical": 332.0 / 16.0}
+# Amplitude-kernel variants: direction tile (TX, TY) per lane and resident blocks per CU.
+VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2)}
+
+
+def flops_per_eval(variant, with_j=True):
+    """FP64 flops per (t, w, n) eval of the amplitude kernel (FMA = 2): a lane makes
+    TX + TY phase factors per time step for TX*TY directions, 36 flops each (phase
+    product, exact reduction, f^2, two 9-term polynomials, f * poly); then per eval
+    a complex product (6) and 2 flops per real accumulator (A_x, A_y and J: 12)."""
+    tx, ty, _ = VARIANTS[variant]
+    return 36.0 * (tx + ty) / (tx * ty) + 6.0 + (12.0 if with_j else 8.0)
+
+
+# VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
+# FP64 kernel (365 per 16 evals with J, 332 without), counted in the gfx950
+# assembly of this build.
+VALU_PER_EVAL_44 = {True: 365.0 / 16.0, False: 332.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "a5538fbd0ded16d9", "particles": 256, "bytes_per_launch": 2.119e10}
+MEASURED_TRAFFIC = {"sources_sha256": "8dd2645e53f05520", "particles": 256, "bytes_per_launch": 2.087e10}
 
 
 def kernel_sources_sha():
@@ -61,7 +71,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--particles", type=int, default=256)
+    p.add_argument("--particles", type=int, default=0, help="0: the workload's own count")
+    p.add_argument("--workload", default="positron_spinhalf",
+                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed"])
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
@@ -70,12 +82,137 @@ def parse():
 
 
 def build_workload(n_particles):
+    """The positron spin-1/2 workload: one segment per trajectory."""
     from paper_1910_10391_amd.synth import channeling, presets
     cfg = presets.positron_config()
     trs = channeling.generate(cfg, n_particles, threads=min(16, os.cpu_count() or 1))
     segs = [tr[0] for tr in trs]
     grid = presets.positron_grid()
     return cfg, segs, grid
+
+
+def build_sections_workload(n_particles):
+    """50 GeV electrons, 1 mm in 10 sections: segments, their trajectory index, grid."""
+    from paper_1910_10391_amd.synth import channeling, presets
+    cfg = presets.electron_50gev_config()
+    trs = channeling.generate(cfg, n_particles, threads=min(16, os.cpu_count() or 1))
+    segs, idx = [], []
+    for p, secs in enumerate(trs):
+        for sec in secs:
+            segs.append(sec)
+            idx.append(p)
+    return segs, idx, presets.electron_50gev_grid()
+
+
+def build_pm_workload(n_each):
+    """n_each positrons + n_each electrons at 10 GeV, one segment each."""
+    from paper_1910_10391_amd.synth import channeling, presets
+    cp, ce = presets.pm_configs()
+    th = min(16, os.cpu_count() or 1)
+    segs = [tr[0] for tr in channeling.generate(cp, n_each, threads=th)]
+    segs += [tr[0] for tr in channeling.generate(ce, n_each, threads=th)]
+    return segs, presets.pm_grid()
+
+
+def timed(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_sections(args):
+    """50 GeV sections workload: the persistent, autotuned, graph-replayed mixed-precision
+    launch against the plain FP64 launch on the same GPU."""
+    import torch
+    from paper_1910_10391_amd import autotune, rad
+    n = args.particles or 512
+    segs, idx, g = build_sections_workload(n)
+    ds = rad.DeviceSegments(segs)
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    evals = int(sum(ds.n)) * int(np.prod(grid.shape))
+    kinds = rad.SPINHALF
+    print("bench: %d trajectories, %d sections, %.3e evals/step" % (n, len(segs), evals),
+          file=sys.stderr, flush=True)
+    tune_p = autotune.tune(grid, ds, kinds, rad.MIXED, persistent=True, sample=16)
+    side = torch.cuda.Stream()
+    out = torch.empty((n, 1) + grid.shape, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(side):
+        plan = rad.Plan(grid, ds, idx, n, kinds, precision=rad.MIXED, stream=side)
+        for _ in range(args.warmup):
+            plan.launch_graph(out, stream=side)
+        dt_mx = timed(lambda: plan.launch_graph(out, stream=side), args.steps, side.synchronize)
+    print("bench: mixed persistent graph %.3f s/step" % dt_mx, file=sys.stderr, flush=True)
+    ws = torch.empty(rad.batch_workspace_bytes(grid, ds, n, kinds, rad.FP64), dtype=torch.uint8,
+                     device="cuda")
+    out64 = torch.empty_like(out)
+    step64 = lambda: rad.batch(grid, ds, idx, n, kinds, rad.FP64, out=out64, workspace=ws)  # noqa
+    step64()
+    dt_64 = timed(step64, max(1, min(args.steps, 2)), torch.cuda.synchronize)
+    print("bench: plain fp64 %.3f s/step" % dt_64, file=sys.stderr, flush=True)
+    a, b = out[:, 0].cpu().numpy(), out64[:, 0].cpu().numpy()
+    m1 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {
+        "metric": METRIC, "value": evals / dt_mx, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt_mx * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "electron_50gev_sections: %d e- at 50 GeV, 1 mm in 10 sections, "
+                               "%d..%d samples per section; spin-1/2, 256 log hw 1 MeV-20 GeV x "
+                               "16x16 within 4/gamma; mixed precision, persistent plan replayed "
+                               "from a hipGraph, autotuned" % (n, min(ds.n), max(ds.n)),
+                   "segments": len(segs), "grid": list(grid.shape),
+                   "autotune": {k: v["variant"] for k, v in tune_p.items()}},
+        "trajectories_per_s": n / dt_mx,
+        "fp64_plain": {"value": evals / dt_64, "ms_per_step": dt_64 * 1e3},
+        "speedup_vs_fp64_plain": dt_64 / dt_mx,
+        "mixed_vs_fp64_rel_err_M1": m1,
+    }
+
+
+def bench_pm(args):
+    """1024 e+ + 1024 e- at 10 GeV, classical + spin-0 + spin-1/2 (two integral sets), mixed
+    precision against FP64 on the same GPU."""
+    import torch
+    from paper_1910_10391_amd import rad
+    n_each = (args.particles or 2048) // 2
+    segs, g = build_pm_workload(n_each)
+    ds = rad.DeviceSegments(segs)
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    evals = 2 * int(sum(ds.n)) * int(np.prod(grid.shape))     # two integral sets (k and k*)
+    idx = list(range(len(segs)))
+    out = torch.empty((len(segs), 3) + grid.shape, dtype=torch.float64, device="cuda")
+    out64 = torch.empty_like(out)
+    ws = torch.empty(rad.batch_workspace_bytes(grid, ds, len(segs), 7, rad.FP64), dtype=torch.uint8,
+                     device="cuda")
+    print("bench: %d trajectories, %.3e evals/step" % (len(segs), evals), file=sys.stderr, flush=True)
+    stepm = lambda: rad.batch(grid, ds, idx, len(segs), 7, rad.MIXED, out=out, workspace=ws)  # noqa
+    step64 = lambda: rad.batch(grid, ds, idx, len(segs), 7, rad.FP64, out=out64, workspace=ws)  # noqa
+    for _ in range(args.warmup):
+        stepm()
+    dt_mx = timed(stepm, args.steps, torch.cuda.synchronize)
+    step64()
+    dt_64 = timed(step64, 1, torch.cuda.synchronize)
+    a, b = out.cpu().numpy(), out64.cpu().numpy()
+    errs = {k: float(np.linalg.norm(a[:, i] - b[:, i]) / np.linalg.norm(b[:, i]))
+            for i, k in enumerate(("classical", "spin0", "spinhalf"))}
+    return {
+        "metric": METRIC, "value": evals / dt_mx, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt_mx * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "pm_mixed: %d e+ + %d e- at 10 GeV, 100 um, %d..%d samples; "
+                               "classical + spin-0 + spin-1/2, 256 log hw 0.5-200 MeV x 16x16 "
+                               "within 5/gamma; mixed precision" % (n_each, n_each, min(ds.n),
+                                                                   max(ds.n)),
+                   "grid": list(grid.shape)},
+        "trajectories_per_s": len(segs) / dt_mx,
+        "fp64": {"value": evals / dt_64, "ms_per_step": dt_64 * 1e3},
+        "speedup_vs_fp64": dt_64 / dt_mx,
+        "mixed_vs_fp64_rel_err_M1": errs,
+    }
 
 
 def sample_points(segs, grid):
@@ -129,10 +266,14 @@ def main():
               "design note only", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1910_10391_amd import rad
+    from paper_1910_10391_amd import autotune, rad
 
+    if args.workload != "positron_spinhalf":
+        fn = bench_sections if args.workload == "electron_50gev_sections" else bench_pm
+        print(json.dumps(fn(args)), flush=True)
+        return
     t_gen = time.perf_counter()
-    cfg, segs, g = build_workload(args.particles)
+    cfg, segs, g = build_workload(args.particles or 256)
     t_gen = time.perf_counter() - t_gen
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -149,6 +290,10 @@ def main():
     print("bench: %d trajectories, %d samples, grid %s, %.3e evals/step, workspace %.2f GB, "
           "inputs generated in %.1f s" % (len(segs), n_samples, grid.shape, evals, ws.numel() / 1e9,
                                           t_gen), file=sys.stderr, flush=True)
+
+    tuned = autotune.tune(grid, ds, kinds, rad.FP64, persistent=False, sample=8)
+    print("bench: autotuned variants %s" % {k: v["variant"] for k, v in tuned.items()},
+          file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)    # 1 GiB
@@ -221,16 +366,19 @@ def main():
             mixed["rel_err_M1"] = parity["mixed_M1_max"]
             mixed["rel_err_M2"] = parity["mixed_M2_max"]
 
-    flops = FLOPS_PER_EVAL["spinhalf"] * evals
+    variant = rad.tune_get_variant(False, False, True)
+    flops = flops_per_eval(variant, True) * evals
     achieved = flops / kern_s / 1e12
     traffic = None
-    if (kernel_sources_sha() == MEASURED_TRAFFIC["sources_sha256"]
+    if (kernel_sources_sha() == MEASURED_TRAFFIC["sources_sha256"] and variant == 0
             and len(segs) == MEASURED_TRAFFIC["particles"]):
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": "amp_kernel<4,4,J,fp64>", "kernel_ms": kern_s * 1e3,
-                "valu_issue_frac": VALU_PER_EVAL["spinhalf"] * evals / kern_s / 1e12 / VALU_PEAK_TOPS}
+                "kernel": "amp_kernel<%d,%d,J,fp64,%d>" % VARIANTS[variant], "kernel_ms": kern_s * 1e3,
+                "flops_per_eval": flops_per_eval(variant, True),
+                "valu_issue_frac": (VALU_PER_EVAL_44[True] * evals / kern_s / 1e12 / VALU_PEAK_TOPS
+                                    if variant == 0 else None)}
     res = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -240,7 +388,8 @@ def main():
                                "spin-1/2, 512 log hw 0.5-200 MeV x 32x32 within 5/gamma"
                                % (len(segs), min(ds.n), max(ds.n)),
                    "trajectories": len(segs), "samples": n_samples, "grid": list(grid.shape),
-                   "kinds": "spin-1/2", "precision": "fp64"},
+                   "kinds": "spin-1/2", "precision": "fp64",
+                   "autotune": {k: v["variant"] for k, v in tuned.items()}},
         "trajectories_per_s": len(segs) / dt,
         "mixed": mixed,
         "parity": parity,

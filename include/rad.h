@@ -151,6 +151,30 @@ rad_status rad_batch(const rad_grid *grid, const rad_segment *segs, int n_segs,
                      void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Persistent, replayable batches.  A plan fixes one rad_batch call's segments,
+ * outputs, kinds, precision and workspace: rad_plan_create validates, orders the
+ * work longest segment first and writes the work list into `ws` (synchronising
+ * `stream` once).  rad_plan_launch then issues only kernels -- a ticket reset, a
+ * persistent amplitude kernel per integral set whose resident blocks pull work
+ * items from the list, and the finalize kernel -- with no host copy and no
+ * allocation.  rad_plan_launch_graph captures that sequence into a hipGraph on
+ * its first call for a given `out` and replays the graph afterwards; it needs a
+ * created (non-default) stream.  The plan keeps pointers to the grid, the
+ * segment columns and `ws`: they must stay valid and unchanged while the plan
+ * is used.  Calls on one plan must not overlap in time (they share the work
+ * list's tickets).  Results equal rad_batch's to rounding; repeated launches of
+ * one plan, eager or from the graph, are bitwise identical.
+ * ws_bytes >= rad_batch_workspace_bytes(grid, segs, n_segs, n_out, kinds, prec).
+ */
+typedef struct rad_plan rad_plan;
+rad_status rad_plan_create(const rad_grid *grid, const rad_segment *segs, int n_segs,
+                           const int *out_index, int n_out, int kinds, rad_precision prec,
+                           void *ws, size_t ws_bytes, void *stream, rad_plan **plan);
+rad_status rad_plan_launch(rad_plan *plan, double *out, void *stream);
+rad_status rad_plan_launch_graph(rad_plan *plan, double *out, void *stream);
+void rad_plan_free(rad_plan *plan);
+
+/*
  * Angle integral (Sec. IV): dIdw[c][i] = sum_{jy,jx} cube[c][i][jy][jx] dthx[jx] dthy[jy]
  * for n_cubes consecutive DEVICE cubes; dIdw is DEVICE [n_cubes][n_w].
  */
@@ -164,14 +188,17 @@ const char *rad_status_string(rad_status status);
 const char *rad_last_error(void);
 
 /*
- * Tuning knobs of the amplitude kernel (process-wide).  A variant fixes the
- * direction tile each lane owns and the resident blocks per CU it is compiled
- * for; `with_j` selects the integral set that also carries J (spin-1/2).
- * Every variant computes the same sums; only the speed differs.
+ * Tuning knobs of the amplitude kernel (process-wide), set by the autotuner.  A
+ * variant fixes the direction tile each lane owns (4x4, 4x3, 4x2) and the
+ * resident blocks per CU it is compiled for.  It is chosen per form
+ * (`persistent`: rad_plan_* vs the one-block-per-item calls), per precision
+ * (`mixed`) and per integral set (`with_j`: the set that also carries J for
+ * spin-1/2).  Every variant computes the same sums; only the speed differs.
+ * A plan keeps the variants in force when it was created.
  * rad_tune_set_variant: RAD_EINVAL for an unknown variant.
  */
-rad_status rad_tune_set_variant(int with_j, int variant);
-rad_status rad_tune_get_variant(int with_j, int *variant);
+rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant);
+rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *variant);
 int rad_tune_num_variants(void);
 
 /*

@@ -57,6 +57,7 @@ struct AmpLaunch {
     int quantum;           // 0: kappa = k; 1: kappa = k E/(E - hw)
     int comps;             // 2 (A_x, A_y) or 3 (A_x, A_y, J)
     double2 *part;         // partial amplitudes [seg][chunk][comp][n][w]
+    unsigned *counter;     // ticket of the persistent form (zeroed before the launch)
 };
 
 // Finalize: per output, the segments that feed it, in segment order.

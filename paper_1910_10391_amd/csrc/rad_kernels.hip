@@ -55,27 +55,39 @@ __device__ __forceinline__ void lane_cis(double kh, double part, double &c, doub
     }
 }
 
-template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
-__global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
+// LDS of one work item: the staged integrand and phase parts of kSlots
+// (time step, direction tile) pairs.
+template <int TX, int TY, bool WITHJ>
+struct AmpSmem {
+    double2 fxy[kSlots * TX * TY];
+    double fq[WITHJ ? kSlots * TX * TY : 1];
+    double px[kSlots * TX];
+    double py[kSlots * TY];
+    int seg;
+};
+
+// One work item b = (segment, time chunk, direction-tile group, photon-energy
+// block) of an amplitude launch, computed by the whole block.
+template <int TX, int TY, bool WITHJ, bool MIXED>
+__device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ> &sm)
 {
     constexpr int NP = TX * TY;
-    __shared__ double2 s_fxy[kSlots * NP];
-    __shared__ double s_fq[WITHJ ? kSlots * NP : 1];
-    __shared__ double s_px[kSlots * TX];
-    __shared__ double s_py[kSlots * TY];
-    __shared__ int s_seg;
+    double2 *const s_fxy = sm.fxy;
+    double *const s_fq = sm.fq;
+    double *const s_px = sm.px;
+    double *const s_py = sm.py;
 
-    // segment of this block: last s with block_begin <= blockIdx.x
-    const int64_t b = blockIdx.x;
+    // segment of this item: last s with block_begin <= b
     if (threadIdx.x == 0) {
         int lo = 0, hi = L.n_segs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (L.segs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
         }
-        s_seg = lo;
+        sm.seg = lo;
     }
     __syncthreads();
+    const int s_seg = sm.seg;
     const SegDesc &S = L.segs[s_seg];
     const int64_t n = S.n;
     const double c0 = S.c0;
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
     }
 
     // ---- partial amplitudes of this chunk: part[seg][chunk][comp][n][w]
-    if (iw >= L.n_w || gtile >= n_tiles) return;
+    if (iw >= L.n_w || gtile >= n_tiles) return;   // no barrier follows in this item
     const int64_t n_n = (int64_t)L.n_x * L.n_y;
     const int64_t base = S.part_off + (int64_t)chunk * L.comps * n_n * L.n_w;
     const int tx0 = (gtile % L.n_tx) * TX, ty0 = (gtile / L.n_tx) * TY;
@@ -234,6 +246,40 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
         L.part[base + (1 * n_n + nn) * L.n_w + iw] = make_double2(ayr[p], ayi[p]);
         if constexpr (WITHJ) L.part[base + (2 * n_n + nn) * L.n_w + iw] = make_double2(jr[p], ji[p]);
     }
+}
+
+// One block per work item.
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+__global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
+{
+    __shared__ AmpSmem<TX, TY, WITHJ> sm;
+    amp_item<TX, TY, WITHJ, MIXED>(L, blockIdx.x, sm);
+}
+
+// Persistent form: a fixed grid of resident blocks pulls work items in launch
+// order (longest segment first) from an atomic ticket until the list is
+// exhausted; every block leaves the loop once a ticket is past the end.  The
+// ticket only schedules: every item writes its own partial slot, so results do
+// not depend on which block ran it.
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+__global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
+{
+    __shared__ AmpSmem<TX, TY, WITHJ> sm;
+    __shared__ int64_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(L.counter, 1u);
+        __syncthreads();
+        const int64_t b = s_item;
+        __syncthreads();   // all lanes hold b before thread 0 may take the next ticket
+        if (b >= L.n_blocks) break;
+        amp_item<TX, TY, WITHJ, MIXED>(L, b, sm);
+    }
+}
+
+// Tickets start at zero for every launch (a kernel, so graphs hold no memset node).
+__global__ void reset_counters_kernel(unsigned *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
 __device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
@@ -329,30 +375,50 @@ __global__ __launch_bounds__(256) void angle_kernel(const double *__restrict__ c
 }
 
 // ---------------------------------------------------------------- launchers
+// grid_blocks > 0: persistent launch with that many blocks; 0: one block per item.
+// occupancy != nullptr: only report resident blocks per CU of the persistent kernel.
 template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
-static hipError_t launch_amp_t(const AmpLaunch &L, hipStream_t st)
+static hipError_t launch_amp_t(const AmpLaunch &L, int grid_blocks, hipStream_t st, int *occupancy)
 {
-    hipLaunchKernelGGL((amp_kernel<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)L.n_blocks),
-                       dim3(kBlock), 0, st, L);
+    if (occupancy)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occupancy, reinterpret_cast<const void *>(amp_persistent<TX, TY, WITHJ, MIXED, MINB>), kBlock, 0);
+    if (grid_blocks > 0)
+        hipLaunchKernelGGL((amp_persistent<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)grid_blocks),
+                           dim3(kBlock), 0, st, L);
+    else
+        hipLaunchKernelGGL((amp_kernel<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)L.n_blocks),
+                           dim3(kBlock), 0, st, L);
     return hipGetLastError();
 }
 
 template <bool WITHJ, bool MIXED>
-static hipError_t launch_amp_v(const AmpLaunch &L, int variant, hipStream_t st)
+static hipError_t launch_amp_v(const AmpLaunch &L, int variant, int grid_blocks, hipStream_t st,
+                               int *occupancy)
 {
     switch (variant) {
-    case kVar44x2: return launch_amp_t<4, 4, WITHJ, MIXED, 2>(L, st);
-    case kVar43x2: return launch_amp_t<4, 3, WITHJ, MIXED, 2>(L, st);
-    case kVar44x1: return launch_amp_t<4, 4, WITHJ, MIXED, 1>(L, st);
-    case kVar42x2: return launch_amp_t<4, 2, WITHJ, MIXED, 2>(L, st);
+    case kVar44x2: return launch_amp_t<4, 4, WITHJ, MIXED, 2>(L, grid_blocks, st, occupancy);
+    case kVar43x2: return launch_amp_t<4, 3, WITHJ, MIXED, 2>(L, grid_blocks, st, occupancy);
+    case kVar44x1: return launch_amp_t<4, 4, WITHJ, MIXED, 1>(L, grid_blocks, st, occupancy);
+    case kVar42x2: return launch_amp_t<4, 2, WITHJ, MIXED, 2>(L, grid_blocks, st, occupancy);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, hipStream_t st)
+hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, int grid_blocks,
+                      hipStream_t st, int *occupancy)
 {
-    if (withj) return mixed ? launch_amp_v<true, true>(L, variant, st) : launch_amp_v<true, false>(L, variant, st);
-    return mixed ? launch_amp_v<false, true>(L, variant, st) : launch_amp_v<false, false>(L, variant, st);
+    if (withj)
+        return mixed ? launch_amp_v<true, true>(L, variant, grid_blocks, st, occupancy)
+                     : launch_amp_v<true, false>(L, variant, grid_blocks, st, occupancy);
+    return mixed ? launch_amp_v<false, true>(L, variant, grid_blocks, st, occupancy)
+                 : launch_amp_v<false, false>(L, variant, grid_blocks, st, occupancy);
+}
+
+hipError_t launch_reset(unsigned *counters, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, counters, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_fin(const FinLaunch &F, hipStream_t st)

@@ -23,13 +23,17 @@
 #include "rad_internal.h"
 
 namespace rad {
-hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, hipStream_t st);
+hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, int grid_blocks,
+                      hipStream_t st, int *occupancy);
+hipError_t launch_reset(unsigned *counters, int n, hipStream_t st);
 hipError_t launch_fin(const FinLaunch &F, hipStream_t st);
 hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
                         int n_w, int n_cubes, double *out, hipStream_t st);
 }  // namespace rad
 
 using namespace rad;
+
+struct rad_plan;
 
 struct rad_grid {
     int n_w = 0, n_x = 0, n_y = 0;
@@ -92,14 +96,17 @@ rad_status check_dev_range(const void *p, size_t bytes, const char *name)
     return RAD_OK;
 }
 
-// Kernel variant per integral set: [0] without J, [1] with J.
+// Kernel variant per [persistent][mixed][with J].  Defaults are the measured
+// best on MI355X; the persistent FP64 form with J spills in its hot loop at 4x4,
+// so it defaults to 4x3.
 std::mutex g_var_mu;
-int g_variant[2] = {kVar44x2, kVar44x2};
+int g_variant[2][2][2] = {{{kVar44x2, kVar44x2}, {kVar44x2, kVar44x2}},
+                          {{kVar44x2, kVar43x2}, {kVar44x2, kVar44x2}}};
 
-int variant_for(bool withj)
+int variant_for(bool persistent, bool mixed, bool withj)
 {
     std::lock_guard<std::mutex> lk(g_var_mu);
-    return g_variant[withj ? 1 : 0];
+    return g_variant[persistent ? 1 : 0][mixed ? 1 : 0][withj ? 1 : 0];
 }
 
 struct Tile {
@@ -148,7 +155,8 @@ void plan_chunks(int64_t n, int64_t c, int32_t &n_chunks, int32_t &chunk_len)
 int popcount3(int k) { return (k & 1) + ((k >> 1) & 1) + ((k >> 2) & 1); }
 
 struct Layout {
-    size_t off_amp_c, off_amp_q, off_id_c, off_id_q, off_begin, off_list, off_part_c, off_part_q;
+    size_t off_counters, off_amp_c, off_amp_q, off_id_c, off_id_q, off_begin, off_list, off_part_c,
+        off_part_q;
     size_t desc_bytes;  // bytes of the descriptor region (uploaded)
     size_t total;
     int comps_q;
@@ -159,6 +167,7 @@ Layout layout(const rad_grid *g, int n_segs, int n_out, int kinds, int64_t sum_c
     Layout L{};
     const size_t sd = sizeof(SegDesc) * (size_t)n_segs;
     size_t o = 0;
+    L.off_counters = o; o = align_up(o + 2 * sizeof(unsigned));
     L.off_amp_c = o; o = align_up(o + sd);
     L.off_amp_q = o; o = align_up(o + sd);
     L.off_id_c = o; o = align_up(o + sd);
@@ -209,10 +218,24 @@ rad_status check_segment(const rad_segment *s, int idx, bool quantum)
     return RAD_OK;
 }
 
-// Shared driver of rad_classical, rad_quantum and rad_batch.
-rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index, int n_out,
-               int kinds, rad_precision prec, double *out, void *ws, size_t ws_bytes,
-               hipStream_t st)
+// A planned call: everything the kernels need, decided on the host.
+struct Plan {
+    rad_grid *g = nullptr;
+    int n_segs = 0, n_out = 0, kinds = 0, n_kinds = 0;
+    bool mixed = false, quantum = false, withj = false;
+    Layout lay{};
+    Tile tile_c{}, tile_q{};
+    int64_t blocks_c = 0, blocks_q = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<char> host;      // descriptor region, uploaded to ws[0, lay.desc_bytes)
+    bool persistent = false;
+    int pgrid_c = 0, pgrid_q = 0;  // persistent grid sizes
+};
+
+rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index,
+                      int n_out, int kinds, rad_precision prec, void *ws, size_t ws_bytes,
+                      bool persistent, Plan &P)
 {
     rad_status rs = check_grid(g);
     if (rs != RAD_OK) return rs;
@@ -228,44 +251,46 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
         rs = check_segment(&segs[s], s, quantum);
         if (rs != RAD_OK) return rs;
     }
-    const bool withj = (kinds & RAD_SPINHALF) != 0;
-    const Tile tile_c = plan_tile(g, variant_for(false));
-    const Tile tile_q = plan_tile(g, variant_for(withj));
-    const Tile &tile = (kinds & RAD_CLASSICAL) ? tile_c : tile_q;   // sets the chunking
-    const int64_t cf = chunk_factor(tile, n_segs);
+    P.g = g;
+    P.n_segs = n_segs;
+    P.n_out = n_out;
+    P.kinds = kinds;
+    P.n_kinds = popcount3(kinds);
+    P.mixed = prec == RAD_MIXED;
+    P.quantum = quantum;
+    P.withj = (kinds & RAD_SPINHALF) != 0;
+    P.tile_c = plan_tile(g, variant_for(persistent, P.mixed, false));
+    P.tile_q = plan_tile(g, variant_for(persistent, P.mixed, P.withj));
+    const int64_t cf = chunk_factor(plan_tile(g, kVar44x2), n_segs);   // variant-independent chunking
     std::vector<int32_t> nch(n_segs), clen(n_segs);
     int64_t sum_chunks = 0;
     for (int s = 0; s < n_segs; ++s) {
         plan_chunks(segs[s].n, cf, nch[s], clen[s]);
         sum_chunks += nch[s];
     }
-    const Layout lay = layout(g, n_segs, n_out, kinds, sum_chunks);
+    P.lay = layout(g, n_segs, n_out, kinds, sum_chunks);
     if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
-    if (ws_bytes < lay.total)
-        return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, lay.total);
-    const int n_kinds = popcount3(kinds);
+    if (ws_bytes < P.lay.total)
+        return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, P.lay.total);
+    rs = check_dev_range(ws, P.lay.total, "workspace");
+    if (rs != RAD_OK) return rs;
+    P.ws = (char *)ws;
+    P.ws_bytes = ws_bytes;
     const size_t cube = (size_t)g->n_w * g->n_x * g->n_y;
-    rs = check_dev_range(ws, lay.total, "workspace");
-    if (rs != RAD_OK) return rs;
-    rs = check_dev_range(out, (size_t)n_out * n_kinds * cube * sizeof(double), "out");
-    if (rs != RAD_OK) return rs;
 
-    // launch order: longest segment first (the dispatcher hands out blocks in order)
+    // launch order: longest segment first (dispatch order, and the persistent queue's order)
     std::vector<int> order(n_segs);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return segs[a].n > segs[b].n; });
 
-    char *wsb = (char *)ws;
-    double2 *part_c = (double2 *)(wsb + lay.off_part_c);
-    double2 *part_q = (double2 *)(wsb + lay.off_part_q);
-    std::vector<char> host(lay.desc_bytes, 0);
-    SegDesc *amp_c = (SegDesc *)(host.data() + lay.off_amp_c);
-    SegDesc *amp_q = (SegDesc *)(host.data() + lay.off_amp_q);
-    SegDesc *id_c = (SegDesc *)(host.data() + lay.off_id_c);
-    SegDesc *id_q = (SegDesc *)(host.data() + lay.off_id_q);
-    int *begin = (int *)(host.data() + lay.off_begin);
-    int *list = (int *)(host.data() + lay.off_list);
+    P.host.assign(P.lay.desc_bytes, 0);
+    SegDesc *amp_c = (SegDesc *)(P.host.data() + P.lay.off_amp_c);
+    SegDesc *amp_q = (SegDesc *)(P.host.data() + P.lay.off_amp_q);
+    SegDesc *id_c = (SegDesc *)(P.host.data() + P.lay.off_id_c);
+    SegDesc *id_q = (SegDesc *)(P.host.data() + P.lay.off_id_q);
+    int *begin = (int *)(P.host.data() + P.lay.off_begin);
+    int *list = (int *)(P.host.data() + P.lay.off_list);
 
     std::vector<int64_t> part_off_c(n_segs), part_off_q(n_segs);
     {
@@ -274,7 +299,7 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
             part_off_c[s] = oc;
             part_off_q[s] = oq;
             oc += (int64_t)nch[s] * 2 * (int64_t)cube;
-            oq += (int64_t)nch[s] * lay.comps_q * (int64_t)cube;
+            oq += (int64_t)nch[s] * P.lay.comps_q * (int64_t)cube;
         }
     }
     int64_t blocks_c = 0, blocks_q = 0;
@@ -294,8 +319,8 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
         SegDesc dc = d, dq = d;
         dc.block_begin = blocks_c;
         dq.block_begin = blocks_q;
-        blocks_c += (int64_t)nch[s] * tile_c.base_blocks;
-        blocks_q += (int64_t)nch[s] * tile_q.base_blocks;
+        blocks_c += (int64_t)nch[s] * P.tile_c.base_blocks;
+        blocks_q += (int64_t)nch[s] * P.tile_q.base_blocks;
         dc.part_off = part_off_c[s];
         dq.part_off = part_off_q[s];
         amp_c[r] = dc;
@@ -305,6 +330,8 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
     }
     if (std::max(blocks_c, blocks_q) >= ((int64_t)1 << 31) - 1)
         return fail(RAD_EUNSUPPORTED, "launch of %lld blocks", (long long)std::max(blocks_c, blocks_q));
+    P.blocks_c = blocks_c;
+    P.blocks_q = blocks_q;
     // outputs -> segments in segment order
     {
         std::vector<int> cnt(n_out + 1, 0);
@@ -314,37 +341,81 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
         std::vector<int> fill(cnt.begin(), cnt.end() - 1);
         for (int s = 0; s < n_segs; ++s) list[fill[out_index[s]]++] = s;
     }
-
-    // upload descriptors through the grid's pinned staging buffer
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (g->stage_pending) {
-            hipError_t e = hipEventSynchronize(g->stage_done);
-            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-            g->stage_pending = false;
+    P.persistent = persistent;
+    if (persistent) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return fail(RAD_EDEVICE, "cannot query the compute-unit count");
+        auto grid_for = [&](const Tile &t, bool wj, int64_t items, int &gb) -> rad_status {
+            int occ = 0;
+            hipError_t e = launch_amp(AmpLaunch{}, t.variant, wj, P.mixed, 0, nullptr, &occ);
+            if (e != hipSuccess || occ <= 0) return hip_fail(e, "occupancy query");
+            gb = (int)std::min<int64_t>(items, (int64_t)occ * cus);
+            return RAD_OK;
+        };
+        if (kinds & RAD_CLASSICAL) {
+            rs = grid_for(P.tile_c, false, blocks_c, P.pgrid_c);
+            if (rs != RAD_OK) return rs;
         }
-        if (g->stage_bytes < lay.desc_bytes) {
-            if (g->stage) (void)hipHostFree(g->stage);
-            g->stage = nullptr;
-            g->stage_bytes = 0;
-            hipError_t e = hipHostMalloc(&g->stage, lay.desc_bytes, hipHostMallocDefault);
-            if (e != hipSuccess) return fail(RAD_ENOMEM, "pinned staging of %zu bytes", lay.desc_bytes);
-            g->stage_bytes = lay.desc_bytes;
+        if (quantum) {
+            rs = grid_for(P.tile_q, P.lay.comps_q == 3, blocks_q, P.pgrid_q);
+            if (rs != RAD_OK) return rs;
         }
-        if (!g->stage_done) {
-            hipError_t e = hipEventCreateWithFlags(&g->stage_done, hipEventDisableTiming);
-            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-        }
-        std::memcpy(g->stage, host.data(), lay.desc_bytes);
-        hipError_t e = hipMemcpyAsync(ws, g->stage, lay.desc_bytes, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-        e = hipEventRecord(g->stage_done, st);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        g->stage_pending = true;
     }
+    return RAD_OK;
+}
+
+// Upload the descriptor region through the grid's pinned staging buffer (async on st).
+rad_status plan_upload_async(Plan &P, hipStream_t st)
+{
+    rad_grid *g = P.g;
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->stage_pending) {
+        hipError_t e = hipEventSynchronize(g->stage_done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        g->stage_pending = false;
+    }
+    if (g->stage_bytes < P.lay.desc_bytes) {
+        if (g->stage) (void)hipHostFree(g->stage);
+        g->stage = nullptr;
+        g->stage_bytes = 0;
+        hipError_t e = hipHostMalloc(&g->stage, P.lay.desc_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(RAD_ENOMEM, "pinned staging of %zu bytes", P.lay.desc_bytes);
+        g->stage_bytes = P.lay.desc_bytes;
+    }
+    if (!g->stage_done) {
+        hipError_t e = hipEventCreateWithFlags(&g->stage_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    std::memcpy(g->stage, P.host.data(), P.lay.desc_bytes);
+    hipError_t e = hipMemcpyAsync(P.ws, g->stage, P.lay.desc_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipEventRecord(g->stage_done, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    g->stage_pending = true;
+    return RAD_OK;
+}
+
+// Kernels only: no host copy, no allocation (capturable).  `profile` brackets the
+// amplitude launches with events.
+rad_status check_out(const Plan &P, const double *out)
+{
+    const size_t cube = (size_t)P.g->n_w * P.g->n_x * P.g->n_y;
+    return check_dev_range(out, (size_t)P.n_out * P.n_kinds * cube * sizeof(double), "out");
+}
+
+// `out` must have passed check_out.
+rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
+{
+    const rad_grid *g = P.g;
+    char *wsb = P.ws;
+    double2 *part_c = (double2 *)(wsb + P.lay.off_part_c);
+    double2 *part_q = (double2 *)(wsb + P.lay.off_part_q);
+    unsigned *counters = (unsigned *)(wsb + P.lay.off_counters);
 
     AmpLaunch L{};
-    L.n_segs = n_segs;
+    L.n_segs = P.n_segs;
     L.hw = g->d_hw;
     L.k = g->d_k;
     L.thx = g->d_thx;
@@ -361,70 +432,92 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
         L.n_groups = t.n_groups;
         L.n_wblocks = t.n_wblocks;
     };
-
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool prof;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        prof = g_prof_on;
+    if (P.persistent) {
+        hipError_t e = launch_reset(counters, 2, st);
+        if (e != hipSuccess) return hip_fail(e, "counter reset launch");
     }
-    if (prof) {
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (profile) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return fail(RAD_EDEVICE, "hipEventCreate for profiling");
         (void)hipEventRecord(ev0, st);
     }
-    const bool mixed = prec == RAD_MIXED;
-    if (kinds & RAD_CLASSICAL) {
-        set_tile(tile_c, blocks_c);
-        L.segs = (const SegDesc *)(wsb + lay.off_amp_c);
+    if (P.kinds & RAD_CLASSICAL) {
+        set_tile(P.tile_c, P.blocks_c);
+        L.segs = (const SegDesc *)(wsb + P.lay.off_amp_c);
         L.quantum = 0;
         L.comps = 2;
         L.part = part_c;
-        hipError_t e = launch_amp(L, tile_c.variant, false, mixed, st);
+        L.counter = counters;
+        hipError_t e = launch_amp(L, P.tile_c.variant, false, P.mixed, P.persistent ? P.pgrid_c : 0, st, nullptr);
         if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
     }
-    if (quantum) {
-        set_tile(tile_q, blocks_q);
-        L.segs = (const SegDesc *)(wsb + lay.off_amp_q);
+    if (P.quantum) {
+        set_tile(P.tile_q, P.blocks_q);
+        L.segs = (const SegDesc *)(wsb + P.lay.off_amp_q);
         L.quantum = 1;
-        L.comps = lay.comps_q;
+        L.comps = P.lay.comps_q;
         L.part = part_q;
-        hipError_t e = launch_amp(L, tile_q.variant, lay.comps_q == 3, mixed, st);
+        L.counter = counters + 1;
+        hipError_t e = launch_amp(L, P.tile_q.variant, P.lay.comps_q == 3, P.mixed,
+                                  P.persistent ? P.pgrid_q : 0, st, nullptr);
         if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
     }
-    if (prof) {
+    if (profile) {
         (void)hipEventRecord(ev1, st);
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof_pending.emplace_back(ev0, ev1);
     }
 
     FinLaunch F{};
-    F.out_seg_begin = (const int *)(wsb + lay.off_begin);
-    F.out_seg_list = (const int *)(wsb + lay.off_list);
-    F.cls = (const SegDesc *)(wsb + lay.off_id_c);
-    F.qs = (const SegDesc *)(wsb + lay.off_id_q);
+    F.out_seg_begin = (const int *)(wsb + P.lay.off_begin);
+    F.out_seg_list = (const int *)(wsb + P.lay.off_list);
+    F.cls = (const SegDesc *)(wsb + P.lay.off_id_c);
+    F.qs = (const SegDesc *)(wsb + P.lay.off_id_q);
     F.part_c = part_c;
     F.part_q = part_q;
-    F.comps_q = lay.comps_q;
+    F.comps_q = P.lay.comps_q;
     F.hw = g->d_hw;
     F.thx = g->d_thx;
     F.thy = g->d_thy;
     F.n_w = g->n_w;
     F.n_x = g->n_x;
     F.n_y = g->n_y;
-    F.n_out = n_out;
-    F.kinds = kinds;
-    F.n_kinds = n_kinds;
+    F.n_out = P.n_out;
+    F.kinds = P.kinds;
+    F.n_kinds = P.n_kinds;
     F.out = out;
     hipError_t e = launch_fin(F, st);
     if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
     return RAD_OK;
 }
 
+bool profiling_on()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
+// Shared driver of rad_classical, rad_quantum and rad_batch.
+rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index, int n_out,
+               int kinds, rad_precision prec, double *out, void *ws, size_t ws_bytes,
+               hipStream_t st)
+{
+    Plan P;
+    rad_status rs = plan_build(g, segs, n_segs, out_index, n_out, kinds, prec, ws, ws_bytes, false, P);
+    if (rs != RAD_OK) return rs;
+    rs = check_out(P, out);
+    if (rs != RAD_OK) return rs;
+    rs = plan_upload_async(P, st);
+    if (rs != RAD_OK) return rs;
+    return plan_launch(P, out, st, profiling_on());
+}
+
+// The chunking (and so the size) must not depend on which form or variant runs:
+// it is planned with the 4x4 tile count whatever the variant.
 size_t workspace_for(const rad_grid *g, const std::vector<int64_t> &ns, int n_out, int kinds, bool bound)
 {
-    const bool withj = (kinds & RAD_SPINHALF) != 0;
-    const Tile tile = plan_tile(g, (kinds & RAD_CLASSICAL) ? variant_for(false) : variant_for(withj));
+    const Tile tile = plan_tile(g, kVar44x2);
     const int64_t cf = chunk_factor(tile, (int64_t)ns.size());
     int64_t sum = 0;
     for (int64_t n : ns) {
@@ -604,18 +697,114 @@ rad_status rad_angle_integrate(const rad_grid *g, const double *cube, int n_cube
     return RAD_OK;
 }
 
-rad_status rad_tune_set_variant(int with_j, int variant)
+struct rad_plan {
+    Plan P;
+    hipGraphExec_t gexec = nullptr;
+    double *g_out = nullptr;
+};
+
+rad_status rad_plan_create(const rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index,
+                           int n_out, int kinds, rad_precision prec, void *ws, size_t ws_bytes,
+                           void *stream, rad_plan **out)
 {
-    if (variant < 0 || variant >= kNumVariants) return fail(RAD_EINVAL, "variant %d unknown", variant);
-    std::lock_guard<std::mutex> lk(g_var_mu);
-    g_variant[with_j ? 1 : 0] = variant;
+    if (!out) return fail(RAD_EINVAL, "out is NULL");
+    *out = nullptr;
+    rad_plan *p = new rad_plan();
+    rad_status rs = plan_build(const_cast<rad_grid *>(g), segs, n_segs, out_index, n_out, kinds, prec,
+                               ws, ws_bytes, true, p->P);
+    if (rs != RAD_OK) {
+        delete p;
+        return rs;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(p->P.ws, p->P.host.data(), p->P.lay.desc_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "plan upload");
+    }
+    *out = p;
     return RAD_OK;
 }
 
-rad_status rad_tune_get_variant(int with_j, int *variant)
+rad_status rad_plan_launch(rad_plan *p, double *out, void *stream)
+{
+    if (!p) return fail(RAD_EINVAL, "plan is NULL");
+    rad_status rs = check_grid(p->P.g);
+    if (rs != RAD_OK) return rs;
+    rs = check_out(p->P, out);
+    if (rs != RAD_OK) return rs;
+    return plan_launch(p->P, out, (hipStream_t)stream, profiling_on());
+}
+
+rad_status rad_plan_launch_graph(rad_plan *p, double *out, void *stream)
+{
+    if (!p) return fail(RAD_EINVAL, "plan is NULL");
+    if (!stream) return fail(RAD_EINVAL, "graph capture needs a created stream, not the default stream");
+    rad_status rs = check_grid(p->P.g);
+    if (rs != RAD_OK) return rs;
+    rs = check_out(p->P, out);
+    if (rs != RAD_OK) return rs;
+    hipStream_t st = (hipStream_t)stream;
+    if (!p->gexec || p->g_out != out) {
+        if (p->gexec) {
+            (void)hipGraphExecDestroy(p->gexec);
+            p->gexec = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        rs = plan_launch(p->P, out, st, false);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(st, &graph);
+        if (rs != RAD_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rs;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            p->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->g_out = out;
+    }
+    const bool prof = profiling_on();
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return fail(RAD_EDEVICE, "hipEventCreate for profiling");
+        (void)hipEventRecord(ev0, st);
+    }
+    hipError_t e = hipGraphLaunch(p->gexec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (prof) {
+        (void)hipEventRecord(ev1, st);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_pending.emplace_back(ev0, ev1);
+    }
+    return RAD_OK;
+}
+
+void rad_plan_free(rad_plan *p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    delete p;
+}
+
+rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant)
+{
+    if (variant < 0 || variant >= kNumVariants) return fail(RAD_EINVAL, "variant %d unknown", variant);
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_variant[persistent ? 1 : 0][mixed ? 1 : 0][with_j ? 1 : 0] = variant;
+    return RAD_OK;
+}
+
+rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *variant)
 {
     if (!variant) return fail(RAD_EINVAL, "variant is NULL");
-    *variant = variant_for(with_j != 0);
+    *variant = variant_for(persistent != 0, mixed != 0, with_j != 0);
     return RAD_OK;
 }
 

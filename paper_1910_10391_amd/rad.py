@@ -58,8 +58,13 @@ def lib():
                 "rad_angle_integrate": (I, [P, P, I, P, P]),
                 "rad_status_string": (ctypes.c_char_p, [I]),
                 "rad_last_error": (ctypes.c_char_p, []),
-                "rad_tune_set_variant": (I, [I, I]),
-                "rad_tune_get_variant": (I, [I, ctypes.POINTER(I)]),
+                "rad_tune_set_variant": (I, [I, I, I, I]),
+                "rad_tune_get_variant": (I, [I, I, I, ctypes.POINTER(I)]),
+                "rad_plan_create": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, S, P,
+                                        ctypes.POINTER(P)]),
+                "rad_plan_launch": (I, [P, P, P]),
+                "rad_plan_launch_graph": (I, [P, P, P]),
+                "rad_plan_free": (None, [P]),
                 "rad_tune_num_variants": (I, []),
                 "rad_profile_enable": (I, [I]),
                 "rad_profile_read": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]),
@@ -261,14 +266,72 @@ def angle_integrate(grid, cubes, out=None, stream=None):
     return out
 
 
-def tune_set_variant(with_j, variant):
-    _check(lib().rad_tune_set_variant(int(bool(with_j)), int(variant)), "rad_tune_set_variant")
+def tune_set_variant(persistent, mixed, with_j, variant):
+    _check(lib().rad_tune_set_variant(int(bool(persistent)), int(bool(mixed)), int(bool(with_j)),
+                                      int(variant)), "rad_tune_set_variant")
 
 
-def tune_get_variant(with_j):
+def tune_get_variant(persistent, mixed, with_j):
     v = ctypes.c_int()
-    _check(lib().rad_tune_get_variant(int(bool(with_j)), ctypes.byref(v)), "rad_tune_get_variant")
+    _check(lib().rad_tune_get_variant(int(bool(persistent)), int(bool(mixed)), int(bool(with_j)),
+                                      ctypes.byref(v)), "rad_tune_get_variant")
     return v.value
+
+
+class Plan:
+    """A replayable batch (rad_plan_*): persistent kernels over a longest-first work list.
+
+    The plan keeps the device segments, the workspace and the grid alive.  ``launch``
+    issues kernels only; ``launch_graph`` captures them into a hipGraph on first use
+    (per output tensor) and replays it; it needs a created stream (not the default
+    stream), e.g. ``torch.cuda.Stream()``.
+    """
+
+    def __init__(self, grid, segs, out_index, n_out, kinds, precision=FP64, workspace=None,
+                 stream=None):
+        ds = _as_segments(segs)
+        if len(out_index) != len(ds):
+            raise ValueError("out_index must have one entry per segment")
+        self.grid, self.ds, self.n_out, self.kinds = grid, ds, int(n_out), int(kinds)
+        self.precision = int(precision)
+        self.shape = (self.n_out, n_kinds(kinds)) + grid.shape
+        idx = (ctypes.c_int * len(ds))(*[int(i) for i in out_index])
+        self.ws = _workspace(batch_workspace_bytes(grid, ds, n_out, kinds, precision), workspace,
+                             ds.data.device)
+        h = ctypes.c_void_p()
+        _check(lib().rad_plan_create(grid.handle, ds.structs, len(ds), idx, self.n_out, self.kinds,
+                                     self.precision, _dptr(self.ws), _nbytes(self.ws),
+                                     _stream(stream), ctypes.byref(h)), "rad_plan_create")
+        self.handle = h
+
+    def _out(self, out):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.ds.data.device)
+        _check_out(out, self.shape)
+        return out
+
+    def launch(self, out=None, stream=None):
+        out = self._out(out)
+        _check(lib().rad_plan_launch(self.handle, _dptr(out), _stream(stream)), "rad_plan_launch")
+        return out
+
+    def launch_graph(self, out=None, stream=None):
+        out = self._out(out)
+        _check(lib().rad_plan_launch_graph(self.handle, _dptr(out), _stream(stream)),
+               "rad_plan_launch_graph")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().rad_plan_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_num_variants():

@@ -59,5 +59,5 @@ def test_validation_before_device(lib):
     assert b"hw_eV" in lib.rad_last_error()
     assert lib.rad_workspace_bytes(None, 100, 1, 0) == 0
     assert lib.rad_batch_workspace_bytes(None, None, 0, 1, 1, 0) == 0
-    assert lib.rad_tune_set_variant(0, 99) == 1
+    assert lib.rad_tune_set_variant(0, 0, 0, 99) == 1
     assert lib.rad_tune_num_variants() >= 1

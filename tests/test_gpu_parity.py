@@ -155,17 +155,21 @@ def test_variants_agree(rad):
     th = analytic.cell_centred(9, 5.0 / seg["gamma"])
     grid = rad.Grid(hw, th, th)
     ref = oracle.spectrum(seg, hw, th, th, 7)
-    keep = (rad.tune_get_variant(False), rad.tune_get_variant(True))
+    keys = [(p, m, j) for p in (0, 1) for m in (0, 1) for j in (0, 1)]
+    keep = {k: rad.tune_get_variant(*k) for k in keys}
     try:
         for v in range(rad.tune_num_variants()):
-            rad.tune_set_variant(False, v)
-            rad.tune_set_variant(True, v)
+            for k in keys:
+                rad.tune_set_variant(*k, v)
             out = _cpu(rad.batch(grid, [seg], [0], 1, 7))[0]
+            plan = rad.Plan(grid, [seg], [0], 1, 7)
+            outp = _cpu(plan.launch())[0]
             for i, k in enumerate((1, 2, 4)):
                 assert_parity(out[i], ref[k], th, th, FP64_TOL, "variant %d kind %d" % (v, k))
+                assert_parity(outp[i], ref[k], th, th, FP64_TOL, "persistent variant %d kind %d" % (v, k))
     finally:
-        rad.tune_set_variant(False, keep[0])
-        rad.tune_set_variant(True, keep[1])
+        for k in keys:
+            rad.tune_set_variant(*k, keep[k])
 
 
 def test_bitwise_reproducible(rad):
