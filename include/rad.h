@@ -181,6 +181,27 @@ void rad_plan_free(rad_plan *plan);
 rad_status rad_angle_integrate(const rad_grid *grid, const double *cube, int n_cubes, double *dIdw,
                                void *stream);
 
+/*
+ * Exact cell integrals for the learned angular sampler's refinement.  The
+ * directions of `grid` are split into cells of cx x cy (8 x 8 supported; n_x, n_y
+ * must be multiples): cell c = (ci, cj) covers thx[ci*cx .. ci*cx+cx-1] x
+ * thy[cj*cy .. cj*cy+cy-1], cells numbered c = cj * (n_x/cx) + ci.  For every
+ * segment s, photon energy w and cell c with mask[s][w][c] != 0 (HOST uint8
+ * [n_segs][n_w][n_cells]) it writes
+ *   cell_out[s][w][c] = sum over the cell's directions of the `kind` spectrum
+ *                       (exactly one of RAD_CLASSICAL, RAD_SPIN0, RAD_SPINHALF)
+ *                       times dthx dthy (the grid's angle-cell widths),
+ * and 0 where the mask is 0 (cell_out: DEVICE [n_segs][n_w][n_cells]).  Only the
+ * masked cells are computed (per block of 64 photon energies); segments are
+ * single sections (no summing across segments).  ws_bytes >=
+ * rad_cells_workspace_bytes(...) for the same mask.  Errors as rad_batch.
+ */
+size_t rad_cells_workspace_bytes(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                                 rad_precision prec, int cx, int cy, const uint8_t *mask);
+rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                     rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
+                     void *ws, size_t ws_bytes, void *stream);
+
 /* Static text of a status code. */
 const char *rad_status_string(rad_status status);
 

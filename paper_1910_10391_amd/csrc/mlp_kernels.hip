@@ -1,0 +1,358 @@
+// BF16 MLP kernels of the learned angular sampler (gfx950).
+//
+// Network: in = [trajectory features (nf), point inputs (np)] -> 256 -> 256 -> 256 -> 1,
+// SiLU activations, BF16 weights and activations, FP32 accumulation, Adam on FP32
+// master weights.  The dense layers are matrix products on the MFMA units
+// (v_mfma_f32_32x32x16_bf16); the 3-input point layer of inference, the output
+// layer, the loss, the reductions and Adam are vector kernels.
+//
+// Layouts: activations [point][feature] row-major; weights [out][in] row-major;
+// a transposed copy [in][out] of the 256 x 256 weights serves the backward
+// data products.  BF16 values are stored as uint16 (round to nearest even).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mlp_internal.h"
+
+namespace radmlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                       // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoidf_(z); }
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = sigmoidf_(z);
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------- GEMM
+// C[m][n] = sum_k A[m][k] B[n][k]; A, B BF16 with K contiguous (lda, ldb in
+// elements, multiples of 8, 16-byte aligned rows); M, N multiples of 64; the K
+// range of blockIdx.z is [z kslice, (z+1) kslice), a multiple of 16.
+// Block = 4 waves in a 2 x 2 arrangement of 32 x 32 MFMA tiles.
+// MFMA operand layout (32x32x16 bf16): lane l holds A[l % 32][8 (l / 32) + j] and
+// B[l % 32][8 (l / 32) + j], j = 0..7; result register i of lane l is
+// C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int kb = blockIdx.z * g.kslice;
+    const int ke = min(g.K, kb + g.kslice);
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    const uint16_t *Ap = g.A + (size_t)(m0 + r) * g.lda + kh;
+    const uint16_t *Bp = g.B + (size_t)(n0 + r) * g.ldb + kh;
+    floatx16 acc = {};
+    for (int k = kb; k < ke; k += 16) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ap + k);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Bp + k);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+    const int col = n0 + r;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int row = m0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const size_t o = (size_t)row * g.N + col;
+        const float v = acc[i];
+        if constexpr (EPI == kEpiFwd) {            // z = acc + b; h = silu(z)
+            const float z = v + g.bias[col];
+            if (g.out_z) g.out_z[o] = z;
+            g.out_h[(size_t)row * g.ldh + col] = f2bf(silu(z));
+        } else if constexpr (EPI == kEpiBwd) {     // dz = acc * silu'(z_prev)
+            const float dz = v * dsilu(g.zin[o]);
+            g.out_z[o] = dz;
+            g.out_h[(size_t)row * g.ldh + col] = f2bf(dz);
+        } else {                                   // split-K partial
+            g.out_z[(size_t)blockIdx.z * g.M * g.N + o] = v;
+        }
+    }
+}
+
+// out[n][m] = in[m][n] (BF16), 32 x 32 tiles through LDS; M, N multiples of 32.
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t *__restrict__ in, int M, int N,
+                                                             uint16_t *__restrict__ out)
+{
+    __shared__ uint16_t t[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx over N, by over M
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int j = ty; j < 32; j += 8) t[j][tx] = in[(size_t)(by + j) * N + bx + tx];
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) out[(size_t)(bx + j) * M + by + tx] = t[tx][j];
+}
+
+// ---------------------------------------------------------------- reductions
+// Stage 1: part[s][n] = sum over rows m in slice s of w[m] X[m][n] (w null -> 1),
+// X FP32 (xf) or BF16 (xb); rows in order.  Stage 2: out[n] = sum_s part[s][n].
+__global__ __launch_bounds__(256) void colsum_stage1(const float *__restrict__ xf, const uint16_t *__restrict__ xb,
+                                                     const float *__restrict__ w, int M, int N, int rows_per,
+                                                     float *__restrict__ part)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (n >= N) return;
+    const int m0 = s * rows_per, m1 = min(M, m0 + rows_per);
+    float acc = 0.0f;
+    for (int m = m0; m < m1; ++m) {
+        const float v = xf ? xf[(size_t)m * N + n] : bf2f(xb[(size_t)m * N + n]);
+        acc += w ? w[m] * v : v;
+    }
+    part[(size_t)s * N + n] = acc;
+}
+
+__global__ __launch_bounds__(256) void sum_slices(const float *__restrict__ part, int slices, int64_t len,
+                                                  float *__restrict__ out, int64_t out_stride, int n_cols,
+                                                  int src_cols)
+{
+    // out row r, column c (c < n_cols) = sum_s part[s][r * src_cols + c]
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rows = len / src_cols;
+    if (i >= rows * n_cols) return;
+    const int64_t r = i / n_cols, c = i % n_cols;
+    float acc = 0.0f;
+    for (int s = 0; s < slices; ++s) acc += part[(size_t)s * len + r * src_cols + c];
+    out[r * out_stride + c] = acc;
+}
+
+// ---------------------------------------------------------------- input / output layers
+// in1[m][c] = bf16(feat[traj[m]][c]) for c < nf, bf16(x[m][c - nf]) for c < nf + np, else 0.
+__global__ __launch_bounds__(256) void assemble_in1(const float *__restrict__ feat, int nf, const int *__restrict__ traj,
+                                                    const float *__restrict__ x, int np, int B, int Bp,
+                                                    uint16_t *__restrict__ in1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)Bp * kIn1) return;
+    const int m = (int)(i / kIn1), c = (int)(i % kIn1);
+    float v = 0.0f;
+    if (m < B) {
+        if (c < nf) v = feat[(size_t)traj[m] * nf + c];
+        else if (c < nf + np) v = x[(size_t)m * np + (c - nf)];
+    }
+    in1[i] = f2bf(v);
+}
+
+// Inference, trajectory part of layer 1 folded into a bias:
+// cb[t][o] = b1[o] + sum_{f < nf} W1[o][f] bf16(feat[t][f]).
+__global__ __launch_bounds__(256) void fold_bias(const uint16_t *__restrict__ W1p, const float *__restrict__ b1,
+                                                 const float *__restrict__ feat, int nf, int n_traj,
+                                                 float *__restrict__ cb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_traj * kWidth) return;
+    const int t = i / kWidth, o = i % kWidth;
+    float acc = 0.0f;
+    for (int f = 0; f < nf; ++f) acc += bf2f(W1p[o * kIn1 + f]) * bf2f(f2bf(feat[(size_t)t * nf + f]));
+    cb[i] = acc + b1[o];
+}
+
+// Inference layer 1 on the point inputs: h1[m][o] = silu(cb[traj[m]][o] + sum_j W1[o][nf+j] bf16(x[m][j])).
+__global__ __launch_bounds__(256) void layer1_points(const uint16_t *__restrict__ W1p, const float *__restrict__ cb,
+                                                     int nf, const int *__restrict__ traj,
+                                                     const float *__restrict__ x, int np, int B, int Bp,
+                                                     uint16_t *__restrict__ h1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)Bp * kWidth) return;
+    const int m = (int)(i / kWidth), o = (int)(i % kWidth);
+    float z = 0.0f;
+    if (m < B) {
+        z = cb[(size_t)traj[m] * kWidth + o];
+        for (int j = 0; j < np; ++j) z += bf2f(W1p[o * kIn1 + nf + j]) * bf2f(f2bf(x[(size_t)m * np + j]));
+    }
+    h1[i] = f2bf(silu(z));
+}
+
+// Output layer: y[m] = b4 + sum_i W4[i] h3[m][i], one wave per point.  Training
+// (target != null): also dy[m] = 2 (y - t)/B, loss part, and the start of the
+// backward pass dz3[m][i] = dy W4[i] silu'(z3[m][i]) (FP32 and BF16).
+// Rows B..Bp-1 are padding: every output there is zero.
+__global__ __launch_bounds__(256) void output_layer(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ W4b,
+                                                    const float *__restrict__ b4, int B, int Bp,
+                                                    const float *__restrict__ target, const float *__restrict__ z3,
+                                                    float *__restrict__ y, float *__restrict__ dy,
+                                                    float *__restrict__ sqerr, float *__restrict__ dz3,
+                                                    uint16_t *__restrict__ dz3b)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + wave;
+    if (m >= Bp) return;
+    if (m >= B) {
+        if (lane == 0) {
+            y[m] = 0.0f;
+            if (target) {
+                dy[m] = 0.0f;
+                sqerr[m] = 0.0f;
+            }
+        }
+        if (target)
+            for (int i = lane; i < kWidth; i += 64) {
+                dz3[(size_t)m * kWidth + i] = 0.0f;
+                dz3b[(size_t)m * kWidth + i] = 0;
+            }
+        return;
+    }
+    float acc = 0.0f;
+    for (int i = lane; i < kWidth; i += 64) acc += bf2f(W4b[i]) * bf2f(h3[(size_t)m * kWidth + i]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const float ym = acc + b4[0];
+    if (lane == 0) y[m] = ym;
+    if (!target) return;
+    const float d = ym - target[m];
+    const float g = 2.0f * d / (float)B;
+    if (lane == 0) {
+        dy[m] = g;
+        sqerr[m] = d * d;
+    }
+    for (int i = lane; i < kWidth; i += 64) {
+        const size_t o = (size_t)m * kWidth + i;
+        const float v = g * bf2f(W4b[i]) * dsilu(z3[o]);
+        dz3[o] = v;
+        dz3b[o] = f2bf(v);
+    }
+}
+
+// ---------------------------------------------------------------- Adam and working copies
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, float *__restrict__ m1,
+                                                   float *__restrict__ m2, const float *__restrict__ g, int64_t n,
+                                                   float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = v;
+    p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// BF16 working copies of the FP32 masters: W1 padded to kIn1 columns, W2, W3 and
+// their transposes, W4.
+__global__ __launch_bounds__(256) void refresh_bf16(const float *__restrict__ p, MlpLayout L,
+                                                    uint16_t *__restrict__ W1p, uint16_t *__restrict__ W2,
+                                                    uint16_t *__restrict__ W2T, uint16_t *__restrict__ W3,
+                                                    uint16_t *__restrict__ W3T, uint16_t *__restrict__ W4)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sq = (int64_t)kWidth * kWidth;
+    if (i < (int64_t)kWidth * kIn1) {
+        const int o = (int)(i / kIn1), c = (int)(i % kIn1);
+        W1p[i] = c < L.n_in ? f2bf(p[L.w1 + (int64_t)o * L.n_in + c]) : (uint16_t)0;
+    }
+    if (i < sq) {
+        const int o = (int)(i / kWidth), c = (int)(i % kWidth);
+        W2[i] = f2bf(p[L.w2 + i]);
+        W3[i] = f2bf(p[L.w3 + i]);
+        W2T[(int64_t)c * kWidth + o] = f2bf(p[L.w2 + i]);
+        W3T[(int64_t)c * kWidth + o] = f2bf(p[L.w3 + i]);
+    }
+    if (i < kWidth) W4[i] = f2bf(p[L.w4 + i]);
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t st)
+{
+    const dim3 grid((unsigned)(g.M / 64), (unsigned)(g.N / 64), (unsigned)splits);
+    switch (epi) {
+    case kEpiFwd: hipLaunchKernelGGL(gemm_nt_kernel<kEpiFwd>, grid, dim3(256), 0, st, g); break;
+    case kEpiBwd: hipLaunchKernelGGL(gemm_nt_kernel<kEpiBwd>, grid, dim3(256), 0, st, g); break;
+    default: hipLaunchKernelGGL(gemm_nt_kernel<kEpiPartial>, grid, dim3(256), 0, st, g); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const uint16_t *in, int M, int N, uint16_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3((unsigned)(N / 32), (unsigned)(M / 32)), dim3(256), 0, st,
+                       in, M, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *xf, const uint16_t *xb, const float *w, int M, int N, float *part,
+                         int slices, float *out, hipStream_t st)
+{
+    const int rows_per = (M + slices - 1) / slices;
+    hipLaunchKernelGGL(colsum_stage1, dim3((unsigned)((N + 255) / 256), (unsigned)slices), dim3(256), 0, st,
+                       xf, xb, w, M, N, rows_per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_slices, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, slices,
+                       (int64_t)N, out, (int64_t)N, N, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_slices(const float *part, int slices, int rows, int src_cols, int n_cols, float *out,
+                             int64_t out_stride, hipStream_t st)
+{
+    const int64_t items = (int64_t)rows * n_cols;
+    hipLaunchKernelGGL(sum_slices, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, part, slices,
+                       (int64_t)rows * src_cols, out, out_stride, n_cols, src_cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_in1(const float *feat, int nf, const int *traj, const float *x, int np, int B, int Bp,
+                               uint16_t *in1, hipStream_t st)
+{
+    const int64_t n = (int64_t)Bp * kIn1;
+    hipLaunchKernelGGL(assemble_in1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, feat, nf, traj, x, np,
+                       B, Bp, in1);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_bias(const uint16_t *W1p, const float *b1, const float *feat, int nf, int n_traj, float *cb,
+                            hipStream_t st)
+{
+    const int n = n_traj * kWidth;
+    hipLaunchKernelGGL(fold_bias, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W1p, b1, feat, nf, n_traj, cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer1_points(const uint16_t *W1p, const float *cb, int nf, const int *traj, const float *x, int np,
+                                int B, int Bp, uint16_t *h1, hipStream_t st)
+{
+    const int64_t n = (int64_t)Bp * kWidth;
+    hipLaunchKernelGGL(layer1_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W1p, cb, nf, traj, x, np,
+                       B, Bp, h1);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
+                         const float *target, const float *z3, float *y, float *dy, float *sqerr, float *dz3,
+                         uint16_t *dz3b, hipStream_t st)
+{
+    hipLaunchKernelGGL(output_layer, dim3((unsigned)((Bp + 3) / 4)), dim3(256), 0, st, h3, W4b, b4, B, Bp, target,
+                       z3, y, dy, sqerr, dz3, dz3b);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, m1, m2, g, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uint16_t *W2, uint16_t *W2T,
+                          uint16_t *W3, uint16_t *W3T, uint16_t *W4, hipStream_t st)
+{
+    const int64_t n = (int64_t)kWidth * kWidth;
+    hipLaunchKernelGGL(refresh_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, L, W1p, W2, W2T, W3,
+                       W3T, W4);
+    return hipGetLastError();
+}
+
+}  // namespace radmlp

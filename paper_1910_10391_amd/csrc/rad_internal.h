@@ -25,7 +25,9 @@ constexpr int kVarTY[kNumVariants] = {4, 3, 4, 2};
 
 enum Column { C_T = 0, C_X, C_Y, C_DZ, C_VX, C_VY, C_DVZ, C_AX, C_AY, C_AZ, C_NCOL };
 
-// One segment as the kernels see it.
+// One segment as the kernels see it: a trajectory piece and the (hw, direction)
+// grid it is integrated on (all segments of a rad_batch call share one grid; the
+// cell refinement gives each (trajectory, cell) its own view of the fine grid).
 struct SegDesc {
     const double *col[C_NCOL];
     const double *w;       // nullable -> trapezoid
@@ -37,23 +39,25 @@ struct SegDesc {
     int32_t n_chunks;
     int32_t chunk_len;
     int64_t block_begin;   // first block of this segment in the amplitude launch
+    const double *hw;      // [n_w] eV
+    const double *k;       // [n_w] 1/m
+    const double *thx;     // [n_x]
+    const double *thy;     // [n_y]
+    int32_t n_w, n_x, n_y;
+    int32_t n_tx, n_ty;    // direction tiles along x, y
+    int32_t n_groups;      // ceil(n_tx * n_ty / nt)
+    int32_t n_wblocks;     // ceil(n_w / (64 wg))
+    int32_t pad_;
 };
 
 // One amplitude launch: one "set" (classical kappa = k, or quantum kappa = k*).
 struct AmpLaunch {
     const SegDesc *segs;   // in launch (longest-first) order
+    const int4 *items;     // explicit work items (segment, chunk, group, w block) or null
     int n_segs;
-    int64_t n_blocks;
-    const double *hw;      // [n_w] eV
-    const double *k;       // [n_w] 1/m
-    const double *thx;     // [n_x]
-    const double *thy;     // [n_y]
-    int n_w, n_x, n_y;
-    int n_tx, n_ty;        // direction tiles along x, y
+    int64_t n_blocks;      // work items
     int wg;                // waves per block spread over photon energies (1, 2, 4)
     int nt;                // direction tiles per block (4 / wg)
-    int n_groups;          // ceil(n_tx * n_ty / nt)
-    int n_wblocks;         // ceil(n_w / (64 wg))
     int quantum;           // 0: kappa = k; 1: kappa = k E/(E - hw)
     int comps;             // 2 (A_x, A_y) or 3 (A_x, A_y, J)
     double2 *part;         // partial amplitudes [seg][chunk][comp][n][w]
@@ -75,6 +79,21 @@ struct FinLaunch {
     int kinds;
     int n_kinds;
     double *out;                // [n_out][n_kinds][n_w][n_y][n_x]
+};
+
+// Cell integrals of the refinement: for each (segment, photon energy, cell) with
+// its mask set, the spectrum summed over the cell's directions times their
+// solid-angle weights.
+struct CellsFin {
+    const SegDesc *segs;        // active (segment, cell) pseudo-segments
+    const int *psof;            // [n_segs][n_cells] -> pseudo-segment or -1
+    const uint8_t *mask;        // [n_segs][n_w][n_cells]
+    const double2 *part;
+    int comps, kind;
+    const double *wx, *wy;      // direction cell widths of the fine grid
+    const double *hw;
+    int n_segs, n_w, n_x, ncx, n_cells, cx, cy;
+    double *out;                // [n_segs][n_w][n_cells]
 };
 
 }  // namespace rad

@@ -77,17 +77,26 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     double *const s_px = sm.px;
     double *const s_py = sm.py;
 
-    // segment of this item: last s with block_begin <= b
+    // segment and coordinates of this item: from the explicit list, or the
+    // last segment s with block_begin <= b
+    int chunk = 0, grp = 0, wb = 0;
     if (threadIdx.x == 0) {
-        int lo = 0, hi = L.n_segs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.segs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+        int lo;
+        if (L.items) {
+            lo = L.items[b].x;
+        } else {
+            lo = 0;
+            int hi = L.n_segs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.segs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+            }
         }
         sm.seg = lo;
     }
     __syncthreads();
-    const int s_seg = sm.seg;
+    // wave-uniform: descriptor fields then live in SGPRs (scalar loads), not VGPRs
+    const int s_seg = __builtin_amdgcn_readfirstlane(sm.seg);
     const SegDesc &S = L.segs[s_seg];
     const int64_t n = S.n;
     const double c0 = S.c0;
@@ -103,30 +112,42 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     const double *__restrict__ cay = S.col[C_AY];
     const double *__restrict__ caz = S.col[C_AZ];
     const double *__restrict__ cw = S.w;
+    const double *__restrict__ g_hw = S.hw;
+    const double *__restrict__ g_k = S.k;
+    const double *__restrict__ g_thx = S.thx;
+    const double *__restrict__ g_thy = S.thy;
+    const int n_w = S.n_w, n_x = S.n_x, n_y = S.n_y, n_tx = S.n_tx;
 
-    int64_t local = b - S.block_begin;
-    const int wb = (int)(local % L.n_wblocks);
-    local /= L.n_wblocks;
-    const int grp = (int)(local % L.n_groups);
-    const int chunk = (int)(local / L.n_groups);
+    if (L.items) {
+        const int4 it = L.items[b];
+        chunk = __builtin_amdgcn_readfirstlane(it.y);
+        grp = __builtin_amdgcn_readfirstlane(it.z);
+        wb = __builtin_amdgcn_readfirstlane(it.w);
+    } else {
+        int64_t local = b - S.block_begin;
+        wb = (int)(local % S.n_wblocks);
+        local /= S.n_wblocks;
+        grp = (int)(local % S.n_groups);
+        chunk = (int)(local / S.n_groups);
+    }
     const int64_t k_begin = (int64_t)chunk * S.chunk_len;
     const int64_t k_end = min(n, k_begin + (int64_t)S.chunk_len);
 
     const int nt = L.nt, wg = L.wg;
     const int T = kSlots / nt;
-    const int n_tiles = L.n_tx * L.n_ty;
+    const int n_tiles = n_tx * S.n_ty;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int tl = wave / wg;
     const int iw = (wb * wg + wave % wg) * kWave + lane;
     const int gtile = grp * nt + tl;
 
     double kappa = 0.0;
-    if (iw < L.n_w) {
-        const double k = L.k[iw];
+    if (iw < n_w) {
+        const double k = g_k[iw];
         if (!L.quantum) {
             kappa = k;
         } else {
-            const double hw = L.hw[iw];
+            const double hw = g_hw[iw];
             kappa = hw < energy ? k * energy / (energy - hw) : 0.0;
         }
     }
@@ -147,11 +168,11 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             const int tloc = slot / nt, tile = slot % nt;
             const int64_t k = k0 + tloc;
             const int gt = grp * nt + tile;
-            const int jx = (gt % L.n_tx) * TX + p % TX;
-            const int jy = (gt / L.n_tx) * TY + p / TX;
+            const int jx = (gt % n_tx) * TX + p % TX;
+            const int jy = (gt / n_tx) * TY + p / TX;
             double fx = 0.0, fy = 0.0, fq = 0.0;
-            if (k < k_end && gt < n_tiles && jx < L.n_x && jy < L.n_y) {
-                const double thx = L.thx[jx], thy = L.thy[jy];
+            if (k < k_end && gt < n_tiles && jx < n_x && jy < n_y) {
+                const double thx = g_thx[jx], thy = g_thy[jy];
                 const double vx = cvx[k], vy = cvy[k], dvz = cdvz[k];
                 const double ax = cax[k], ay = cay[k], az = caz[k];
                 const double w = cw ? cw[k]
@@ -189,12 +210,12 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             if (k < k_end && gt < n_tiles) {
                 const double t = ct[k];
                 if (j < TX) {
-                    const int jx = (gt % L.n_tx) * TX + j;
-                    const double thx = jx < L.n_x ? L.thx[jx] : 0.0;
+                    const int jx = (gt % n_tx) * TX + j;
+                    const double thx = jx < n_x ? g_thx[jx] : 0.0;
                     v = (c0 * t - cdz[k]) + thx * (0.5 * thx * t - cx[k]);
                 } else {
-                    const int jy = (gt / L.n_tx) * TY + (j - TX);
-                    const double thy = jy < L.n_y ? L.thy[jy] : 0.0;
+                    const int jy = (gt / n_tx) * TY + (j - TX);
+                    const double thy = jy < n_y ? g_thy[jy] : 0.0;
                     v = thy * (0.5 * thy * t - cy[k]);
                 }
             }
@@ -210,6 +231,10 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
 #pragma unroll
             for (int jy = 0; jy < TY; ++jy) {
+                // with J at 16 directions per lane the kernel sits at the VGPR limit: keep
+                // each row's LDS reads next to their use (hoisting all TX*TY integrand
+                // loads of a time step costs 4 VGPRs each and spills the accumulators)
+                if constexpr (WITHJ && TX * TY >= 16) __builtin_amdgcn_sched_barrier(0);
                 double yr, yi;
                 lane_cis<MIXED>(kh, s_py[slot * TY + jy], yr, yi);
 #pragma unroll
@@ -233,18 +258,18 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     }
 
     // ---- partial amplitudes of this chunk: part[seg][chunk][comp][n][w]
-    if (iw >= L.n_w || gtile >= n_tiles) return;   // no barrier follows in this item
-    const int64_t n_n = (int64_t)L.n_x * L.n_y;
-    const int64_t base = S.part_off + (int64_t)chunk * L.comps * n_n * L.n_w;
-    const int tx0 = (gtile % L.n_tx) * TX, ty0 = (gtile / L.n_tx) * TY;
+    if (iw >= n_w || gtile >= n_tiles) return;   // no barrier follows in this item
+    const int64_t n_n = (int64_t)n_x * n_y;
+    const int64_t base = S.part_off + (int64_t)chunk * L.comps * n_n * n_w;
+    const int tx0 = (gtile % n_tx) * TX, ty0 = (gtile / n_tx) * TY;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int jx = tx0 + p % TX, jy = ty0 + p / TX;
-        if (jx >= L.n_x || jy >= L.n_y) continue;
-        const int64_t nn = (int64_t)jy * L.n_x + jx;
-        L.part[base + (0 * n_n + nn) * L.n_w + iw] = make_double2(axr[p], axi[p]);
-        L.part[base + (1 * n_n + nn) * L.n_w + iw] = make_double2(ayr[p], ayi[p]);
-        if constexpr (WITHJ) L.part[base + (2 * n_n + nn) * L.n_w + iw] = make_double2(jr[p], ji[p]);
+        if (jx >= n_x || jy >= n_y) continue;
+        const int64_t nn = (int64_t)jy * n_x + jx;
+        L.part[base + (0 * n_n + nn) * n_w + iw] = make_double2(axr[p], axi[p]);
+        L.part[base + (1 * n_n + nn) * n_w + iw] = make_double2(ayr[p], ayi[p]);
+        if constexpr (WITHJ) L.part[base + (2 * n_n + nn) * n_w + iw] = make_double2(jr[p], ji[p]);
     }
 }
 
@@ -265,11 +290,11 @@ template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
 {
     __shared__ AmpSmem<TX, TY, WITHJ> sm;
-    __shared__ int64_t s_item;
+    __shared__ int s_item;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(L.counter, 1u);
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(L.counter, 1u);
         __syncthreads();
-        const int64_t b = s_item;
+        const int64_t b = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();   // all lanes hold b before thread 0 may take the next ticket
         if (b >= L.n_blocks) break;
         amp_item<TX, TY, WITHJ, MIXED>(L, b, sm);
@@ -349,6 +374,64 @@ __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
     if (F.kinds & 4) out[(kk++) * cube + dst] = sh;
 }
 
+// Cell integrals of the refinement.  Thread per (segment, cell, photon energy),
+// photon energy fastest (contiguous partial reads).  Directions and chunks are
+// summed in a fixed order.
+__global__ __launch_bounds__(256) void cells_fin_kernel(CellsFin F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)F.n_segs * F.n_cells * F.n_w;
+    if (i >= total) return;
+    const int w = (int)(i % F.n_w);
+    const int c = (int)((i / F.n_w) % F.n_cells);
+    const int s = (int)(i / ((int64_t)F.n_w * F.n_cells));
+    const int64_t dst = ((int64_t)s * F.n_w + w) * F.n_cells + c;
+    const int p = F.psof[(int64_t)s * F.n_cells + c];
+    if (p < 0 || !F.mask[dst]) {
+        F.out[dst] = 0.0;
+        return;
+    }
+    const SegDesc &d = F.segs[p];
+    const double hw = F.hw[w], E = d.energy;
+    if (F.kind != 1 && !(hw < E)) {
+        F.out[dst] = 0.0;
+        return;
+    }
+    const int ci = c % F.ncx, cj = c / F.ncx;
+    const int n_dir = F.cx * F.cy;
+    const int64_t stride = (int64_t)F.comps * n_dir * F.n_w;
+    const double pref = kAlpha / (4.0 * kPi * kPi);
+    double acc = 0.0;
+    for (int nn = 0; nn < n_dir; ++nn) {
+        const int jx = nn % F.cx, jy = nn / F.cx;
+        const double thx = d.thx[jx], thy = d.thy[jy];
+        double re[3] = {0.0, 0.0, 0.0}, im[3] = {0.0, 0.0, 0.0};
+        for (int comp = 0; comp < F.comps; ++comp) {
+            const double2 *q = F.part + d.part_off + ((int64_t)comp * n_dir + nn) * F.n_w + w;
+            for (int ch = 0; ch < d.n_chunks; ++ch) {
+                const double2 v = q[(int64_t)ch * stride];
+                re[comp] += v.x;
+                im[comp] += v.y;
+            }
+        }
+        const double zr = -(thx * re[0] + thy * re[1]), zi = -(thx * im[0] + thy * im[1]);
+        const double S = re[0] * re[0] + im[0] * im[0] + re[1] * re[1] + im[1] * im[1] + zr * zr + zi * zi;
+        double spec;
+        if (F.kind == 1) {
+            spec = pref * S;
+        } else {
+            const double Es = E - hw;
+            if (F.kind == 2)
+                spec = pref * (Es / E) * S;
+            else
+                spec = pref * ((Es * Es + E * E) / (2.0 * E * E) * S +
+                               hw * hw / (2.0 * E * E * d.gamma * d.gamma) * (re[2] * re[2] + im[2] * im[2]));
+        }
+        acc += spec * F.wx[ci * F.cx + jx] * F.wy[cj * F.cy + jy];
+    }
+    F.out[dst] = acc;
+}
+
 // dIdw[c][i] = sum_{jy, jx} cube[c][i][jy][jx] wx[jx] wy[jy]; one block per (i, c),
 // a fixed strided partial sum per thread and a fixed tree: deterministic.
 __global__ __launch_bounds__(256) void angle_kernel(const double *__restrict__ cube,
@@ -413,6 +496,13 @@ hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, i
                      : launch_amp_v<true, false>(L, variant, grid_blocks, st, occupancy);
     return mixed ? launch_amp_v<false, true>(L, variant, grid_blocks, st, occupancy)
                  : launch_amp_v<false, false>(L, variant, grid_blocks, st, occupancy);
+}
+
+hipError_t launch_cells_fin(const CellsFin &F, hipStream_t st)
+{
+    const int64_t total = (int64_t)F.n_segs * F.n_cells * F.n_w;
+    hipLaunchKernelGGL(cells_fin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, F);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset(unsigned *counters, int n, hipStream_t st)

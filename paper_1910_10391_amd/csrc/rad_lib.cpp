@@ -26,6 +26,7 @@ namespace rad {
 hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, int grid_blocks,
                       hipStream_t st, int *occupancy);
 hipError_t launch_reset(unsigned *counters, int n, hipStream_t st);
+hipError_t launch_cells_fin(const CellsFin &F, hipStream_t st);
 hipError_t launch_fin(const FinLaunch &F, hipStream_t st);
 hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
                         int n_w, int n_cubes, double *out, hipStream_t st);
@@ -96,12 +97,11 @@ rad_status check_dev_range(const void *p, size_t bytes, const char *name)
     return RAD_OK;
 }
 
-// Kernel variant per [persistent][mixed][with J].  Defaults are the measured
-// best on MI355X; the persistent FP64 form with J spills in its hot loop at 4x4,
-// so it defaults to 4x3.
+// Kernel variant per [persistent][mixed][with J]; the default is the measured best
+// on MI355X for the benchmark shapes, the autotuner may change it.
 std::mutex g_var_mu;
 int g_variant[2][2][2] = {{{kVar44x2, kVar44x2}, {kVar44x2, kVar44x2}},
-                          {{kVar44x2, kVar43x2}, {kVar44x2, kVar44x2}}};
+                          {{kVar44x2, kVar44x2}, {kVar44x2, kVar44x2}}};
 
 int variant_for(bool persistent, bool mixed, bool withj)
 {
@@ -218,6 +218,14 @@ rad_status check_segment(const rad_segment *s, int idx, bool quantum)
     return RAD_OK;
 }
 
+void set_grid_tiles(SegDesc &d, const Tile &t)
+{
+    d.n_tx = t.n_tx;
+    d.n_ty = t.n_ty;
+    d.n_groups = t.n_groups;
+    d.n_wblocks = t.n_wblocks;
+}
+
 // A planned call: everything the kernels need, decided on the host.
 struct Plan {
     rad_grid *g = nullptr;
@@ -316,7 +324,16 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
         d.energy = sg.energy_eV;
         d.n_chunks = nch[s];
         d.chunk_len = clen[s];
+        d.hw = g->d_hw;
+        d.k = g->d_k;
+        d.thx = g->d_thx;
+        d.thy = g->d_thy;
+        d.n_w = g->n_w;
+        d.n_x = g->n_x;
+        d.n_y = g->n_y;
         SegDesc dc = d, dq = d;
+        set_grid_tiles(dc, P.tile_c);
+        set_grid_tiles(dq, P.tile_q);
         dc.block_begin = blocks_c;
         dq.block_begin = blocks_q;
         blocks_c += (int64_t)nch[s] * P.tile_c.base_blocks;
@@ -416,21 +433,11 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
 
     AmpLaunch L{};
     L.n_segs = P.n_segs;
-    L.hw = g->d_hw;
-    L.k = g->d_k;
-    L.thx = g->d_thx;
-    L.thy = g->d_thy;
-    L.n_w = g->n_w;
-    L.n_x = g->n_x;
-    L.n_y = g->n_y;
+    L.items = nullptr;
     auto set_tile = [&](const Tile &t, int64_t nb) {
         L.n_blocks = nb;
-        L.n_tx = t.n_tx;
-        L.n_ty = t.n_ty;
         L.wg = t.wg;
         L.nt = t.nt;
-        L.n_groups = t.n_groups;
-        L.n_wblocks = t.n_wblocks;
     };
     if (P.persistent) {
         hipError_t e = launch_reset(counters, 2, st);
@@ -697,6 +704,14 @@ rad_status rad_angle_integrate(const rad_grid *g, const double *cube, int n_cube
     return RAD_OK;
 }
 
+}  // extern "C"
+
+namespace rad_err {
+void set(const char *msg) { g_err = msg; }
+}  // namespace rad_err
+
+extern "C" {
+
 struct rad_plan {
     Plan P;
     hipGraphExec_t gexec = nullptr;
@@ -793,6 +808,232 @@ void rad_plan_free(rad_plan *p)
     delete p;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- cell refinement
+namespace {
+
+struct CellsPlan {
+    int n_segs = 0, ncx = 0, ncy = 0, n_cells = 0, n_wb = 0;
+    int n_ps = 0;                 // active (segment, cell) pseudo-segments
+    int64_t n_items = 0;
+    size_t off_ps, off_items, off_psof, off_mask, off_part, desc_bytes, total;
+    std::vector<char> host;
+};
+
+constexpr int kCellWg = 1;        // 64 photon energies per block, 4 direction tiles (one 8x8 cell)
+
+rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, int kind, int cx, int cy,
+                      const uint8_t *mask, bool fill, CellsPlan &C, int comps)
+{
+    if (!g) return fail(RAD_EINVAL, "grid is NULL");
+    if (!segs || n_segs <= 0) return fail(RAD_EINVAL, "no segments");
+    if (!mask) return fail(RAD_EINVAL, "mask is NULL");
+    if (kind != RAD_CLASSICAL && kind != RAD_SPIN0 && kind != RAD_SPINHALF)
+        return fail(RAD_EINVAL, "kind must be exactly one of RAD_CLASSICAL, RAD_SPIN0, RAD_SPINHALF");
+    if (cx != 8 || cy != 8) return fail(RAD_EUNSUPPORTED, "cells of %d x %d directions (8 x 8 supported)", cx, cy);
+    if (g->n_x % cx || g->n_y % cy) return fail(RAD_EINVAL, "the grid (%d x %d) is not a whole number of cells", g->n_x, g->n_y);
+    C.n_segs = n_segs;
+    C.ncx = g->n_x / cx;
+    C.ncy = g->n_y / cy;
+    C.n_cells = C.ncx * C.ncy;
+    C.n_wb = (g->n_w + kWave * kCellWg - 1) / (kWave * kCellWg);
+    const int n_w = g->n_w;
+    // active (segment, cell) pairs and their photon-energy blocks
+    std::vector<int> psof((size_t)n_segs * C.n_cells, -1);
+    std::vector<std::vector<int>> wbs;
+    std::vector<std::pair<int, int>> ps;   // (segment, cell)
+    for (int s = 0; s < n_segs; ++s)
+        for (int c = 0; c < C.n_cells; ++c) {
+            std::vector<int> blocks;
+            for (int b = 0; b < C.n_wb; ++b) {
+                bool any = false;
+                for (int w = b * kWave * kCellWg; w < std::min(n_w, (b + 1) * kWave * kCellWg) && !any; ++w)
+                    any = mask[((size_t)s * n_w + w) * C.n_cells + c] != 0;
+                if (any) blocks.push_back(b);
+            }
+            if (!blocks.empty()) {
+                psof[(size_t)s * C.n_cells + c] = (int)ps.size();
+                ps.emplace_back(s, c);
+                wbs.push_back(blocks);
+            }
+        }
+    C.n_ps = (int)ps.size();
+    const int64_t base_items = 0;
+    (void)base_items;
+    int64_t items = 0;
+    for (auto &v : wbs) items += (int64_t)v.size();
+    // time chunks: enough items to fill the GPU
+    const int64_t cf = items >= kTargetBlocks ? 1 : (kTargetBlocks + std::max<int64_t>(items, 1) - 1) / std::max<int64_t>(items, 1);
+    std::vector<int32_t> nch(std::max(C.n_ps, 1)), clen(std::max(C.n_ps, 1));
+    int64_t sum_chunks = 0;
+    for (int p = 0; p < C.n_ps; ++p) {
+        plan_chunks(segs[ps[p].first].n, cf, nch[p], clen[p]);
+        sum_chunks += nch[p];
+        items += (int64_t)(nch[p] - 1) * (int64_t)wbs[p].size();
+    }
+    C.n_items = items;
+    const size_t cell_dirs = (size_t)cx * cy;
+    size_t o = 0;
+    C.off_ps = o; o = align_up(o + sizeof(SegDesc) * (size_t)std::max(C.n_ps, 1));
+    C.off_items = o; o = align_up(o + sizeof(int4) * (size_t)std::max<int64_t>(items, 1));
+    C.off_psof = o; o = align_up(o + sizeof(int) * psof.size());
+    C.off_mask = o; o = align_up(o + (size_t)n_segs * n_w * C.n_cells);
+    C.desc_bytes = o;
+    C.off_part = o;
+    o = align_up(o + (size_t)sum_chunks * comps * cell_dirs * n_w * sizeof(double2));
+    C.total = o;
+    if (!fill) return RAD_OK;
+    // descriptors
+    C.host.assign(C.desc_bytes, 0);
+    SegDesc *D = (SegDesc *)(C.host.data() + C.off_ps);
+    int4 *I = (int4 *)(C.host.data() + C.off_items);
+    std::memcpy(C.host.data() + C.off_psof, psof.data(), sizeof(int) * psof.size());
+    std::memcpy(C.host.data() + C.off_mask, mask, (size_t)n_segs * n_w * C.n_cells);
+    // launch order: longest segment first
+    std::vector<int> order(C.n_ps);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return segs[ps[a].first].n > segs[ps[b].first].n; });
+    int64_t part = 0, it = 0;
+    for (int p = 0; p < C.n_ps; ++p) {
+        const rad_segment &sg = segs[ps[p].first];
+        const int c = ps[p].second, ci = c % C.ncx, cj = c / C.ncx;
+        SegDesc d{};
+        const double *cols[C_NCOL] = {sg.t, sg.x, sg.y, sg.dz, sg.vx, sg.vy, sg.dvz, sg.ax, sg.ay, sg.az};
+        for (int k = 0; k < C_NCOL; ++k) d.col[k] = cols[k];
+        d.w = sg.w;
+        d.n = sg.n;
+        d.gamma = sg.gamma;
+        d.c0 = 1.0 / (2.0 * sg.gamma * sg.gamma);
+        d.energy = sg.energy_eV;
+        d.n_chunks = nch[p];
+        d.chunk_len = clen[p];
+        d.part_off = part;
+        part += (int64_t)nch[p] * comps * (int64_t)cell_dirs * n_w;
+        d.block_begin = 0;
+        d.hw = g->d_hw;
+        d.k = g->d_k;
+        d.thx = g->d_thx + (size_t)ci * cx;
+        d.thy = g->d_thy + (size_t)cj * cy;
+        d.n_w = n_w;
+        d.n_x = cx;
+        d.n_y = cy;
+        d.n_tx = cx / 4;
+        d.n_ty = cy / 4;
+        d.n_groups = 1;
+        d.n_wblocks = C.n_wb;
+        D[p] = d;
+    }
+    for (int r = 0; r < C.n_ps; ++r) {
+        const int p = order[r];
+        for (int ch = 0; ch < nch[p]; ++ch)
+            for (int b : wbs[p]) I[it++] = make_int4(p, ch, 0, b);
+    }
+    return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rad_cells_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int kind,
+                                 rad_precision prec, int cx, int cy, const uint8_t *mask)
+{
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    CellsPlan C;
+    if (cells_plan(g, segs, n_segs, kind, cx, cy, mask, false, C, kind == RAD_SPINHALF ? 3 : 2) != RAD_OK)
+        return 0;
+    return C.total;
+}
+
+rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                     rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
+                     void *ws, size_t ws_bytes, void *stream)
+{
+    rad_grid *g = const_cast<rad_grid *>(grid);
+    rad_status rs = check_grid(g);
+    if (rs != RAD_OK) return rs;
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    const bool quantum = kind != RAD_CLASSICAL;
+    for (int s = 0; s < n_segs && segs; ++s) {
+        rs = check_segment(&segs[s], s, quantum);
+        if (rs != RAD_OK) return rs;
+    }
+    const int comps = kind == RAD_SPINHALF ? 3 : 2;
+    CellsPlan C;
+    rs = cells_plan(g, segs, n_segs, kind, cx, cy, mask, true, C, comps);
+    if (rs != RAD_OK) return rs;
+    if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
+    if (ws_bytes < C.total) return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, C.total);
+    rs = check_dev_range(ws, C.total, "workspace");
+    if (rs != RAD_OK) return rs;
+    rs = check_dev_range(cell_out, (size_t)n_segs * g->n_w * C.n_cells * sizeof(double), "cell_out");
+    if (rs != RAD_OK) return rs;
+    hipStream_t st = (hipStream_t)stream;
+    Plan P;      // only for the staging upload
+    P.g = g;
+    P.ws = (char *)ws;
+    P.lay.desc_bytes = C.desc_bytes;
+    P.host.swap(C.host);
+    rs = plan_upload_async(P, st);
+    if (rs != RAD_OK) return rs;
+    char *wsb = (char *)ws;
+    double2 *part = (double2 *)(wsb + C.off_part);
+    if (C.n_items > 0) {
+        AmpLaunch L{};
+        L.segs = (const SegDesc *)(wsb + C.off_ps);
+        L.items = (const int4 *)(wsb + C.off_items);
+        L.n_segs = C.n_ps;
+        L.n_blocks = C.n_items;
+        L.wg = kCellWg;
+        L.nt = kWavesPerBlock / kCellWg;
+        L.quantum = quantum ? 1 : 0;
+        L.comps = comps;
+        L.part = part;
+        L.counter = nullptr;
+        const bool mixed = prec == RAD_MIXED;
+        const bool prof = profiling_on();
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (prof) {
+            if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+                return fail(RAD_EDEVICE, "hipEventCreate for profiling");
+            (void)hipEventRecord(ev0, st);
+        }
+        hipError_t e = launch_amp(L, kVar44x2, comps == 3, mixed, 0, st, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
+        if (prof) {
+            (void)hipEventRecord(ev1, st);
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof_pending.emplace_back(ev0, ev1);
+        }
+    }
+    CellsFin F{};
+    F.segs = (const SegDesc *)(wsb + C.off_ps);
+    F.psof = (const int *)(wsb + C.off_psof);
+    F.mask = (const uint8_t *)(wsb + C.off_mask);
+    F.part = part;
+    F.comps = comps;
+    F.kind = kind;
+    F.wx = g->d_wx;
+    F.wy = g->d_wy;
+    F.hw = g->d_hw;
+    F.n_segs = n_segs;
+    F.n_w = g->n_w;
+    F.n_x = g->n_x;
+    F.ncx = C.ncx;
+    F.n_cells = C.n_cells;
+    F.cx = cx;
+    F.cy = cy;
+    F.out = cell_out;
+    hipError_t e = launch_cells_fin(F, st);
+    if (e != hipSuccess) return hip_fail(e, "cell finalize launch");
+    return RAD_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant)
 {
     if (variant < 0 || variant >= kNumVariants) return fail(RAD_EINVAL, "variant %d unknown", variant);

@@ -65,6 +65,8 @@ def lib():
                 "rad_plan_launch": (I, [P, P, P]),
                 "rad_plan_launch_graph": (I, [P, P, P]),
                 "rad_plan_free": (None, [P]),
+                "rad_cells_workspace_bytes": (S, [P, SP, I, I, I, I, I, P]),
+                "rad_cells": (I, [P, SP, I, I, I, I, I, P, P, P, S, P]),
                 "rad_tune_num_variants": (I, []),
                 "rad_profile_enable": (I, [I]),
                 "rad_profile_read": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]),
@@ -263,6 +265,32 @@ def angle_integrate(grid, cubes, out=None, stream=None):
     _check_out(out, lead + (grid.shape[0],))
     _check(lib().rad_angle_integrate(grid.handle, _dptr(cubes), n_cubes, _dptr(out),
                                      _stream(stream)), "rad_angle_integrate")
+    return out
+
+
+def cells(grid, segs, kind, mask, precision=FP64, cx=8, cy=8, out=None, workspace=None,
+          stream=None):
+    """Exact cell integrals [n_segs, n_w, n_cells] where ``mask`` (uint8, same shape) is set
+    (rad_cells): the ``kind`` spectrum summed over each cx x cy cell times dthx dthy."""
+    import torch
+    ds = _as_segments(segs)
+    n_w, n_y, n_x = grid.shape
+    n_cells = (n_x // cx) * (n_y // cy)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if m.shape != (len(ds), n_w, n_cells):
+        raise ValueError("mask must have shape %s" % ((len(ds), n_w, n_cells),))
+    mp = ctypes.c_void_p(m.ctypes.data)
+    nb = int(lib().rad_cells_workspace_bytes(grid.handle, ds.structs, len(ds), int(kind),
+                                             int(precision), cx, cy, mp))
+    if nb == 0:
+        raise RadError(1, "rad_cells_workspace_bytes: invalid arguments: %s"
+                       % lib().rad_last_error().decode())
+    ws = _workspace(nb, workspace, ds.data.device)
+    if out is None:
+        out = torch.empty((len(ds), n_w, n_cells), dtype=torch.float64, device=ds.data.device)
+    _check_out(out, (len(ds), n_w, n_cells))
+    _check(lib().rad_cells(grid.handle, ds.structs, len(ds), int(kind), int(precision), cx, cy, mp,
+                           _dptr(out), _dptr(ws), _nbytes(ws), _stream(stream)), "rad_cells")
     return out
 
 

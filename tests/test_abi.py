@@ -10,11 +10,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rad.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rad.h", "rad_mlp.h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(rad_[a-z_0-9]+)\s*\(", src)))
 

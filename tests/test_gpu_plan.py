@@ -124,3 +124,33 @@ def test_autotune_picks_and_caches(rad, tmp_path, monkeypatch):
     finally:
         for k in keys:
             rad.tune_set_variant(*k, keep[k])
+
+
+def test_cells_match_full_grid(rad):
+    """rad_cells (masked cell integrals) equals the full-grid cube summed over each cell."""
+    import torch
+    segs, idx = _sections(2, seed=47)
+    segs = segs[:3]
+    g = segs[0]["gamma"]
+    hw = analytic.log_omega(100, 1e6, 20e9)      # 2 photon-energy blocks, ragged
+    th = analytic.cell_centred(16, 4.0 / g)      # 2 x 2 cells of 8 x 8
+    grid = rad.Grid(hw, th, th)
+    rng = np.random.default_rng(5)
+    mask = (rng.random((3, 100, 4)) < 0.3).astype(np.uint8)
+    mask[1] = 0                                   # a segment with nothing to do
+    mask[2, :, 3] = 1
+    for prec, tol in ((rad.FP64, 1e-12), (rad.MIXED, 1e-4)):
+        for kind, ki in ((rad.CLASSICAL, 0), (rad.SPINHALF, 2)):
+            got = rad.cells(grid, segs, kind, mask, precision=prec).cpu().numpy()
+            full = rad.batch(grid, segs, [0, 1, 2], 3, 7, precision=rad.FP64).cpu().numpy()[:, ki]
+            w = oracle.angle_weights(th)
+            cell = np.zeros((3, 100, 4))
+            for c in range(4):
+                ci, cj = c % 2, c // 2
+                blk = full[:, :, cj * 8:(cj + 1) * 8, ci * 8:(ci + 1) * 8]
+                cell[:, :, c] = np.einsum("swyx,y,x->sw", blk, w[cj * 8:(cj + 1) * 8], w[ci * 8:(ci + 1) * 8])
+            ref = np.where(mask > 0, cell, 0.0)
+            assert np.all(got[mask == 0] == 0)
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print("cells prec %d kind %d: max rel err %.3e" % (prec, kind, err), flush=True)
+            assert err < tol
