@@ -56,9 +56,9 @@ rad_status rad_mlp_set_params(rad_mlp *mlp, const float *host, void *stream);
 rad_status rad_mlp_get_adam(const rad_mlp *mlp, float *m1, float *m2, int64_t *step, void *stream);
 rad_status rad_mlp_set_adam(rad_mlp *mlp, const float *m1, const float *m2, int64_t step, void *stream);
 
-/* Workspace bytes of rad_mlp_grad / rad_mlp_forward for up to `batch` points and
- * `n_traj` trajectories. */
-size_t rad_mlp_workspace_bytes(const rad_mlp *mlp, int batch, int n_traj);
+/* Workspace bytes for up to `batch` points and `n_traj` trajectories: of
+ * rad_mlp_grad when `training` != 0, of rad_mlp_forward otherwise. */
+size_t rad_mlp_workspace_bytes(const rad_mlp *mlp, int batch, int n_traj, int training);
 
 /* Gradient of the mean squared error (1/B) sum_m (y_m - target_m)^2 with respect
  * to every parameter: grad (DEVICE float [param_count]); loss_sum (DEVICE float

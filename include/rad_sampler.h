@@ -1,0 +1,70 @@
+/*
+ * rad_sampler.h -- C ABI of the learned angular sampler's kernels (part of librad).
+ *
+ * The sampler estimates dI/d hw on a fine angular grid (n_x x n_y directions,
+ * split into cells of cx x cy) from (1) the exact spectrum at the cell centres
+ * (rad_batch on a coarse grid), (2) the MLP's predicted log intensity at every
+ * fine direction (include/rad_mlp.h), (3) exact cell integrals on the cells the
+ * prediction selects (rad_cells in include/rad.h); cells left out count as their
+ * centre value times their area.  A mismatch between the predicted and the
+ * coarse angle-integrated intensity makes a photon energy fall back to the full
+ * grid, the exact reference.  Conventions as in rad.h.
+ */
+#ifndef RAD_SAMPLER_H
+#define RAD_SAMPLER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rad.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAD_N_FEATURES 34
+
+/*
+ * Trajectory features for the network, one row of RAD_N_FEATURES floats per
+ * segment (DEVICE feat [n_segs][34]): log(gamma / 1e4); a 32-bin histogram, over
+ * [0, d/2] with d = plane_spacing_m, of the transverse oscillation amplitudes
+ * (half the distance between consecutive sign changes of v_x; amplitudes >= d/2,
+ * over-barrier motion, fall in the last bin), normalised to sum 1; and
+ * log(omega_osc / 1e5 m^-1) with omega_osc = pi (sign changes of v_x) / (t_end -
+ * t_0).  Uses only t, x, vx, n and gamma of each segment.  ws: DEVICE workspace of
+ * at least n_segs * 40 bytes.  Synchronises `stream` (one upload).
+ */
+rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacing_m, float *feat, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/*
+ * Cell selection per (trajectory, photon energy) of the fine grid `fine`:
+ * pred (DEVICE float [n_traj][n_w][n_y][n_x]) is the network's output, the log
+ * intensity being mu + sigma * pred; coarse (DEVICE double [n_traj][n_w][n_cells])
+ * the exact spectrum at the cell centres.  Writes mask (DEVICE uint8
+ * [n_traj][n_w][n_cells]) and fallback (DEVICE uint8 [n_traj][n_w]):
+ * fallback = |M_pred / M_coarse - 1| > tau (or M_coarse = 0), then every cell is
+ * selected; otherwise cells are taken in decreasing predicted mass while the
+ * predicted mass before them is below coverage * M_pred, at most `cap` cells.
+ * The selection is then widened to whole blocks of 64 photon energies (w / 64):
+ * a cell selected for one energy of a block is selected for all of them, since
+ * rad_cells evaluates a cell for a whole block at the cost of one.
+ * Needs n_cells = (n_x/cx)(n_y/cy) <= 64.
+ */
+rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
+                              const double *coarse, int cx, int cy, float coverage, int cap, float tau,
+                              uint8_t *mask, uint8_t *fallback, void *stream);
+
+/*
+ * dIdw (DEVICE double [n_traj][n_w]) = sum over cells of the exact cell integral
+ * (cells, DEVICE [n_traj][n_w][n_cells], from rad_cells) where mask is set, else
+ * the coarse centre value times the cell's area.
+ */
+rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
+                               const uint8_t *mask, const double *coarse, double *dIdw, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAD_SAMPLER_H */

@@ -23,7 +23,6 @@ struct rad_mlp {
 };
 
 // Error text shared with the rest of librad.
-extern "C" const char *rad_last_error(void);
 namespace rad_err {
 void set(const char *msg);
 }
@@ -78,6 +77,22 @@ struct MWs {
 constexpr int kSplits = 32;     // split-K slices of the weight-gradient products
 constexpr int kColSlices = 64;  // slices of the column sums
 
+// Inference needs only h1..h3, y and the folded biases (about 1.5 KB per point).
+MWs carve_infer(char *base, int64_t Bp, int n_traj)
+{
+    MWs w{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *p = base ? base + o : nullptr; o = al(o + bytes); return p; };
+    const size_t act = (size_t)Bp * kWidth;
+    w.h1 = (uint16_t *)take(act * 2);
+    w.h2 = (uint16_t *)take(act * 2);
+    w.h3 = (uint16_t *)take(act * 2);
+    w.y = (float *)take((size_t)Bp * 4);
+    w.cb = (float *)take((size_t)std::max(n_traj, 1) * kWidth * 4);
+    w.total = o;
+    return w;
+}
+
 MWs carve(char *base, int64_t Bp, int n_traj)
 {
     MWs w{};
@@ -129,21 +144,21 @@ rad_status check_range(const void *p, size_t bytes, const char *name)
 }
 
 rad_status check_batch(const rad_mlp *m, const float *feat, int n_traj, const int *traj, const float *x, int batch,
-                       void *ws, size_t ws_bytes, MWs &w)
+                       void *ws, size_t ws_bytes, MWs &w, bool training)
 {
     rad_status rs = check_mlp(m);
     if (rs != RAD_OK) return rs;
     if (batch <= 0 || n_traj <= 0) return mfail(RAD_EINVAL, "batch and n_traj must be > 0");
     if (batch > (1 << 26)) return mfail(RAD_EINVAL, "batch too large");
     const int64_t Bp = round64(batch);
-    w = carve(nullptr, Bp, n_traj);
+    w = training ? carve(nullptr, Bp, n_traj) : carve_infer(nullptr, Bp, n_traj);
     if (!ws) return mfail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < w.total) return mfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, w.total);
     if ((rs = check_range(ws, w.total, "workspace")) != RAD_OK) return rs;
     if (m->L.n_feat > 0 && (rs = check_range(feat, (size_t)n_traj * m->L.n_feat * 4, "feat")) != RAD_OK) return rs;
     if ((rs = check_range(traj, (size_t)batch * 4, "traj")) != RAD_OK) return rs;
     if ((rs = check_range(x, (size_t)batch * m->L.n_point * 4, "x")) != RAD_OK) return rs;
-    w = carve((char *)ws, Bp, n_traj);
+    w = training ? carve((char *)ws, Bp, n_traj) : carve_infer((char *)ws, Bp, n_traj);
     return RAD_OK;
 }
 
@@ -275,10 +290,10 @@ rad_status rad_mlp_set_adam(rad_mlp *m, const float *m1, const float *m2, int64_
     return e == hipSuccess ? RAD_OK : mhip(e, "Adam state upload");
 }
 
-size_t rad_mlp_workspace_bytes(const rad_mlp *m, int batch, int n_traj)
+size_t rad_mlp_workspace_bytes(const rad_mlp *m, int batch, int n_traj, int training)
 {
     if (!m || batch <= 0 || n_traj <= 0) return 0;
-    return carve(nullptr, round64(batch), n_traj).total;
+    return (training ? carve(nullptr, round64(batch), n_traj) : carve_infer(nullptr, round64(batch), n_traj)).total;
 }
 
 rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const int *traj, const float *x,
@@ -286,7 +301,7 @@ rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const i
                         void *stream)
 {
     MWs w;
-    rad_status rs = check_batch(m, feat, n_traj, traj, x, batch, ws, ws_bytes, w);
+    rad_status rs = check_batch(m, feat, n_traj, traj, x, batch, ws, ws_bytes, w, true);
     if (rs != RAD_OK) return rs;
     if ((rs = check_range(target, (size_t)batch * 4, "target")) != RAD_OK) return rs;
     if ((rs = check_range(grad, (size_t)m->L.total * 4, "grad")) != RAD_OK) return rs;
@@ -366,7 +381,7 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
                            int batch, float *y, void *ws, size_t ws_bytes, void *stream)
 {
     MWs w;
-    rad_status rs = check_batch(m, feat, n_traj, traj, x, batch, ws, ws_bytes, w);
+    rad_status rs = check_batch(m, feat, n_traj, traj, x, batch, ws, ws_bytes, w, false);
     if (rs != RAD_OK) return rs;
     if ((rs = check_range(y, (size_t)batch * 4, "y")) != RAD_OK) return rs;
     hipStream_t st = (hipStream_t)stream;

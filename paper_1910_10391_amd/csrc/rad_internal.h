@@ -96,4 +96,16 @@ struct CellsFin {
     double *out;                // [n_segs][n_w][n_cells]
 };
 
+// Read-only view of a grid handle's device arrays (for the sampler's host code).
+struct GridView {
+    const double *hw, *k, *thx, *thy, *wx, *wy;
+    int n_w, n_x, n_y, device;
+};
+
 }  // namespace rad
+
+struct rad_grid;
+bool rad_grid_view(const rad_grid *g, rad::GridView *v);
+namespace rad_err {
+void set(const char *msg);
+}

@@ -710,6 +710,13 @@ namespace rad_err {
 void set(const char *msg) { g_err = msg; }
 }  // namespace rad_err
 
+bool rad_grid_view(const rad_grid *g, rad::GridView *v)
+{
+    if (!g || !v) return false;
+    *v = rad::GridView{g->d_hw, g->d_k, g->d_thx, g->d_thy, g->d_wx, g->d_wy, g->n_w, g->n_x, g->n_y, g->device};
+    return true;
+}
+
 extern "C" {
 
 struct rad_plan {

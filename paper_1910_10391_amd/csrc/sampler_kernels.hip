@@ -1,0 +1,219 @@
+// Kernels of the learned angular sampler (gfx950): trajectory features, cell
+// selection from the network's prediction, and the refined angle integral.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sampler_internal.h"
+
+namespace radsmp {
+
+// ---------------------------------------------------------------- features
+// One block per trajectory.  Turning points are the sign changes of v_x
+// (between samples k and k+1, position x[k+1]); a half oscillation runs between
+// consecutive turning points and its amplitude is half the distance between
+// them.  Features: log(gamma / 1e4); a kHistBins-bin histogram of the amplitudes
+// over [0, d/2] (amplitudes >= d/2, over-barrier motion, fall in the last bin),
+// normalised to sum 1 (with fewer than two turning points the only entry is half
+// the total x excursion); log(omega_osc / 1e5 m^-1) with
+// omega_osc = pi (number of sign changes) / (t_end - t_0).
+__global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
+{
+    __shared__ int s_cnt[256];
+    __shared__ float s_tp[kMaxTurning];
+    __shared__ double s_min[256], s_max[256];
+    const FeatSeg &S = F.segs[blockIdx.x];
+    const int64_t n = S.n;
+    const int tid = threadIdx.x;
+    const int64_t per = (n - 1 + 255) / 256;             // pairs (k, k+1), k in [0, n-1)
+    const int64_t k0 = tid * per, k1 = min(n - 1, k0 + per);
+    int cnt = 0;
+    double xmn = 1e300, xmx = -1e300;
+    for (int64_t k = k0; k < k1; ++k) {
+        const bool a = S.vx[k] >= 0.0, b = S.vx[k + 1] >= 0.0;
+        cnt += (a != b);
+    }
+    for (int64_t k = tid; k < n; k += 256) {
+        xmn = fmin(xmn, S.x[k]);
+        xmx = fmax(xmx, S.x[k]);
+    }
+    s_cnt[tid] = cnt;
+    s_min[tid] = xmn;
+    s_max[tid] = xmx;
+    __syncthreads();
+    // exclusive prefix of the counts (in chunk order = time order) and the extrema
+    if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int c = s_cnt[i];
+            s_cnt[i] = acc;
+            acc += c;
+        }
+        double a = 1e300, b = -1e300;
+        for (int i = 0; i < 256; ++i) {
+            a = fmin(a, s_min[i]);
+            b = fmax(b, s_max[i]);
+        }
+        s_min[0] = a;
+        s_max[0] = b;
+    }
+    __syncthreads();
+    int o = s_cnt[tid];
+    for (int64_t k = k0; k < k1; ++k) {
+        const bool a = S.vx[k] >= 0.0, b = S.vx[k + 1] >= 0.0;
+        if (a != b) {
+            if (o < kMaxTurning) s_tp[o] = (float)S.x[k + 1];
+            ++o;
+        }
+    }
+    __syncthreads();
+    // the last thread's end offset is the total number of sign changes
+    __shared__ int s_total;
+    if (tid == 255) s_total = o;
+    __syncthreads();
+    if (tid != 0) return;
+    const int total = s_total;
+    const int stored = min(total, kMaxTurning);
+    float hist[kHistBins];
+    for (int i = 0; i < kHistBins; ++i) hist[i] = 0.0f;
+    const double half = 0.5 * F.plane_spacing;
+    int runs = 0;
+    auto put = [&](double amp) {
+        int bin = (int)(amp / half * kHistBins);
+        bin = bin < 0 ? 0 : (bin >= kHistBins ? kHistBins - 1 : bin);
+        hist[bin] += 1.0f;
+        ++runs;
+    };
+    for (int i = 0; i + 1 < stored; ++i) put(0.5 * fabs((double)s_tp[i + 1] - (double)s_tp[i]));
+    if (runs == 0) put(0.5 * (s_max[0] - s_min[0]));
+    float *f = F.feat + (int64_t)blockIdx.x * kFeatures;
+    f[0] = (float)log(S.gamma / 1e4);
+    for (int i = 0; i < kHistBins; ++i) f[1 + i] = hist[i] / (float)runs;
+    const double span = S.t[n - 1] - S.t[0];
+    const double w_osc = span > 0.0 ? kPi * (double)total / span : 0.0;
+    f[1 + kHistBins] = (float)log(fmax(w_osc, 1.0) / 1e5);
+}
+
+// ---------------------------------------------------------------- selection
+// One wave per (trajectory, photon energy); lane c < n_cells owns cell c.
+// Predicted cell mass: sum over the cell's fine directions of
+// exp(mu + sigma * yhat) dthx dthy.  Coarse cell mass: the exact spectrum at the
+// cell centre times the cell's area.  Fallback (every cell refined) when
+// |M_pred / M_coarse - 1| > tau.  Otherwise cells are taken in decreasing
+// predicted mass (ties by index) while the mass before them is below
+// coverage * M_pred, at most `cap` of them.
+__global__ __launch_bounds__(256) void select_kernel(SelectLaunch L)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;   // traj * n_w + w
+    if (item >= (int64_t)L.n_traj * L.n_w) return;
+    const int ncx = L.n_x / L.cx;
+    const int c = lane;
+    const bool live = c < L.n_cells;
+    double pm = 0.0, cm = 0.0, area = 0.0;
+    if (live) {
+        const int ci = c % ncx, cj = c / ncx;
+        const float *pred = L.pred + item * (int64_t)L.n_x * L.n_y;
+        for (int jy = 0; jy < L.cy; ++jy)
+            for (int jx = 0; jx < L.cx; ++jx) {
+                const int gx = ci * L.cx + jx, gy = cj * L.cy + jy;
+                const double dA = L.wx[gx] * L.wy[gy];
+                pm += exp((double)L.mu + (double)L.sigma * (double)pred[(int64_t)gy * L.n_x + gx]) * dA;
+                area += dA;
+            }
+        cm = L.coarse[item * L.n_cells + c] * area;
+    }
+    double Mp = pm, Mc = cm;
+    for (int off = 32; off > 0; off >>= 1) {
+        Mp += __shfl_xor(Mp, off, 64);
+        Mc += __shfl_xor(Mc, off, 64);
+    }
+    const bool fb = !(Mc > 0.0) || fabs(Mp / Mc - 1.0) > (double)L.tau;
+    // rank and predicted mass ahead of this cell
+    int rank = 0;
+    double ahead = 0.0;
+    for (int j = 0; j < 64; ++j) {
+        const double mj = __shfl(pm, j, 64);
+        const bool lj = j < L.n_cells;
+        const bool before = lj && (mj > pm || (mj == pm && j < c));
+        if (before) {
+            ++rank;
+            ahead += mj;
+        }
+    }
+    const bool sel = live && (fb || (rank < L.cap && ahead < (double)L.coverage * Mp));
+    if (live) L.mask[item * L.n_cells + c] = sel ? 1 : 0;
+    if (lane == 0) L.fallback[item] = fb ? 1 : 0;
+}
+
+// Widen the selection to whole blocks of kWBlock photon energies: rad_cells
+// evaluates a cell for a whole block at the cost of one energy, so every energy of
+// a block whose cell is selected anywhere in the block takes the exact value.
+// One thread per (trajectory, energy block, cell); in place.
+__global__ __launch_bounds__(256) void widen_kernel(uint8_t *mask, int n_traj, int n_w, int n_cells)
+{
+    const int n_wb = (n_w + kWBlock - 1) / kWBlock;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_traj * n_wb * n_cells) return;
+    const int c = (int)(i % n_cells);
+    const int b = (int)((i / n_cells) % n_wb);
+    const int64_t s = i / ((int64_t)n_cells * n_wb);
+    const int w0 = b * kWBlock, w1 = min(n_w, w0 + kWBlock);
+    uint8_t *m = mask + (s * n_w) * n_cells + c;
+    uint8_t any = 0;
+    for (int w = w0; w < w1; ++w) any |= m[(int64_t)w * n_cells];
+    if (any)
+        for (int w = w0; w < w1; ++w) m[(int64_t)w * n_cells] = 1;
+}
+
+// ---------------------------------------------------------------- combine
+// dI/dhw[traj][w] = sum_c (mask ? exact cell integral : coarse value x cell area).
+__global__ __launch_bounds__(256) void combine_kernel(CombineLaunch L)
+{
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= (int64_t)L.n_traj * L.n_w) return;
+    const int ncx = L.n_x / L.cx;
+    double acc = 0.0;
+    for (int c = 0; c < L.n_cells; ++c) {
+        const int64_t i = item * L.n_cells + c;
+        if (L.mask[i]) {
+            acc += L.cells[i];
+        } else {
+            const int ci = c % ncx, cj = c / ncx;
+            double ax = 0.0, ay = 0.0;
+            for (int j = 0; j < L.cx; ++j) ax += L.wx[ci * L.cx + j];
+            for (int j = 0; j < L.cy; ++j) ay += L.wy[cj * L.cy + j];
+            acc += L.coarse[i] * ax * ay;
+        }
+    }
+    L.out[item] = acc;
+}
+
+hipError_t launch_features(const FeatLaunch &F, int n_segs, hipStream_t st)
+{
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)n_segs), dim3(256), 0, st, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectLaunch &L, hipStream_t st)
+{
+    const int64_t items = (int64_t)L.n_traj * L.n_w;
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(uint8_t *mask, int n_traj, int n_w, int n_cells, hipStream_t st)
+{
+    const int64_t items = (int64_t)n_traj * ((n_w + kWBlock - 1) / kWBlock) * n_cells;
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, mask, n_traj, n_w,
+                       n_cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineLaunch &L, hipStream_t st)
+{
+    const int64_t items = (int64_t)L.n_traj * L.n_w;
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
+}  // namespace radsmp

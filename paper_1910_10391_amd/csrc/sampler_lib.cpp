@@ -1,0 +1,141 @@
+// librad: host side of the sampler C ABI (include/rad_sampler.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "rad_internal.h"
+#include "rad_sampler.h"
+#include "sampler_internal.h"
+
+using namespace radsmp;
+
+static_assert(sizeof(FeatSeg) == 40, "rad_features documents 40 workspace bytes per segment");
+
+namespace {
+
+rad_status sfail(rad_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    rad_err::set(buf);
+    return st;
+}
+
+rad_status srange(const void *p, size_t bytes, const char *name)
+{
+    if (!p) return sfail(RAD_EINVAL, "%s is NULL", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return sfail(RAD_EINVAL, "%s (%p) is not a device allocation", name, p);
+    }
+    if ((const char *)p + bytes > (const char *)base + size)
+        return sfail(RAD_EINVAL, "%s: %zu bytes exceed its device allocation", name, bytes);
+    return RAD_OK;
+}
+
+rad_status view_of(const rad_grid *g, rad::GridView &v)
+{
+    if (!rad_grid_view(g, &v)) return sfail(RAD_EINVAL, "grid is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return sfail(RAD_EDEVICE, "no HIP device");
+    if (dev != v.device) return sfail(RAD_EINVAL, "grid lives on device %d, current device is %d", v.device, dev);
+    return RAD_OK;
+}
+
+rad_status cells_shape(const rad::GridView &v, int cx, int cy, int &n_cells)
+{
+    if (cx <= 0 || cy <= 0 || v.n_x % cx || v.n_y % cy)
+        return sfail(RAD_EINVAL, "cells of %d x %d do not tile the %d x %d grid", cx, cy, v.n_x, v.n_y);
+    n_cells = (v.n_x / cx) * (v.n_y / cy);
+    if (n_cells > 64) return sfail(RAD_EUNSUPPORTED, "%d cells (at most 64)", n_cells);
+    return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacing_m, float *feat, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    if (!segs || n_segs <= 0) return sfail(RAD_EINVAL, "no segments");
+    if (!(plane_spacing_m > 0.0) || !std::isfinite(plane_spacing_m))
+        return sfail(RAD_EINVAL, "plane_spacing_m must be finite and > 0");
+    const size_t need = sizeof(FeatSeg) * (size_t)n_segs;
+    if (ws_bytes < need) return sfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    rad_status rs = srange(ws, need, "workspace");
+    if (rs != RAD_OK) return rs;
+    if ((rs = srange(feat, (size_t)n_segs * kFeatures * sizeof(float), "feat")) != RAD_OK) return rs;
+    std::vector<FeatSeg> h(n_segs);
+    for (int s = 0; s < n_segs; ++s) {
+        const rad_segment &sg = segs[s];
+        if (sg.n < 2) return sfail(RAD_EINVAL, "segment %d: n < 2", s);
+        if (!(sg.gamma > 0.0)) return sfail(RAD_EINVAL, "segment %d: gamma must be > 0", s);
+        const size_t b = (size_t)sg.n * sizeof(double);
+        if ((rs = srange(sg.t, b, "t")) != RAD_OK || (rs = srange(sg.x, b, "x")) != RAD_OK ||
+            (rs = srange(sg.vx, b, "vx")) != RAD_OK)
+            return rs;
+        h[s] = FeatSeg{sg.t, sg.x, sg.vx, sg.n, sg.gamma};
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(ws, h.data(), need, hipMemcpyHostToDevice, st);
+    FeatLaunch F{(const FeatSeg *)ws, plane_spacing_m, feat};
+    if (e == hipSuccess) e = launch_features(F, n_segs, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vector goes out of scope
+    if (e != hipSuccess) return sfail(RAD_EDEVICE, "features: %s", hipGetErrorString(e));
+    return RAD_OK;
+}
+
+rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
+                              const double *coarse, int cx, int cy, float coverage, int cap, float tau,
+                              uint8_t *mask, uint8_t *fallback, void *stream)
+{
+    rad::GridView v;
+    rad_status rs = view_of(fine, v);
+    if (rs != RAD_OK) return rs;
+    int n_cells = 0;
+    if ((rs = cells_shape(v, cx, cy, n_cells)) != RAD_OK) return rs;
+    if (n_traj <= 0) return sfail(RAD_EINVAL, "n_traj must be > 0");
+    if (!(coverage > 0.0f && coverage <= 1.0f) || cap < 1 || !(tau >= 0.0f) || !std::isfinite(mu) ||
+        !std::isfinite(sigma))
+        return sfail(RAD_EINVAL, "invalid coverage, cap, tau, mu or sigma");
+    const size_t items = (size_t)n_traj * v.n_w;
+    if ((rs = srange(pred, items * v.n_x * v.n_y * sizeof(float), "pred")) != RAD_OK) return rs;
+    if ((rs = srange(coarse, items * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
+    if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
+    if ((rs = srange(fallback, items, "fallback")) != RAD_OK) return rs;
+    SelectLaunch L{pred, mu, sigma, coarse, v.wx, v.wy, n_traj, v.n_w, v.n_x, v.n_y, cx, cy, n_cells,
+                   coverage, tau, cap, mask, fallback};
+    hipError_t e = launch_select(L, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_widen(mask, n_traj, v.n_w, n_cells, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "select: %s", hipGetErrorString(e));
+}
+
+rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
+                               const uint8_t *mask, const double *coarse, double *dIdw, void *stream)
+{
+    rad::GridView v;
+    rad_status rs = view_of(fine, v);
+    if (rs != RAD_OK) return rs;
+    int n_cells = 0;
+    if ((rs = cells_shape(v, cx, cy, n_cells)) != RAD_OK) return rs;
+    if (n_traj <= 0) return sfail(RAD_EINVAL, "n_traj must be > 0");
+    const size_t items = (size_t)n_traj * v.n_w;
+    if ((rs = srange(cells, items * n_cells * sizeof(double), "cells")) != RAD_OK) return rs;
+    if ((rs = srange(coarse, items * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
+    if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
+    if ((rs = srange(dIdw, items * sizeof(double), "dIdw")) != RAD_OK) return rs;
+    CombineLaunch L{cells, coarse, v.wx, v.wy, mask, n_traj, v.n_w, v.n_x, cx, cy, n_cells, dIdw};
+    hipError_t e = launch_combine(L, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "combine: %s", hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -28,7 +28,7 @@ def _lib():
             "rad_mlp_set_params": (I, [P, FP, P]),
             "rad_mlp_get_adam": (I, [P, FP, FP, ctypes.POINTER(I64), P]),
             "rad_mlp_set_adam": (I, [P, FP, FP, I64, P]),
-            "rad_mlp_workspace_bytes": (S, [P, I, I]),
+            "rad_mlp_workspace_bytes": (S, [P, I, I, I]),
             "rad_mlp_grad": (I, [P, P, I, P, P, P, I, P, P, P, S, P]),
             "rad_mlp_adam": (I, [P, P, F, F, F, F, P]),
             "rad_mlp_forward": (I, [P, P, I, P, P, I, P, P, S, P]),
@@ -103,9 +103,9 @@ class MLP:
             self.set_params(z["params"])
             self.set_adam(z["m1"], z["m2"], int(z["step"]))
 
-    def _workspace(self, batch, n_traj):
+    def _workspace(self, batch, n_traj, training=True):
         import torch
-        nb = int(_lib().rad_mlp_workspace_bytes(self.handle, int(batch), int(n_traj)))
+        nb = int(_lib().rad_mlp_workspace_bytes(self.handle, int(batch), int(n_traj), int(training)))
         if self._ws is None or self._ws.numel() < nb:
             self._ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
         return self._ws
@@ -152,7 +152,7 @@ class MLP:
         B = x.shape[0]
         if y is None:
             y = torch.empty(B, dtype=torch.float32, device="cuda")
-        ws = self._workspace(B, feat.shape[0])
+        ws = self._workspace(B, feat.shape[0], training=False)
         rad._check(_lib().rad_mlp_forward(self.handle, rad._dptr(feat), feat.shape[0], rad._dptr(traj),
                                           rad._dptr(x), B, rad._dptr(y), rad._dptr(ws), ws.numel(),
                                           rad._stream(stream)), "rad_mlp_forward")

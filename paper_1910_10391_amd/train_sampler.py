@@ -1,0 +1,160 @@
+"""Train, tune and evaluate the learned angular sampler on planar-channeling positrons.
+
+    python -m paper_1910_10391_amd.train_sampler --out sampler.npz --report report.json
+
+1. Training data: spectra the library computes (mixed precision, spin-1/2) for
+   ``--train`` positron trajectories (10 GeV, 100 um, harmonic+quartic planar well,
+   multiple scattering and radiative loss), each at 64 of the 512 photon energies
+   on the full 64 x 64 grid within +-5/gamma.
+2. Training: Adam on minibatches of (trajectory, energy, direction) points with the
+   library's BF16 MLP kernels.
+3. Tuning: the mass-mismatch tolerance tau on ``--val`` held-out trajectories.
+4. Evaluation on ``--test`` further held-out trajectories against the full-grid angle
+   integral: relative error of dI/d hw, evaluations and time, next to refinement
+   ranked by the coarse values alone (no network) and the coarse grid alone.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import rad
+from .mlp import MLP
+from .sampler import N_FEATURES, Grids, Sampler, train, training_set
+from .synth import channeling, presets
+
+
+def errors(est, full, floor=1e-3):
+    """Per-trajectory relative errors of dI/d hw: the largest |est - full| / full over energies
+    where full >= floor x the trajectory's peak, and the largest |est - full| / peak."""
+    est, full = np.asarray(est), np.asarray(full)
+    peak = full.max(axis=1, keepdims=True)
+    sel = full >= floor * peak
+    rel = np.where(sel, np.abs(est - full) / np.where(sel, full, 1.0), 0.0)
+    return rel.max(axis=1), (np.abs(est - full) / peak).max(axis=1)
+
+
+def _device_segments(cfg, n, first):
+    trs = channeling.generate(cfg, n, first=first, threads=16)
+    return rad.DeviceSegments([tr[0] for tr in trs])
+
+
+def evaluate(smp, ds, full, precision, rule="learned", reps=1):
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        r = smp.estimate(ds, precision=precision, rule=rule)
+        if best is None or r["seconds"] < best["seconds"]:
+            best = r
+    rel, peak = errors(best["dIdw"].cpu().numpy(), full)
+    return dict(rule=rule, max_rel_err=float(rel.max()), p95_rel_err=float(np.percentile(rel, 95)),
+                max_peak_err=float(peak.max()), fallback_frac=float(best["fallback"].mean()),
+                refined_cells_mean=best["refined_cells_mean"], evals=best["evals"],
+                evals_full=best["evals_full"], seconds=best["seconds"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--train", type=int, default=782, help="training trajectories (x 64 energies each)")
+    ap.add_argument("--val", type=int, default=32)
+    ap.add_argument("--test", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--coverage", type=float, default=0.99)
+    ap.add_argument("--cap", type=int, default=16)
+    ap.add_argument("--target", type=float, default=0.01, help="error bound tau is tuned for")
+    ap.add_argument("--out", default=None, help="checkpoint (.npz)")
+    ap.add_argument("--report", default=None, help="JSON report")
+    ap.add_argument("--load", default=None, help="skip training, load this checkpoint")
+    a = ap.parse_args(argv)
+    import torch
+
+    cfg = presets.positron_config()
+    pg = presets.positron_grid()
+    gamma = cfg.energy_eV / channeling.ME_EV
+    t_start = time.time()
+    report = dict(config=dict(workload="positron_spinhalf_sampler", particles_train=a.train,
+                              particles_val=a.val, particles_test=a.test, n_w=int(pg.hw.size), fine=64,
+                              cell=8, coverage=a.coverage, cap=a.cap, steps=a.steps, batch=a.batch))
+    if a.load:
+        smp = Sampler.load(a.load, pg.hw, gamma)
+        smp.coverage, smp.cap = a.coverage, a.cap
+        grids = smp.grids
+    else:
+        grids = Grids(pg.hw, gamma, n_fine=64, half_width_over_gamma=5.0)
+        t0 = time.time()
+        feat, W, Y = training_set(cfg, a.train, grids, n_w_train=64, first=40000, verbose=True)
+        torch.cuda.synchronize()
+        report["training_set_seconds"] = time.time() - t0
+        print("training set: %d spectra in %.1f s" % (W.numel(), report["training_set_seconds"]), flush=True)
+        mlp = MLP(N_FEATURES, 3, seed=a.seed)
+        t0 = time.time()
+        norm, losses = train(mlp, grids, feat, W, Y, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed,
+                             verbose=True)
+        torch.cuda.synchronize()
+        report["training_seconds"] = time.time() - t0
+        report["loss_first_last"] = [losses[0][1], losses[-1][1]]
+        del Y
+        smp = Sampler(mlp, norm, grids, cfg.d_m, a.coverage, a.cap, tau=0.25)
+    prec = rad.MIXED
+
+    # tau on held-out validation trajectories: the largest tolerance that keeps every
+    # validation error within the target
+    dv = _device_segments(cfg, a.val, 60000)
+    fv, _ = smp.full_grid(dv, prec)
+    fv = fv.cpu().numpy()
+    tune = []
+    chosen = 0.0
+    for tau in (0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0):
+        smp.tau = tau
+        r = evaluate(smp, dv, fv, prec)
+        tune.append(dict(tau=tau, max_rel_err=r["max_rel_err"], fallback_frac=r["fallback_frac"],
+                         evals_frac=r["evals"] / r["evals_full"]))
+        print("tau %.2f: max rel err %.4f fallback %.3f evals %.3f" % (
+            tau, r["max_rel_err"], r["fallback_frac"], r["evals"] / r["evals_full"]), flush=True)
+        if r["max_rel_err"] <= a.target:
+            chosen = tau
+    smp.tau = chosen
+    report["tau_scan"] = tune
+    report["tau"] = chosen
+
+    # test: held-out trajectories
+    dt_ = _device_segments(cfg, a.test, 70000)
+    smp.full_grid(dt_, prec)                              # warm-up
+    t_full = []
+    for _ in range(2):
+        f, s = smp.full_grid(dt_, prec)
+        t_full.append(s)
+    full = f.cpu().numpy()
+    res = {}
+    for rule in ("learned", "coarse"):
+        res[rule] = evaluate(smp, dt_, full, prec, rule=rule, reps=2)
+    # the coarse grid alone: every cell at its centre value x area
+    c = smp.coarse(dt_, prec)
+    area = float((2 * 5.0 / gamma / 8) ** 2)
+    rel, peak = errors((c.sum(dim=2) * area).cpu().numpy(), full)
+    res["coarse_only"] = dict(max_rel_err=float(rel.max()), max_peak_err=float(peak.max()))
+    res["full_grid_seconds"] = min(t_full)
+    for k in ("learned", "coarse"):
+        res[k]["speedup_vs_full"] = res["full_grid_seconds"] / res[k]["seconds"]
+        res[k]["evals_frac"] = res[k]["evals"] / res[k]["evals_full"]
+    report["test"] = res
+    report["accepted"] = res["learned"]["max_rel_err"] <= a.target
+    report["total_seconds"] = time.time() - t_start
+    print(json.dumps(res, indent=1), flush=True)
+    if a.out:
+        smp.save(a.out)
+    if a.report:
+        with open(a.report, "w") as fh:
+            json.dump(report, fh, indent=1)
+    return report
+
+
+if __name__ == "__main__":
+    main()

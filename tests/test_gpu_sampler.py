@@ -1,0 +1,169 @@
+"""The learned sampler's kernels (features, selection, combination) and the whole estimate
+against the CPU references (oracle/sampler.py and the direct-sum oracle)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sampler as osm
+from paper_1910_10391_amd.synth import analytic, channeling, presets
+
+pytestmark = pytest.mark.gpu
+
+D = 1.92e-10
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10391_amd import rad, sampler
+    rad.lib()
+    return sampler
+
+
+def _seg(t, x, vx, gamma):
+    z = np.zeros_like(t)
+    return dict(t=t, x=x, y=z, dz=z, vx=vx, vy=z, dvz=z, ax=z, ay=z, az=z, gamma=gamma, energy_eV=0.0)
+
+
+def _sinusoid(a, W, periods, per_period=64):
+    t = np.arange(periods * per_period + 1) * (2 * np.pi / W / per_period)
+    ph = W * t + 0.3
+    return t, a * np.sin(ph), a * W * np.cos(ph)
+
+
+def _short_positrons(n, first=0, length=8e-6):
+    cfg = dataclasses.replace(presets.positron_config(seed=11), length_m=length, n_min=3000, n_max=5000)
+    return cfg, [tr[0] for tr in channeling.generate(cfg, n, first=first, threads=8)]
+
+
+def test_features_match_oracle(S):
+    from paper_1910_10391_amd import rad
+    cfg = dataclasses.replace(presets.positron_config(seed=9), length_m=30e-6, n_min=6000, n_max=20000)
+    segs = [tr[0] for tr in channeling.generate(cfg, 3, threads=8)]
+    segs.append(_seg(*_sinusoid(0.3 * D / 2, 2e6, 10), gamma=3e4))
+    segs.append(_seg(*_sinusoid(0.7 * D / 2, 2e6, 3000), gamma=1e4))       # more turning points than kept
+    tl = np.linspace(0.0, 1e-5, 500)
+    segs.append(_seg(tl, 3 * D * tl / tl[-1], np.full_like(tl, 1.0), gamma=2e4))   # no turning point
+    ds = rad.DeviceSegments(segs)
+    got = S.features(ds, D).cpu().numpy().astype(np.float64)
+    for i, sg in enumerate(segs):
+        ref = osm.features(sg["t"], sg["x"], sg["vx"], sg["gamma"], D)
+        print("features %d: max abs diff %.2e" % (i, np.abs(got[i] - ref).max()), flush=True)
+        np.testing.assert_allclose(got[i, 1:33], ref[1:33], rtol=0, atol=1e-6)
+        np.testing.assert_allclose(got[i, [0, 33]], ref[[0, 33]], rtol=1e-6, atol=1e-6)
+
+
+def _fine(n=64, gamma=2e4, n_w=130):
+    from paper_1910_10391_amd import rad
+    th = analytic.cell_centred(n, 5.0 / gamma)
+    hw = analytic.log_omega(n_w, 1e6, 1e8)
+    return rad.Grid(hw, th, th), th
+
+
+def test_select_matches_oracle(S):
+    import torch
+    from paper_1910_10391_amd import rad
+    rng = np.random.default_rng(21)
+    grid, th = _fine()
+    n_w = grid.shape[0]
+    w = oracle.angle_weights(th)
+    n_traj = 3
+    # equal predictions across each 64-energy block, so that widening keeps the decisions visible
+    blocks = (n_w + 63) // 64
+    P = rng.normal(size=(n_traj, blocks, 64, 64)).astype(np.float32) * 2.0
+    pred = np.repeat(P, 64, axis=1)[:, :n_w].copy()
+    mu, sigma = np.float32(-3.0), np.float32(1.5)
+    pm = osm.cell_sums(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), w, w, 8, 8)
+    area = osm.cell_areas(w, w, 8, 8)
+    scale = 1.0 + 0.05 * rng.normal(size=(n_traj, n_w, 1))
+    scale[0, 5] = 2.0           # -> fallback (1/2 - 1 beyond tau)
+    scale[2, 100] = 0.5         # -> fallback
+    coarse = pm / area * scale
+    coarse[1, 7, :] = 0.0       # no coarse mass -> fallback
+    for cov, cap, tau in ((0.99, 16, 0.25), (0.5, 64, 0.25), (0.9, 3, 0.2)):
+        mask, fb = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, cov, cap, tau).select(
+            torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda())
+        rm, rf = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, cov, cap, tau)
+        assert np.array_equal(fb.cpu().numpy(), rf)
+        assert np.array_equal(mask.cpu().numpy(), rm), (cov, cap, tau)
+        print("select cov %.2f cap %d: %d cells of %d, %d fallbacks" % (cov, cap, rm.sum(), rm.size, rf.sum()))
+    # per-energy predictions: the widening itself
+    pred = (rng.normal(size=(n_traj, n_w, 64, 64)) * 2.0).astype(np.float32)
+    pm = osm.cell_sums(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), w, w, 8, 8)
+    coarse = pm / area
+    mask, fb = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, 0.6, 4, 0.25).select(
+        torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda())
+    rm, rf = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, 0.6, 4, 0.25)
+    assert np.array_equal(fb.cpu().numpy(), rf) and np.array_equal(mask.cpu().numpy(), rm)
+
+
+class _G:
+    """Just the fine grid, for calling the selection/combination steps directly."""
+
+    def __init__(self, grid):
+        self.fine = grid
+        self.hw = grid.hw
+        self.n = grid.thx.size
+
+
+def test_combine_matches_oracle(S):
+    import torch
+    rng = np.random.default_rng(22)
+    grid, th = _fine(n_w=70)
+    w = oracle.angle_weights(th)
+    cells = rng.random((2, 70, 64))
+    coarse = rng.random((2, 70, 64))
+    mask = (rng.random((2, 70, 64)) < 0.3).astype(np.uint8)
+    got = S.Sampler(None, dict(mu=0.0, sigma=1.0), _G(grid), D).combine(
+        torch.from_numpy(cells).cuda(), torch.from_numpy(mask).cuda(), torch.from_numpy(coarse).cuda())
+    ref = osm.combine(cells, mask, coarse, w, w, 8, 8)
+    err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print("combine: max rel err %.2e" % err)
+    assert err < 1e-13
+
+
+def test_estimate_matches_oracle(S):
+    """The whole estimate (coarse spectrum, features, network, selection, cell integrals,
+    combination) against the direct-sum oracle with the same selection; and with every
+    energy falling back, against the full-grid angle integral."""
+    import torch
+    from paper_1910_10391_amd import rad
+    from paper_1910_10391_amd.mlp import MLP
+    cfg, segs = _short_positrons(2)
+    gamma = segs[0]["gamma"]
+    hw = analytic.log_omega(70, 1e6, 150e6)
+    grids = S.Grids(hw, gamma, n_fine=16, half_width_over_gamma=5.0)
+    smp = S.Sampler(MLP(S.N_FEATURES, 3, seed=3), dict(mu=-8.0, sigma=2.0), grids, cfg.d_m,
+                    coverage=0.6, cap=2, tau=1e30)
+    ds = rad.DeviceSegments(segs)
+    th = grids.fine.thx
+    thc = grids.coarse.thx
+    w = oracle.angle_weights(th)
+    fine = np.stack([oracle.spectrum(sg, hw, th, th, oracle.KIND_SPINHALF)[oracle.KIND_SPINHALF] for sg in segs])
+    coarse = np.stack([oracle.spectrum(sg, hw, thc, thc, oracle.KIND_SPINHALF)[oracle.KIND_SPINHALF]
+                       for sg in segs]).reshape(2, 70, 4)
+    cells = osm.cell_sums(fine, w, w, 8, 8)
+    full = np.einsum("swyx,y,x->sw", fine, w, w)
+    feat = S.features(ds, cfg.d_m)
+    pred = S.predict(smp.mlp, grids, feat).cpu().numpy()
+    for prec, tol in ((rad.FP64, 1e-9), (rad.MIXED, 1e-4)):
+        res = smp.estimate(ds, precision=prec)
+        rm, rf = osm.select(pred, -8.0, 2.0, coarse, w, w, 8, 8, 0.6, 2, 1e30)
+        assert np.array_equal(res["mask"], rm) and not rf.any()
+        ref = osm.combine(cells, rm, coarse, w, w, 8, 8)
+        err = np.abs(res["dIdw"].cpu().numpy() - ref).max() / np.abs(ref).max()
+        print("estimate prec %d: %.2e (refined %.2f of 4 cells)" % (prec, err, res["refined_cells_mean"]))
+        assert err < tol
+        smp.tau = 0.0                                   # every energy falls back: the full grid
+        res = smp.estimate(ds, precision=prec)
+        assert res["fallback"].all()
+        err = np.abs(res["dIdw"].cpu().numpy() - full).max() / np.abs(full).max()
+        print("fallback prec %d: %.2e" % (prec, err))
+        assert err < tol
+        smp.tau = 1e30
+    dIdw, _ = smp.full_grid(ds, precision=rad.FP64)
+    assert np.abs(dIdw.cpu().numpy() - full).max() / np.abs(full).max() < 1e-9

@@ -1,0 +1,122 @@
+"""Pins of the sampler's CPU reference (oracle/sampler.py) by closed forms and hand-worked cases."""
+import numpy as np
+
+from oracle import sampler as osm
+
+
+D = 1.92e-10   # plane spacing [m]
+
+
+def _sinusoid(a, omega, periods, per_period=200, t0=0.0):
+    n = periods * per_period + 1
+    t = t0 + np.arange(n) * (2 * np.pi / omega / per_period)
+    phase = omega * t + 0.3
+    return t, a * np.sin(phase), a * omega * np.cos(phase)
+
+
+def test_features_sinusoid_closed_form():
+    """x = a sin(W t): every amplitude is a (to O((W dt)^2)), omega_osc = W (to 1/periods)."""
+    a = 10.5 / 32 * (D / 2)              # the middle of bin 10
+    W = 3.0e6                            # rad per metre of ct
+    t, x, vx = _sinusoid(a, W, periods=50)
+    f = osm.features(t, x, vx, gamma=2e4, plane_spacing=D)
+    assert f.shape == (34,)
+    assert abs(f[0] - np.log(2.0)) < 1e-15
+    hist = f[1:33]
+    assert hist[10] == 1.0 and hist.sum() == 1.0
+    assert abs(np.exp(f[33]) * 1e5 / W - 1.0) < 1.0 / 50
+
+
+def test_features_two_amplitudes():
+    """Half the oscillations at a1, half at a2: two bins of weight 1/2."""
+    a1, a2 = 3.5 / 32 * (D / 2), 20.5 / 32 * (D / 2)
+    W = 1.0e6
+    t1, x1, v1 = _sinusoid(a1, W, periods=20, t0=0.0)
+    # continue with the second amplitude from a turning point of the first (phase 0.3 + k 2pi)
+    t2, x2, v2 = _sinusoid(a2, W, periods=20, t0=t1[-1])
+    t = np.concatenate([t1, t2[1:]])
+    x = np.concatenate([x1, x2[1:] - x2[0] + x1[-1]])
+    vx = np.concatenate([v1, v2[1:]])
+    f = osm.features(t, x, vx, gamma=1e4, plane_spacing=D)
+    hist = f[1:33]
+    # one half-oscillation straddles the junction; it falls between the two bins
+    assert abs(hist[3] - 0.5) < 0.05 and abs(hist[20] - 0.5) < 0.05
+    assert abs(hist.sum() - 1.0) < 1e-12
+
+
+def test_features_over_barrier_and_no_turning():
+    """Monotonic drift across several planes: no turning point, omega_osc = 0, last bin."""
+    t = np.linspace(0.0, 1e-4, 1000)
+    x = 5 * D * t / t[-1]
+    vx = np.full_like(t, 5 * D / t[-1])
+    f = osm.features(t, x, vx, gamma=1e4, plane_spacing=D)
+    assert f[32] == 1.0 and f[1:32].sum() == 0.0
+    assert f[33] == np.log(1.0 / 1e5)
+
+
+def _unit_grid_select(masses, coarse_masses, coverage, cap, tau):
+    """1 trajectory, 1 energy, 2 x 2 fine grid with unit widths, 1 x 1 cells."""
+    pred = np.log(np.asarray(masses, dtype=np.float64)).reshape(1, 1, 2, 2)
+    coarse = np.asarray(coarse_masses, dtype=np.float64).reshape(1, 1, 4)
+    w = np.ones(2)
+    return osm.select(pred, 0.0, 1.0, coarse, w, w, 1, 1, coverage, cap, tau)
+
+
+def test_select_hand_worked():
+    m = [0.125, 0.5, 0.125, 0.25]                           # ranks: 1, 3, then 0 and 2 (ties by index)
+    mask, fb = _unit_grid_select(m, m, coverage=0.75, cap=4, tau=0.25)
+    assert fb[0, 0] == 0
+    assert mask[0, 0].tolist() == [0, 1, 0, 1]              # mass ahead of cell 0 is 0.75: not below 0.75
+    mask, _ = _unit_grid_select(m, m, coverage=0.8, cap=4, tau=0.25)
+    assert mask[0, 0].tolist() == [1, 1, 0, 1]              # cell 0 before cell 2 (equal mass)
+    mask, _ = _unit_grid_select(m, m, coverage=1.0, cap=2, tau=0.25)
+    assert mask[0, 0].tolist() == [0, 1, 0, 1]              # the cap
+    mask, fb = _unit_grid_select(m, [2 * v for v in m], coverage=0.5, cap=1, tau=0.25)
+    assert fb[0, 0] == 1 and mask[0, 0].tolist() == [1, 1, 1, 1]   # |0.5 - 1| > tau
+    mask, fb = _unit_grid_select(m, [0.0] * 4, coverage=0.5, cap=1, tau=10.0)
+    assert fb[0, 0] == 1 and mask.all()                     # no coarse mass
+
+
+def test_select_widens_to_energy_blocks():
+    n_w = 100                                               # blocks [0, 64), [64, 100)
+    pred = np.full((1, n_w, 2, 2), -50.0)
+    pred[0, 3, 0, 1] = 0.0                                  # energy 3: only cell 1 carries mass
+    pred[0, 70, 1, 0] = 0.0                                 # energy 70: only cell 2
+    coarse = np.exp(pred).reshape(1, n_w, 4)
+    w = np.ones(2)
+    mask, fb = osm.select(pred, 0.0, 1.0, coarse, w, w, 1, 1, 0.25, 4, 0.25)
+    assert not fb.any()
+    assert mask[0, :64, 1].all() and not mask[0, 64:, 1].any()
+    assert mask[0, 64:, 2].all() and not mask[0, :64, 2].any()
+    # other energies select their own top cell (cell 0 by index among equal masses)
+    assert mask[0, :, 0].all() and not mask[0, :, 3].any()
+
+
+def test_combine_exact_and_coarse():
+    rng = np.random.default_rng(3)
+    wx, wy = rng.random(4) + 0.5, rng.random(4) + 0.5
+    S = rng.random((2, 5, 4, 4))
+    cells = osm.cell_sums(S, wx, wy, 2, 2)
+    coarse = rng.random((2, 5, 4))
+    full = np.einsum("swyx,y,x->sw", S, wy, wx)
+    ones = np.ones((2, 5, 4), np.uint8)
+    assert np.allclose(osm.combine(cells, ones, coarse, wx, wy, 2, 2), full, rtol=1e-14)
+    # a spectrum constant over each cell: the coarse value times the area is exact
+    const = np.repeat(np.repeat(coarse.reshape(2, 5, 2, 2), 2, axis=2), 2, axis=3)
+    exact = np.einsum("swyx,y,x->sw", const, wy, wx)
+    zeros = np.zeros_like(ones)
+    assert np.allclose(osm.combine(cells, zeros, coarse, wx, wy, 2, 2), exact, rtol=1e-14)
+    # a mixed mask takes each cell from its own source
+    mask = (rng.random((2, 5, 4)) < 0.5).astype(np.uint8)
+    got = osm.combine(cells, mask, coarse, wx, wy, 2, 2)
+    area = osm.cell_areas(wx, wy, 2, 2)
+    ref = sum(cells[..., c] * mask[..., c] + coarse[..., c] * area[c] * (1 - mask[..., c]) for c in range(4))
+    assert np.allclose(got, ref, rtol=1e-14)
+
+
+def test_cell_sums_order():
+    """Cell c = cj * ncx + ci covers columns [ci cx, (ci+1) cx) and rows [cj cy, (cj+1) cy)."""
+    v = np.zeros((4, 6))
+    v[3, 4] = 1.0                                           # row 3, column 4 -> cj 1, ci 2
+    c = osm.cell_sums(v, np.ones(6), np.ones(4), 2, 2)
+    assert c.tolist() == [0, 0, 0, 0, 0, 1.0]
