@@ -38,17 +38,18 @@ VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2)}
 
 def flops_per_eval(variant, with_j=True):
     """FP64 flops per (t, w, n) eval of the amplitude kernel (FMA = 2): a lane makes
-    TX + TY phase factors per time step for TX*TY directions, 36 flops each (phase
-    product, exact reduction, f^2, two 9-term polynomials, f * poly); then per eval
+    TX + TY phase factors per time step for TX*TY directions, 34 flops each (phase
+    product, exact reduction, f^2, an 8-term sine and a 9-term cosine polynomial,
+    f * poly); then per eval
     a complex product (6) and 2 flops per real accumulator (A_x, A_y and J: 12)."""
     tx, ty, _ = VARIANTS[variant]
-    return 36.0 * (tx + ty) / (tx * ty) + 6.0 + (12.0 if with_j else 8.0)
+    return 34.0 * (tx + ty) / (tx * ty) + 6.0 + (12.0 if with_j else 8.0)
 
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
-# FP64 kernel (365 per 16 evals with J, 332 without), counted in the gfx950
+# FP64 kernel (358 per 16 evals with J, 329 without), counted in the gfx950
 # assembly of this build.
-VALU_PER_EVAL_44 = {True: 365.0 / 16.0, False: 332.0 / 16.0}
+VALU_PER_EVAL_44 = {True: 358.0 / 16.0, False: 329.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below).
@@ -73,7 +74,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--particles", type=int, default=0, help="0: the workload's own count")
     p.add_argument("--workload", default="positron_spinhalf",
-                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed"])
+                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep"])
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
@@ -215,6 +216,75 @@ def bench_pm(args):
     }
 
 
+def bench_sweep(args):
+    """Timing against the number of integrals (the axis of the paper's Sec. V timing
+    figure): one 3000-sample trajectory, FP64 classical spectrum, 10^2 .. 10^8
+    integrals (10 x 10 directions x 1 .. 10^6 photon energies).  GPU time with the
+    inputs resident, GPU time including the host copies (trajectory in, cube out), and
+    the CPU oracle on the host's cores up to 10^6 integrals; the crossover is the
+    smallest count where the GPU with copies beats the CPU."""
+    import torch
+    import oracle
+    from paper_1910_10391_amd import rad
+    from paper_1910_10391_amd.synth import analytic
+    seg = analytic.undulator(2e4, 0.5, 20e-6, 20, n_steps=2999)
+    ds = rad.DeviceSegments([seg])
+    g = 2e4
+    th = analytic.cell_centred(10, 1.0 / g)
+    fund = analytic.undulator_fundamental_eV(2e4, 0.5, 20e-6)
+    counts = [10 ** e for e in range(2, 9)]
+    rows = []
+    threads = oracle.max_threads()
+    for N in counts:
+        n_w = N // 100
+        hw = analytic.linear_omega(n_w, 1.5 * fund)
+        grid = rad.Grid(hw, th, th)
+        ws = torch.empty(rad.workspace_bytes(grid, ds.n[0], rad.CLASSICAL, rad.FP64), dtype=torch.uint8,
+                         device="cuda")
+        out = torch.empty(grid.shape, dtype=torch.float64, device="cuda")
+        host = torch.empty(grid.shape, dtype=torch.float64, pin_memory=True)
+        run = lambda: rad.classical(grid, ds, out=out, workspace=ws)  # noqa
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        one = time.perf_counter() - t0
+        reps = max(3, min(1000, int(0.3 / max(one, 1e-6))))
+        dt = timed(run, reps, torch.cuda.synchronize)
+
+        def with_copies():
+            d2 = rad.DeviceSegments([seg])
+            rad.classical(grid, d2, out=out, workspace=ws)
+            host.copy_(out)
+        dtc = timed(with_copies, max(2, reps // 4), torch.cuda.synchronize)
+        cpu = None
+        if N <= 10 ** 6:
+            t0 = time.perf_counter()
+            ref = oracle.spectrum(seg, hw, th, th, oracle.KIND_CLASSICAL)[oracle.KIND_CLASSICAL]
+            cpu = time.perf_counter() - t0
+            err = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
+        else:
+            err = None
+        rows.append({"integrals": N, "gpu_s": dt, "gpu_with_copies_s": dtc, "cpu_oracle_s": cpu,
+                     "evals_per_s": 3000.0 * N / dt, "rel_err_vs_oracle_M1": err})
+        print("bench sweep: %9d integrals  gpu %.3e s  with copies %.3e s  cpu %s" % (
+            N, dt, dtc, "%.3e s" % cpu if cpu else "-"), file=sys.stderr, flush=True)
+        grid.close()
+    cross = next((r["integrals"] for r in rows if r["cpu_oracle_s"] and r["gpu_with_copies_s"] < r["cpu_oracle_s"]),
+                 None)
+    top = rows[-1]
+    return {
+        "metric": METRIC, "value": top["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": top["gpu_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sweep: 3000-sample undulator trajectory (gamma 2e4, K 0.5), FP64 classical, "
+                               "10x10 directions within 1/gamma x 1..1e6 linear hw up to 1.5 x the first "
+                               "harmonic; 1e2..1e8 integrals"},
+        "sweep": rows, "crossover_integrals_vs_cpu": cross, "cpu_cores": threads,
+    }
+
+
 def sample_points(segs, grid):
     """The bounded sample: 2 shortest + 2 longest trajectories, every 8th photon
     energy, an 8 x 8 strided subset of directions."""
@@ -269,7 +339,8 @@ def main():
     from paper_1910_10391_amd import autotune, rad
 
     if args.workload != "positron_spinhalf":
-        fn = bench_sections if args.workload == "electron_50gev_sections" else bench_pm
+        fn = {"electron_50gev_sections": bench_sections, "pm_mixed": bench_pm,
+              "sweep": bench_sweep}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     t_gen = time.perf_counter()

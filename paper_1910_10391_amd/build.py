@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "librad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["rad_kernels.hip", "rad_lib.cpp", "mlp_kernels.hip", "mlp_lib.cpp", "sampler_kernels.hip",
-           "sampler_lib.cpp"]
+           "sampler_lib.cpp", "traj_kernels.hip", "traj_lib.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere in the GPU code

@@ -1,0 +1,123 @@
+// GPU trajectory generator (gfx950): one thread integrates one particle.
+//
+// The transverse motion is sequential in time, so the parallelism is across
+// particles; a thread keeps its state in registers and streams its samples to
+// HBM (88 bytes per step).  Arithmetic is kept in program order (no FMA
+// contraction), so that a host build of the same steps gives the same numbers
+// except where the device and host libraries round log and cos differently.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "traj_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace radtraj {
+
+// dU/dx of the periodic well for unit positive charge [eV/m]
+__device__ inline double slope(const rad_traj_params &p, double x)
+{
+    const double d = p.d_m;
+    const double xr = x - d * floor(x / d + 0.5);
+    const double u = 2.0 * xr / d;
+    return p.U0_eV * ((1.0 - p.q) * 2.0 * u + p.q * 4.0 * u * u * u) * (2.0 / d);
+}
+
+__device__ inline double gaussian(Stream &r)
+{
+    const double u1 = r.uniform(), u2 = r.uniform();
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+}
+
+__global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n_particles) return;
+    const rad_traj_params &p = L.p;
+    const TrajDesc D = L.desc[i];
+    Stream r = particle_stream(p.seed, L.first + i);
+    if (draw_steps(p, r) != D.n) return;   // the host drew the same count; never taken
+    const int64_t n = D.n;
+    double *const c = L.cols + D.off;
+    double *const ct = c, *const cx = c + L.total, *const cy = c + 2 * L.total, *const cdz = c + 3 * L.total;
+    double *const cvx = c + 4 * L.total, *const cvy = c + 5 * L.total, *const cdvz = c + 6 * L.total;
+    double *const cax = c + 7 * L.total, *const cay = c + 8 * L.total, *const caz = c + 9 * L.total;
+    double *const cen = c + 10 * L.total;
+
+    const double h = p.length_m / (double)n;
+    const double g_ref = p.energy_eV / kMe_eV;
+    const double inv2g2_ref = 0.5 / (g_ref * g_ref);
+    const double s = p.charge;
+    double E = p.energy_eV;
+    double x = (r.uniform() - 0.5) * p.d_m;
+    double vx = p.theta_sigma * gaussian(r);
+    double vy = p.theta_sigma * gaussian(r);
+    double y = 0.0, dz = 0.0;
+    // velocities of the two previous samples, for the central-difference accelerations
+    double v1x = 0.0, v1y = 0.0, v1z = 0.0, v2x = 0.0, v2y = 0.0, v2z = 0.0;
+    for (int64_t k = 0; k <= n; ++k) {
+        const double g = E / kMe_eV;
+        const double dvz = inv2g2_ref - 0.5 / (g * g) - 0.5 * (vx * vx + vy * vy);
+        ct[k] = h * (double)k;
+        cx[k] = x;
+        cy[k] = y;
+        cvx[k] = vx;
+        cvy[k] = vy;
+        cdvz[k] = dvz;
+        cdz[k] = dz;
+        cen[k] = E;
+        if (k >= 1) {
+            // sample k-1: central difference between samples max(k-2, 0) and k
+            const int64_t lo = k >= 2 ? k - 2 : 0;
+            const double dt = h * (double)k - h * (double)lo;
+            cax[k - 1] = (vx - (k >= 2 ? v2x : v1x)) / dt;
+            cay[k - 1] = (vy - (k >= 2 ? v2y : v1y)) / dt;
+            caz[k - 1] = (dvz - (k >= 2 ? v2z : v1z)) / dt;
+        }
+        if (k == n) {
+            // last sample: one-sided difference with sample n-1
+            const double dt = h * (double)n - h * (double)(n - 1);
+            cax[n] = (vx - v1x) / dt;
+            cay[n] = (vy - v1y) / dt;
+            caz[n] = (dvz - v1z) / dt;
+            break;
+        }
+        v2x = v1x;
+        v2y = v1y;
+        v2z = v1z;
+        v1x = vx;
+        v1y = vy;
+        v1z = dvz;
+        // RK4 on (x, vx) with E frozen over the step
+        const double f = -s / E;
+        const double k1x = vx, k1v = f * slope(p, x);
+        const double k2x = vx + 0.5 * h * k1v, k2v = f * slope(p, x + 0.5 * h * k1x);
+        const double k3x = vx + 0.5 * h * k2v, k3v = f * slope(p, x + 0.5 * h * k2x);
+        const double k4x = vx + h * k3v, k4v = f * slope(p, x + h * k3x);
+        x += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+        vx += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+        y += h * vy;
+        if (p.loss_on) {
+            const double a_mean = (k1v + 2.0 * k2v + 2.0 * k3v + k4v) / 6.0;
+            E -= h * (2.0 / 3.0) * kAlpha * kHbarC * g * g * g * g * a_mean * a_mean;
+        }
+        if (p.ms_on) {
+            const double sig = (p.eps_s_eV / E) * sqrt(h / p.X0_m);
+            const double dtx = sig * gaussian(r), dty = sig * gaussian(r);
+            vx += dtx;
+            vy += dty;
+            if (p.loss_on) E -= kMe_eV * kAlpha / (2.0 * kPi) * g * g * g * (dtx * dtx + dty * dty);
+        }
+        const double g1 = E / kMe_eV;
+        const double dvz1 = inv2g2_ref - 0.5 / (g1 * g1) - 0.5 * (vx * vx + vy * vy);
+        dz += 0.5 * h * (dvz + dvz1);
+    }
+}
+
+hipError_t launch_traj(const TrajLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(traj_kernel, dim3((unsigned)((L.n_particles + 63) / 64)), dim3(64), 0, st, L);
+    return hipGetLastError();
+}
+
+}  // namespace radtraj

@@ -1,0 +1,115 @@
+// librad: host side of the trajectory generator C ABI (include/rad_traj.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "rad_internal.h"
+#include "rad_traj.h"
+#include "traj_internal.h"
+
+using namespace radtraj;
+
+namespace {
+
+rad_status tfail(rad_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    rad_err::set(buf);
+    return st;
+}
+
+rad_status trange(const void *p, size_t bytes, const char *name)
+{
+    if (!p) return tfail(RAD_EINVAL, "%s is NULL", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return tfail(RAD_EINVAL, "%s (%p) is not a device allocation", name, p);
+    }
+    if ((const char *)p + bytes > (const char *)base + size)
+        return tfail(RAD_EINVAL, "%s: %zu bytes exceed its device allocation", name, bytes);
+    return RAD_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+rad_status check_params(const rad_traj_params *p)
+{
+    if (!p) return tfail(RAD_EINVAL, "params is NULL");
+    if (!(std::isfinite(p->energy_eV) && p->energy_eV > kMe_eV)) return tfail(RAD_EINVAL, "energy_eV must exceed m_e");
+    if (!(p->charge == 1.0 || p->charge == -1.0)) return tfail(RAD_EINVAL, "charge must be +1 or -1");
+    if (!std::isfinite(p->U0_eV) || !finite_pos(p->d_m) || !(p->q >= 0.0 && p->q <= 1.0) ||
+        !finite_pos(p->length_m) || !(std::isfinite(p->theta_sigma) && p->theta_sigma >= 0.0) ||
+        !finite_pos(p->X0_m) || !(std::isfinite(p->eps_s_eV) && p->eps_s_eV >= 0.0))
+        return tfail(RAD_EINVAL, "invalid well, crystal or scattering parameter");
+    if (p->n_min < 1 || p->n_max < p->n_min || p->n_max > (int64_t)1 << 40)
+        return tfail(RAD_EINVAL, "need 1 <= n_min <= n_max");
+    return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rad_status rad_traj_lengths(const rad_traj_params *p, int64_t first, int n_particles, int64_t *out)
+{
+    rad_status rs = check_params(p);
+    if (rs != RAD_OK) return rs;
+    if (n_particles <= 0 || !out || first < 0) return tfail(RAD_EINVAL, "need n_particles > 0, first >= 0, out");
+    for (int i = 0; i < n_particles; ++i) {
+        Stream r = particle_stream(p->seed, first + i);
+        out[i] = draw_steps(*p, r);
+    }
+    return RAD_OK;
+}
+
+size_t rad_traj_workspace_bytes(int n_particles)
+{
+    return n_particles > 0 ? sizeof(TrajDesc) * (size_t)n_particles : 0;
+}
+
+rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_particles, double *cols,
+                             int64_t total_samples, void *ws, size_t ws_bytes, void *stream)
+{
+    rad_status rs = check_params(p);
+    if (rs != RAD_OK) return rs;
+    if (n_particles <= 0 || first < 0) return tfail(RAD_EINVAL, "need n_particles > 0 and first >= 0");
+    std::vector<TrajDesc> desc(n_particles);
+    int64_t off = 0;
+    for (int i = 0; i < n_particles; ++i) {
+        Stream r = particle_stream(p->seed, first + i);
+        desc[i].n = draw_steps(*p, r);
+        desc[i].off = off;
+        off += desc[i].n + 1;
+    }
+    if (off != total_samples)
+        return tfail(RAD_EINVAL, "total_samples is %lld, the particles have %lld", (long long)total_samples,
+                     (long long)off);
+    const size_t need = rad_traj_workspace_bytes(n_particles);
+    if (ws_bytes < need) return tfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if ((rs = trange(ws, need, "workspace")) != RAD_OK) return rs;
+    if ((rs = trange(cols, (size_t)RAD_TRAJ_NCOL * (size_t)total_samples * sizeof(double), "cols")) != RAD_OK)
+        return rs;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t copied = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws, desc.data(), need, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(copied, st);
+    TrajLaunch L{*p, first, n_particles, total_samples, (const TrajDesc *)ws, cols};
+    if (e == hipSuccess) e = launch_traj(L, st);
+    // the descriptors are pageable host memory: wait for their copy (not the kernel)
+    if (e == hipSuccess) e = hipEventSynchronize(copied);
+    if (copied) (void)hipEventDestroy(copied);
+    if (e != hipSuccess) return tfail(RAD_EDEVICE, "trajectory generation: %s", hipGetErrorString(e));
+    return RAD_OK;
+}
+
+}  // extern "C"

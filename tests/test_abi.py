@@ -10,7 +10,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("rad.h", "rad_mlp.h", "rad_sampler.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rad.h", "rad_mlp.h", "rad_sampler.h", "rad_traj.h")]
 
 
 def declared_functions():

@@ -1,0 +1,115 @@
+"""Pins of the CPU trajectory generator (the reference of the GPU generator) against
+closed forms of its model: harmonic motion in the well, the multiple-scattering
+variance and its energy loss (Sec. III), the Larmor loss of a harmonic oscillation
+(the leading Landau-Lifshitz term, Sec. III), and the bookkeeping of dz, dvz and the
+accelerations."""
+import dataclasses
+import math
+
+import numpy as np
+
+from paper_1910_10391_amd.synth import channeling, presets
+
+ME = 0.51099895e6
+ALPHA = 7.2973525693e-3
+HBARC = 1.973269804e-7
+
+
+def _cfg(**kw):
+    base = dataclasses.replace(presets.positron_config(seed=21), length_m=50e-6, n_min=20000, n_max=20000)
+    return dataclasses.replace(base, **kw)
+
+
+def test_harmonic_well_motion():
+    """q = 0, no scattering, no loss, small amplitude: x = A sin(W t + phi) with
+    W^2 = 8 U0 / (E d^2) (d vx/dt = -U'(x)/E, U = U0 (2x/d)^2)."""
+    cfg = _cfg(q=0.0, ms_on=False, loss_on=False, theta_sigma=1e-9)
+    W = math.sqrt(8 * cfg.U0_eV / (cfg.energy_eV * cfg.d_m ** 2))
+    for i in range(3):
+        tr = channeling.trajectory(cfg, i)
+        x0, v0 = tr["x"][0], tr["vx"][0]
+        A = math.hypot(x0, v0 / W)
+        assert A < 0.5 * cfg.d_m
+        ref_x = x0 * np.cos(W * tr["t"]) + v0 / W * np.sin(W * tr["t"])
+        ref_v = -x0 * W * np.sin(W * tr["t"]) + v0 * np.cos(W * tr["t"])
+        assert np.abs(tr["x"] - ref_x).max() < 1e-8 * A
+        assert np.abs(tr["vx"] - ref_v).max() < 1e-8 * A * W
+        assert np.all(tr["energy"] == cfg.energy_eV)
+        assert np.all(tr["vy"] == tr["vy"][0])
+
+
+def test_equation_of_motion_both_charges():
+    """The second difference of x equals the force -charge U'(x)/E of the periodic
+    harmonic+quartic well (to O(h^2)); electrons feel the inverted well."""
+    for charge in (+1.0, -1.0):
+        cfg = _cfg(ms_on=False, loss_on=False, charge=charge, n_min=20000, n_max=20000)
+        tr = channeling.trajectory(cfg, 3)
+        d = cfg.d_m
+        h = tr["t"][1] - tr["t"][0]
+        acc = (tr["x"][2:] - 2 * tr["x"][1:-1] + tr["x"][:-2]) / h ** 2
+        xr = tr["x"][1:-1] - d * np.floor(tr["x"][1:-1] / d + 0.5)
+        u = 2 * xr / d
+        slope = cfg.U0_eV * ((1 - cfg.q) * 2 * u + cfg.q * 4 * u ** 3) * (2 / d)
+        force = -charge * slope / cfg.energy_eV
+        # away from the cusp of the periodic well (|u| near 1), where the second difference straddles it
+        ok = np.abs(u) < 0.9
+        assert ok.sum() > 1000
+        assert np.abs(acc - force)[ok].max() < 1e-4 * np.abs(force).max()
+
+
+def test_multiple_scattering_variance_and_loss():
+    """No well (U0 = 0): the total deflection is the sum of the kicks, variance
+    (eps_s/E)^2 L / X0 in each plane; with loss on, each kick costs
+    (m_e alpha / 2 pi) gamma^3 theta^2, summing to (m_e alpha/2pi) gamma^3 2 (eps_s/E)^2 L/X0
+    on average (Sec. III)."""
+    n = 2000
+    cfg = _cfg(U0_eV=0.0, loss_on=False, length_m=100e-6, n_min=400, n_max=400)
+    var = (cfg.eps_s_eV / cfg.energy_eV) ** 2 * cfg.length_m / cfg.X0_m
+    dx = np.empty(n)
+    dy = np.empty(n)
+    for i in range(n):
+        tr = channeling.trajectory(cfg, i)
+        dx[i] = tr["vx"][-1] - tr["vx"][0]
+        dy[i] = tr["vy"][-1] - tr["vy"][0]
+    for d in (dx, dy):
+        assert abs(d.var() / var - 1.0) < 0.12          # 3.8 sigma of the variance estimate
+        assert abs(d.mean()) < 4 * math.sqrt(var / n)
+    cfg = dataclasses.replace(cfg, loss_on=True)
+    g = cfg.energy_eV / ME
+    expect = ME * ALPHA / (2 * math.pi) * g ** 3 * 2 * var
+    loss = np.array([cfg.energy_eV - channeling.trajectory(cfg, i)["energy"][-1] for i in range(400)])
+    assert abs(loss.mean() / expect - 1.0) < 0.15
+
+
+def test_larmor_loss_of_harmonic_oscillation():
+    """q = 0, no scattering: the energy lost over L is (2/3) alpha hbar c gamma^4 <a^2> L
+    with <a^2> = W^4 A^2 / 2 (to the relative energy change, ~1e-4 here)."""
+    cfg = _cfg(q=0.0, ms_on=False, loss_on=True, theta_sigma=1e-9, length_m=100e-6, n_min=40000,
+               n_max=40000)
+    W = math.sqrt(8 * cfg.U0_eV / (cfg.energy_eV * cfg.d_m ** 2))
+    g = cfg.energy_eV / ME
+    for i in range(3):
+        tr = channeling.trajectory(cfg, i)
+        A = math.hypot(tr["x"][0], tr["vx"][0] / W)
+        # whole periods only, so that <sin^2> = 1/2 exactly
+        L = cfg.length_m
+        T = 2 * math.pi / W
+        k = int(np.searchsorted(tr["t"], math.floor(L / T) * T))
+        expect = (2.0 / 3.0) * ALPHA * HBARC * g ** 4 * W ** 4 * A ** 2 / 2 * tr["t"][k]
+        lost = cfg.energy_eV - tr["energy"][k]
+        assert abs(lost / expect - 1.0) < 2e-3, (lost, expect)
+
+
+def test_longitudinal_bookkeeping_and_accelerations():
+    cfg = _cfg(n_min=3000, n_max=3000)
+    tr = channeling.trajectory(cfg, 7)
+    g_ref = cfg.energy_eV / ME
+    g = tr["energy"] / ME
+    dvz = 0.5 / g_ref ** 2 - 0.5 / g ** 2 - 0.5 * (tr["vx"] ** 2 + tr["vy"] ** 2)
+    assert np.allclose(tr["dvz"], dvz, rtol=0, atol=1e-22)
+    h = tr["t"][1] - tr["t"][0]
+    dz = np.concatenate([[0.0], np.cumsum(0.5 * h * (tr["dvz"][1:] + tr["dvz"][:-1]))])
+    assert np.allclose(tr["dz"], dz, rtol=1e-12, atol=1e-24)
+    ax = np.gradient(tr["vx"], tr["t"], edge_order=1)
+    assert np.allclose(tr["ax"][1:-1], (tr["vx"][2:] - tr["vx"][:-2]) / (tr["t"][2:] - tr["t"][:-2]), rtol=1e-14)
+    assert np.allclose(tr["ax"], ax, rtol=1e-9, atol=1e-9 * np.abs(ax).max())

@@ -1,0 +1,44 @@
+"""Host-side parts of the GPU trajectory generator's C ABI: step counts (same random
+stream as the CPU generator) and argument validation.  No GPU needed."""
+import ctypes
+import dataclasses
+
+import pytest
+
+from paper_1910_10391_amd.synth import channeling, presets
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1910_10391_amd import rad, traj
+    try:
+        rad.lib()
+    except Exception as e:   # the library is built by __graft_entry__.build()
+        pytest.skip("librad not built: %s" % e)
+    return traj
+
+
+def test_lengths_match_cpu_generator(T):
+    for cfg in (presets.positron_config(), presets.electron_50gev_config(),
+                dataclasses.replace(presets.positron_config(seed=99), n_min=7, n_max=7)):
+        for first in (0, 1000):
+            assert (T.lengths(cfg, 50, first) == channeling.lengths(cfg, 50, first)).all()
+
+
+def test_invalid_parameters_rejected(T):
+    from paper_1910_10391_amd import rad
+    good = presets.positron_config()
+    for kw in (dict(energy_eV=1e5), dict(charge=0.5), dict(d_m=0.0), dict(q=1.5), dict(length_m=-1.0),
+               dict(theta_sigma=-1e-6), dict(X0_m=0.0), dict(n_min=0), dict(n_min=10, n_max=5),
+               dict(U0_eV=float("nan"))):
+        with pytest.raises(rad.RadError):
+            T.lengths(dataclasses.replace(good, **kw), 4)
+
+
+def test_generate_rejects_wrong_total_before_any_device_call(T):
+    from paper_1910_10391_amd import rad
+    p = T.params(presets.positron_config())
+    L = T._lib()
+    st = L.rad_traj_generate(ctypes.byref(p), 0, 4, None, 12345, None, 0, None)
+    assert st == 1
+    assert b"total_samples" in rad.lib().rad_last_error()
