@@ -74,7 +74,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--particles", type=int, default=0, help="0: the workload's own count")
     p.add_argument("--workload", default="positron_spinhalf",
-                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep"])
+                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep", "traj"])
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
@@ -285,6 +285,57 @@ def bench_sweep(args):
     }
 
 
+def bench_traj(args):
+    """Trajectory generation for the positron workload on the GPU (one thread per
+    particle) against the CPU generator on the host's cores, and the end-to-end step
+    (generate on the GPU, then the FP64 spin-1/2 spectrum) with no host round trip."""
+    import torch
+    from paper_1910_10391_amd import rad, traj
+    from paper_1910_10391_amd.synth import channeling, presets
+    n = args.particles or 256
+    cfg = presets.positron_config()
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    trs = channeling.generate(cfg, n, threads=threads)
+    cpu_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ds_host = rad.DeviceSegments([tr[0] for tr in trs])
+    torch.cuda.synchronize()
+    h2d = time.perf_counter() - t0
+    del ds_host
+    traj.DeviceTrajectories(cfg, n)          # warm-up
+    torch.cuda.synchronize()
+    gen = lambda: traj.DeviceTrajectories(cfg, n)  # noqa
+    dt_gen = timed(gen, max(1, args.steps), torch.cuda.synchronize)
+    dt = gen()
+    samples = int(sum(dt.n))
+    print("bench traj: %d particles, %d samples: gpu %.3f s, cpu generator %.3f s (%d threads), "
+          "host->device copy %.3f s" % (n, samples, dt_gen, cpu_gen, threads, h2d), file=sys.stderr, flush=True)
+    g = presets.positron_grid()
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    ws = torch.empty(rad.batch_workspace_bytes(grid, dt, n, rad.SPINHALF, rad.FP64), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty((n, 1) + grid.shape, dtype=torch.float64, device="cuda")
+
+    def step():
+        d = traj.DeviceTrajectories(cfg, n)
+        rad.batch(grid, d, list(range(n)), n, rad.SPINHALF, rad.FP64, out=out, workspace=ws)
+    step()
+    dt_step = timed(step, 1, torch.cuda.synchronize)
+    evals = samples * int(np.prod(grid.shape))
+    return {
+        "metric": METRIC, "value": evals / dt_step, "unit": "evals/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": dt_step * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "traj: %d positrons at 10 GeV, 100 um, generated on the GPU, then FP64 "
+                               "spin-1/2 on 512 log hw x 32x32" % n},
+        "generation": {"gpu_s": dt_gen, "cpu_generator_s": cpu_gen, "cpu_threads": threads,
+                       "host_to_device_copy_s": h2d, "samples": samples,
+                       "gpu_samples_per_s": samples / dt_gen, "speedup_vs_cpu": cpu_gen / dt_gen},
+        "trajectories_per_s_end_to_end": n / dt_step,
+    }
+
+
 def sample_points(segs, grid):
     """The bounded sample: 2 shortest + 2 longest trajectories, every 8th photon
     energy, an 8 x 8 strided subset of directions."""
@@ -340,7 +391,7 @@ def main():
 
     if args.workload != "positron_spinhalf":
         fn = {"electron_50gev_sections": bench_sections, "pm_mixed": bench_pm,
-              "sweep": bench_sweep}[args.workload]
+              "sweep": bench_sweep, "traj": bench_traj}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     t_gen = time.perf_counter()
