@@ -74,7 +74,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--particles", type=int, default=0, help="0: the workload's own count")
     p.add_argument("--workload", default="positron_spinhalf",
-                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep", "traj"])
+                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep", "traj", "sampler"])
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
@@ -336,6 +336,32 @@ def bench_traj(args):
     }
 
 
+def bench_sampler(args):
+    """The learned angular sampler on held-out positron trajectories: train (spectra
+    computed by the library, BF16 MLP on the GPU), tune tau on validation trajectories,
+    then time the sampler against the full 64 x 64 grid (both mixed precision, spin-1/2,
+    512 log hw).  value = full-grid evaluations replaced per second, i.e. the full grid's
+    evals divided by the sampler's time, at the measured error."""
+    import tempfile
+    from paper_1910_10391_amd import train_sampler
+    with tempfile.TemporaryDirectory() as d:
+        rep = train_sampler.main(["--report", os.path.join(d, "r.json"), "--test", str(args.particles or 64)])
+    t = rep["test"]
+    L = t["learned"]
+    return {
+        "metric": METRIC, "value": L["evals_full"] / L["seconds"], "unit": "evals/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": L["seconds"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16", "data": "synthetic",
+        "config": {"workload": "sampler: %d held-out positrons at 10 GeV, 100 um; spin-1/2 on 512 log hw x "
+                               "64x64 within 5/gamma, 8x8 cells; network trained on %d x 64 spectra"
+                               % (rep["config"]["particles_test"], rep["config"]["particles_train"])},
+        "speedup_vs_full_grid": L["speedup_vs_full"], "max_rel_err": L["max_rel_err"],
+        "accepted_1pct": rep["accepted"], "tau": rep["tau"], "evals_frac": L["evals_frac"],
+        "coarse_guided": t["coarse"], "coarse_only": t["coarse_only"],
+        "full_grid_s": t["full_grid_seconds"], "training_s": rep.get("training_seconds"),
+    }
+
+
 def sample_points(segs, grid):
     """The bounded sample: 2 shortest + 2 longest trajectories, every 8th photon
     energy, an 8 x 8 strided subset of directions."""
@@ -391,7 +417,8 @@ def main():
 
     if args.workload != "positron_spinhalf":
         fn = {"electron_50gev_sections": bench_sections, "pm_mixed": bench_pm,
-              "sweep": bench_sweep, "traj": bench_traj}[args.workload]
+              "sweep": bench_sweep, "traj": bench_traj,
+              "sampler": bench_sampler}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     t_gen = time.perf_counter()

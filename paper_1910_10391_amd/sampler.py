@@ -162,12 +162,22 @@ class Sampler:
                         coverage and cap and no fallback (refinement without a network,
                         the comparison the sampler has to beat)."""
         import torch
+        phases = {}
+
+        def mark(name, t_prev):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            phases[name] = t - t_prev
+            return t
+
         t0 = time.perf_counter()
         g = self.grids
         coarse = self.coarse(dsegs, precision)
+        t = mark("coarse", t0)
         if rule == "learned":
             feat = features(dsegs, self.d)
             pred = predict(self.mlp, g, feat)
+            t = mark("features_predict", t)
             mask, fb = self.select(pred, coarse)
         elif rule == "coarse":
             k = g.n // CELL
@@ -177,9 +187,11 @@ class Sampler:
         else:
             raise ValueError("rule must be 'learned' or 'coarse'")
         mask_h = mask.cpu().numpy()
+        t = mark("select", t)
         cells = rad.cells(g.fine, dsegs, KIND, mask_h, precision)
+        t = mark("cells", t)
         dIdw = self.combine(cells, mask, coarse)
-        torch.cuda.synchronize()
+        mark("combine", t)
         dt = time.perf_counter() - t0
         n_t = np.array(dsegs.n, dtype=np.float64)
         n_w = g.hw.size
@@ -187,7 +199,7 @@ class Sampler:
         # covers whole 64-energy blocks, and rad_cells evaluates exactly those)
         evals_refine = float(np.sum(n_t * mask_h.reshape(len(dsegs), -1).sum(axis=1)) * CELL * CELL)
         evals_coarse = float(np.sum(n_t) * n_w * g.n_cells)
-        return dict(dIdw=dIdw, mask=mask_h, fallback=fb.cpu().numpy(), seconds=dt,
+        return dict(dIdw=dIdw, mask=mask_h, fallback=fb.cpu().numpy(), seconds=dt, phases=phases,
                     evals=evals_coarse + evals_refine, evals_full=float(np.sum(n_t) * n_w * g.n ** 2),
                     refined_cells_mean=float(mask_h.sum(axis=2).mean()))
 

@@ -53,7 +53,7 @@ def evaluate(smp, ds, full, precision, rule="learned", reps=1):
     rel, peak = errors(best["dIdw"].cpu().numpy(), full)
     return dict(rule=rule, max_rel_err=float(rel.max()), p95_rel_err=float(np.percentile(rel, 95)),
                 max_peak_err=float(peak.max()), fallback_frac=float(best["fallback"].mean()),
-                refined_cells_mean=best["refined_cells_mean"], evals=best["evals"],
+                refined_cells_mean=best["refined_cells_mean"], evals=best["evals"], phases=best["phases"],
                 evals_full=best["evals_full"], seconds=best["seconds"])
 
 
