@@ -108,6 +108,7 @@ class _G:
         self.fine = grid
         self.hw = grid.hw
         self.n = grid.thx.size
+        self.n_cells = (self.n // 8) ** 2
 
 
 def test_combine_matches_oracle(S):
