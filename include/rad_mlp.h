@@ -73,7 +73,10 @@ rad_status rad_mlp_adam(rad_mlp *mlp, const float *grad, float lr, float beta1, 
                         void *stream);
 
 /* Inference y (DEVICE float [batch]): the trajectory part of layer 1 is folded into
- * one bias per trajectory, so layer 1 costs n_point products per unit and point. */
+ * one bias per trajectory, so layer 1 costs n_point products per unit and point.
+ * With n_point <= 8 one fused kernel runs the whole network for 32 points per wave
+ * (activations stay in registers, W2 in LDS); otherwise layer by layer.  The values
+ * of traj must lie in [0, n_traj). */
 rad_status rad_mlp_forward(const rad_mlp *mlp, const float *feat, int n_traj, const int *traj, const float *x,
                            int batch, float *y, void *ws, size_t ws_bytes, void *stream);
 

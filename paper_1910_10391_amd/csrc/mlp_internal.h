@@ -46,6 +46,11 @@ hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b
 hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t st);
 hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uint16_t *W2, uint16_t *W2T,
-                          uint16_t *W3, uint16_t *W3T, uint16_t *W4, hipStream_t st);
+                          uint16_t *W3, uint16_t *W3T, uint16_t *W3P, uint16_t *W4, hipStream_t st);
+// Fused inference (n_point <= 8): y for B points, cb from fold_bias; one block per CU.
+constexpr int kFusedMaxPointHost = 8;
+hipError_t launch_infer_fused(const uint16_t *W1p, const uint16_t *W2, const uint16_t *W3P, const uint16_t *W4,
+                              const float *cb, const float *b2, const float *b3, const float *b4, const int *traj,
+                              const float *x, int nf, int np, int B, float *y, int n_cu, hipStream_t st);
 
 }  // namespace radmlp

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "mlp_internal.h"
 
 namespace radmlp {
@@ -239,12 +241,24 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, float 
     p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
+// Column order of W3 for the fused inference kernel: within every group of 16
+// columns, position q = 8 h + j (h = 0, 1; j = 0..7) holds column 8 (j / 4) + 4 h + j % 4
+// of the group.  That is the order in which a lane of infer_fused_kernel holds the
+// layer-2 outputs (the MFMA result layout), so they serve as the next product's
+// operand without a transpose.
+__host__ __device__ inline int w3_fused_column(int q)
+{
+    const int g = q & ~15, h = (q >> 3) & 1, j = q & 7;
+    return g + 8 * (j >> 2) + 4 * h + (j & 3);
+}
+
 // BF16 working copies of the FP32 masters: W1 padded to kIn1 columns, W2, W3 and
-// their transposes, W4.
+// their transposes, W3 in the fused kernel's column order, W4.
 __global__ __launch_bounds__(256) void refresh_bf16(const float *__restrict__ p, MlpLayout L,
                                                     uint16_t *__restrict__ W1p, uint16_t *__restrict__ W2,
                                                     uint16_t *__restrict__ W2T, uint16_t *__restrict__ W3,
-                                                    uint16_t *__restrict__ W3T, uint16_t *__restrict__ W4)
+                                                    uint16_t *__restrict__ W3T, uint16_t *__restrict__ W3P,
+                                                    uint16_t *__restrict__ W4)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t sq = (int64_t)kWidth * kWidth;
@@ -258,8 +272,129 @@ __global__ __launch_bounds__(256) void refresh_bf16(const float *__restrict__ p,
         W3[i] = f2bf(p[L.w3 + i]);
         W2T[(int64_t)c * kWidth + o] = f2bf(p[L.w2 + i]);
         W3T[(int64_t)c * kWidth + o] = f2bf(p[L.w3 + i]);
+        W3P[i] = f2bf(p[L.w3 + (int64_t)o * kWidth + w3_fused_column(c)]);
     }
     if (i < kWidth) W4[i] = f2bf(p[L.w4 + i]);
+}
+
+// ---------------------------------------------------------------- fused inference
+// y = W4 silu(W3 silu(W2 silu(cb[traj] + W1x x) + b2) + b3) + b4 for 32 points per wave
+// without storing activations: a persistent grid, one block per CU, W2 (BF16) resident
+// in LDS (rows padded to 264 elements, so that the 32 rows an MFMA operand read touches
+// fall in distinct banks).  Products are computed transposed, C^T = W h^T (output units
+// as MFMA rows, points as columns): a lane then holds one point's values, the layer-1
+// activations are formed directly in the operand layout, and the layer-2 results in
+// the MFMA result layout are the layer-3 operand once W3's columns are permuted
+// (w3_fused_column).  BF16 rounding points as in the unfused path.
+constexpr int kFusedRow = kWidth + 8;
+constexpr int kFusedMaxPoint = 8;
+
+struct FusedArgs {
+    const uint16_t *W1p, *W2, *W3P, *W4;
+    const float *cb, *b2, *b3, *b4;
+    const int *traj;
+    const float *x;
+    int nf, np, B;
+    float *y;
+};
+
+__device__ __forceinline__ bf16x8 pack_bf16x8(const float v[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+    return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+__global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sW2[kWidth * kFusedRow];
+    __shared__ float sW1[kWidth * kFusedMaxPoint];
+    __shared__ float sb2[kWidth], sb3[kWidth], sW4[kWidth];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < kWidth * (kWidth / 8); i += 256) {
+        const int r = i / (kWidth / 8), c8 = i % (kWidth / 8);
+        *reinterpret_cast<uint4 *>(&sW2[r * kFusedRow + c8 * 8]) =
+            *reinterpret_cast<const uint4 *>(&a.W2[r * kWidth + c8 * 8]);
+    }
+    for (int i = tid; i < kWidth * a.np; i += 256)
+        sW1[(i / a.np) * kFusedMaxPoint + i % a.np] = bf2f(a.W1p[(i / a.np) * kIn1 + a.nf + i % a.np]);
+    for (int i = tid; i < kWidth; i += 256) {
+        sb2[i] = a.b2[i];
+        sb3[i] = a.b3[i];
+        sW4[i] = bf2f(a.W4[i]);
+    }
+    __syncthreads();
+    const int r = lane & 31, hs = lane >> 5;
+    const int n_tiles = (a.B + 31) / 32;
+    for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
+        const int pt = tile * 32 + r;
+        const int pc = pt < a.B ? pt : a.B - 1;      // padding lanes recompute the last point
+        const float *cbt = a.cb + (size_t)a.traj[pc] * kWidth;
+        float xv[kFusedMaxPoint];
+#pragma unroll
+        for (int j = 0; j < kFusedMaxPoint; ++j) xv[j] = j < a.np ? bf2f(f2bf(a.x[(size_t)pc * a.np + j])) : 0.0f;
+        // layer 1: units ks*16 + 8 hs + j of this lane's point, in operand layout
+        bf16x8 h1[kWidth / 16];
+#pragma unroll
+        for (int ks = 0; ks < kWidth / 16; ++ks) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int u = ks * 16 + 8 * hs + j;
+                float z = cbt[u];
+                for (int q = 0; q < a.np; ++q) z += sW1[u * kFusedMaxPoint + q] * xv[q];
+                v[j] = silu(z);
+            }
+            h1[ks] = pack_bf16x8(v);
+        }
+        // layer 2: C2^T tile mt = W2[mt*32 .. +32][:] h1^T; result register i is unit
+        // mt*32 + 8 (i/4) + 4 hs + i%4 of this lane's point
+        bf16x8 h2[kWidth / 16];
+#pragma unroll
+        for (int mt = 0; mt < kWidth / 32; ++mt) {
+            // one output tile at a time: keeps the operand reads of later tiles from being
+            // hoisted (which would exhaust the registers)
+            __builtin_amdgcn_sched_barrier(0);
+            floatx16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < kWidth / 16; ++ks) {
+                const bf16x8 w = *reinterpret_cast<const bf16x8 *>(&sW2[(mt * 32 + r) * kFusedRow + ks * 16 + 8 * hs]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, h1[ks], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int i = 8 * s2 + j;
+                    const int u = mt * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
+                    v[j] = silu(acc[i] + sb2[u]);
+                }
+                h2[2 * mt + s2] = pack_bf16x8(v);
+            }
+        }
+        // layer 3 with W3's columns in the same order, then the output dot product
+        float ys = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < kWidth / 32; ++mt) {
+            __builtin_amdgcn_sched_barrier(0);
+            floatx16 acc = {};
+            const uint16_t *w3 = a.W3P + (size_t)(mt * 32 + r) * kWidth + 8 * hs;
+#pragma unroll
+            for (int ks = 0; ks < kWidth / 16; ++ks) {
+                const bf16x8 w = *reinterpret_cast<const bf16x8 *>(w3 + ks * 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, h2[ks], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int u = mt * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
+                ys += sW4[u] * bf2f(f2bf(silu(acc[i] + sb3[u])));
+            }
+        }
+        ys += __shfl_xor(ys, 32, 64);
+        if (hs == 0 && pt < a.B) a.y[pt] = ys + a.b4[0];
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -347,11 +482,23 @@ hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n
 }
 
 hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uint16_t *W2, uint16_t *W2T,
-                          uint16_t *W3, uint16_t *W3T, uint16_t *W4, hipStream_t st)
+                          uint16_t *W3, uint16_t *W3T, uint16_t *W3P, uint16_t *W4, hipStream_t st)
 {
     const int64_t n = (int64_t)kWidth * kWidth;
     hipLaunchKernelGGL(refresh_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, L, W1p, W2, W2T, W3,
-                       W3T, W4);
+                       W3T, W3P, W4);
+    return hipGetLastError();
+}
+
+hipError_t launch_infer_fused(const uint16_t *W1p, const uint16_t *W2, const uint16_t *W3P, const uint16_t *W4,
+                              const float *cb, const float *b2, const float *b3, const float *b4, const int *traj,
+                              const float *x, int nf, int np, int B, float *y, int n_cu, hipStream_t st)
+{
+    if (np > kFusedMaxPoint || np < 1 || B < 1) return hipErrorInvalidValue;
+    FusedArgs a{W1p, W2, W3P, W4, cb, b2, b3, b4, traj, x, nf, np, B, y};
+    const int tiles = (B + 31) / 32;
+    const int blocks = std::max(1, std::min(n_cu, (tiles + 3) / 4));
+    hipLaunchKernelGGL(infer_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -18,8 +18,10 @@ struct rad_mlp {
     MlpLayout L{};
     int device = 0;
     float *p = nullptr, *m1 = nullptr, *m2 = nullptr;
-    uint16_t *W1p = nullptr, *W2 = nullptr, *W2T = nullptr, *W3 = nullptr, *W3T = nullptr, *W4 = nullptr;
+    uint16_t *W1p = nullptr, *W2 = nullptr, *W2T = nullptr, *W3 = nullptr, *W3T = nullptr, *W3P = nullptr,
+             *W4 = nullptr;
     int64_t step = 0;
+    int n_cu = 256;
 };
 
 // Error text shared with the rest of librad.
@@ -77,21 +79,26 @@ struct MWs {
 constexpr int kSplits = 32;     // split-K slices of the weight-gradient products
 constexpr int kColSlices = 64;  // slices of the column sums
 
-// Inference needs only h1..h3, y and the folded biases (about 1.5 KB per point).
-MWs carve_infer(char *base, int64_t Bp, int n_traj)
+// Inference needs the folded biases, and unless the fused kernel runs (n_point <= 8)
+// also h1..h3 and y (about 1.5 KB per point).
+MWs carve_infer(char *base, int64_t Bp, int n_traj, bool fused)
 {
     MWs w{};
     size_t o = 0;
     auto take = [&](size_t bytes) { char *p = base ? base + o : nullptr; o = al(o + bytes); return p; };
-    const size_t act = (size_t)Bp * kWidth;
-    w.h1 = (uint16_t *)take(act * 2);
-    w.h2 = (uint16_t *)take(act * 2);
-    w.h3 = (uint16_t *)take(act * 2);
-    w.y = (float *)take((size_t)Bp * 4);
+    const size_t act = fused ? 0 : (size_t)Bp * kWidth;
+    if (!fused) {
+        w.h1 = (uint16_t *)take(act * 2);
+        w.h2 = (uint16_t *)take(act * 2);
+        w.h3 = (uint16_t *)take(act * 2);
+        w.y = (float *)take((size_t)Bp * 4);
+    }
     w.cb = (float *)take((size_t)std::max(n_traj, 1) * kWidth * 4);
     w.total = o;
     return w;
 }
+
+bool fused_ok(const rad_mlp *m) { return m && m->L.n_point <= kFusedMaxPointHost; }
 
 MWs carve(char *base, int64_t Bp, int n_traj)
 {
@@ -151,14 +158,14 @@ rad_status check_batch(const rad_mlp *m, const float *feat, int n_traj, const in
     if (batch <= 0 || n_traj <= 0) return mfail(RAD_EINVAL, "batch and n_traj must be > 0");
     if (batch > (1 << 26)) return mfail(RAD_EINVAL, "batch too large");
     const int64_t Bp = round64(batch);
-    w = training ? carve(nullptr, Bp, n_traj) : carve_infer(nullptr, Bp, n_traj);
+    w = training ? carve(nullptr, Bp, n_traj) : carve_infer(nullptr, Bp, n_traj, fused_ok(m));
     if (!ws) return mfail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < w.total) return mfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, w.total);
     if ((rs = check_range(ws, w.total, "workspace")) != RAD_OK) return rs;
     if (m->L.n_feat > 0 && (rs = check_range(feat, (size_t)n_traj * m->L.n_feat * 4, "feat")) != RAD_OK) return rs;
     if ((rs = check_range(traj, (size_t)batch * 4, "traj")) != RAD_OK) return rs;
     if ((rs = check_range(x, (size_t)batch * m->L.n_point * 4, "x")) != RAD_OK) return rs;
-    w = training ? carve((char *)ws, Bp, n_traj) : carve_infer((char *)ws, Bp, n_traj);
+    w = training ? carve((char *)ws, Bp, n_traj) : carve_infer((char *)ws, Bp, n_traj, fused_ok(m));
     return RAD_OK;
 }
 
@@ -190,12 +197,16 @@ rad_status rad_mlp_create(int n_feat, int n_point, uint64_t seed, void *stream, 
         delete m;
         return mfail(RAD_EDEVICE, "no HIP device");
     }
+    if (hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+        m->n_cu < 1)
+        m->n_cu = 256;
     const size_t P = (size_t)m->L.total;
     const size_t sq = (size_t)kWidth * kWidth;
     struct { void **p; size_t bytes; } allocs[] = {
         {(void **)&m->p, P * 4}, {(void **)&m->m1, P * 4}, {(void **)&m->m2, P * 4},
         {(void **)&m->W1p, (size_t)kWidth * kIn1 * 2}, {(void **)&m->W2, sq * 2}, {(void **)&m->W2T, sq * 2},
-        {(void **)&m->W3, sq * 2}, {(void **)&m->W3T, sq * 2}, {(void **)&m->W4, (size_t)kWidth * 2}};
+        {(void **)&m->W3, sq * 2}, {(void **)&m->W3T, sq * 2}, {(void **)&m->W3P, sq * 2},
+        {(void **)&m->W4, (size_t)kWidth * 2}};
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
             rad_mlp_free(m);
@@ -232,7 +243,7 @@ void rad_mlp_free(rad_mlp *m)
 {
     if (!m) return;
     for (void *p : {(void *)m->p, (void *)m->m1, (void *)m->m2, (void *)m->W1p, (void *)m->W2, (void *)m->W2T,
-                    (void *)m->W3, (void *)m->W3T, (void *)m->W4})
+                    (void *)m->W3, (void *)m->W3T, (void *)m->W3P, (void *)m->W4})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -256,7 +267,7 @@ rad_status rad_mlp_set_params(rad_mlp *m, const float *host, void *stream)
     if (!host) return mfail(RAD_EINVAL, "host buffer is NULL");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(m->p, host, (size_t)m->L.total * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_refresh(m->p, m->L, m->W1p, m->W2, m->W2T, m->W3, m->W3T, m->W4, st);
+    if (e == hipSuccess) e = launch_refresh(m->p, m->L, m->W1p, m->W2, m->W2T, m->W3, m->W3T, m->W3P, m->W4, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e == hipSuccess ? RAD_OK : mhip(e, "parameter upload");
 }
@@ -293,7 +304,8 @@ rad_status rad_mlp_set_adam(rad_mlp *m, const float *m1, const float *m2, int64_
 size_t rad_mlp_workspace_bytes(const rad_mlp *m, int batch, int n_traj, int training)
 {
     if (!m || batch <= 0 || n_traj <= 0) return 0;
-    return (training ? carve(nullptr, round64(batch), n_traj) : carve_infer(nullptr, round64(batch), n_traj)).total;
+    return (training ? carve(nullptr, round64(batch), n_traj)
+                     : carve_infer(nullptr, round64(batch), n_traj, fused_ok(m))).total;
 }
 
 rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const int *traj, const float *x,
@@ -348,9 +360,8 @@ rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const i
         CK(launch_sum_slices(w.part, splits, kWidth, nprev[l], ncols, grad + woff[l], ncols, st));
         CK(launch_colsum(w.dz, nullptr, nullptr, Bp, kWidth, w.cpart, kColSlices, grad + boff[l], st));
         if (l < 2) {
-            // dz_prev = (dz W) * silu'(z_prev); dz is read (as BF16) before it is overwritten
-            // by rows of the product: copy the operand to dzT's buffer first? The product
-            // reads dzb and writes dz/dzb, so use hT as the operand buffer.
+            // dz_prev = (dz W) * silu'(z_prev).  The product overwrites dz/dzb while it
+            // reads its BF16 operand, so the operand is copied to the free hT buffer first.
             CK(hipMemcpyAsync(w.hT, w.dzb, (size_t)Bp * kWidth * 2, hipMemcpyDeviceToDevice, st));
             g = GemmArgs{w.hT, WT[l], Bp, kWidth, kWidth, kWidth, kWidth, kWidth, nullptr, zprev[l], w.dz, w.dzb,
                          kWidth};
@@ -373,7 +384,7 @@ rad_status rad_mlp_adam(rad_mlp *m, const float *grad, float lr, float beta1, fl
     const float c1 = (float)(1.0 - std::pow((double)beta1, (double)m->step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, (double)m->step));
     hipError_t e = launch_adam(m->p, m->m1, m->m2, grad, m->L.total, lr, beta1, beta2, eps, c1, c2, st);
-    if (e == hipSuccess) e = launch_refresh(m->p, m->L, m->W1p, m->W2, m->W2T, m->W3, m->W3T, m->W4, st);
+    if (e == hipSuccess) e = launch_refresh(m->p, m->L, m->W1p, m->W2, m->W2T, m->W3, m->W3T, m->W3P, m->W4, st);
     return e == hipSuccess ? RAD_OK : mhip(e, "Adam launch");
 }
 
@@ -388,6 +399,12 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
     const MlpLayout &L = m->L;
     const int Bp = (int)round64(batch);
     hipError_t e = launch_fold_bias(m->W1p, m->p + L.b1, feat, L.n_feat, n_traj, w.cb, st);
+    if (fused_ok(m)) {
+        if (e == hipSuccess)
+            e = launch_infer_fused(m->W1p, m->W2, m->W3P, m->W4, w.cb, m->p + L.b2, m->p + L.b3, m->p + L.b4, traj, x,
+                                   L.n_feat, L.n_point, batch, y, m->n_cu, st);
+        return e == hipSuccess ? RAD_OK : mhip(e, "MLP forward");
+    }
     if (e == hipSuccess) e = launch_layer1_points(m->W1p, w.cb, L.n_feat, traj, x, L.n_point, batch, Bp, w.h1, st);
     GemmArgs g{w.h1, m->W2, Bp, kWidth, kWidth, kWidth, kWidth, kWidth, m->p + L.b2, nullptr, nullptr, w.h2, kWidth};
     if (e == hipSuccess) e = launch_gemm(kEpiFwd, g, 1, st);

@@ -227,30 +227,56 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         for (int tloc = 0; tloc < tn; ++tloc) {
             const int slot = tloc * nt + tl;
             double xr[TX], xi[TX];
+            // row 0's integrand values and phase part, read before the X phase factors
+            // so that their latency is hidden
+            double2 fn[TX];
+            double qn[TX];
+            double pyn = s_py[slot * TY];
+#pragma unroll
+            for (int jx = 0; jx < TX; ++jx) {
+                fn[jx] = s_fxy[slot * NP + jx];
+                if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + jx];
+            }
 #pragma unroll
             for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
 #pragma unroll
             for (int jy = 0; jy < TY; ++jy) {
-                // with J at 16 directions per lane the kernel sits at the VGPR limit: keep
-                // each row's LDS reads next to their use (hoisting all TX*TY integrand
-                // loads of a time step costs 4 VGPRs each and spills the accumulators)
+                // with J at 16 directions per lane the kernel sits at the VGPR limit: each
+                // row is its own scheduling region, so that only two rows of integrand
+                // values are ever live; the next row's values are read at the end of this
+                // row's region (software pipelining across the barrier).
                 if constexpr (WITHJ && TX * TY >= 16) __builtin_amdgcn_sched_barrier(0);
+                double2 f[TX];
+                double q[TX];
+#pragma unroll
+                for (int jx = 0; jx < TX; ++jx) {
+                    f[jx] = fn[jx];
+                    if constexpr (WITHJ) q[jx] = qn[jx];
+                }
+                // this row's phase part; the next row's is read one region ahead
+                const double py = pyn;
+                if (jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
                 double yr, yi;
-                lane_cis<MIXED>(kh, s_py[slot * TY + jy], yr, yi);
+                lane_cis<MIXED>(kh, py, yr, yi);
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) {
                     const int p = jy * TX + jx;
                     const double er = xr[jx] * yr - xi[jx] * yi;
                     const double ei = xr[jx] * yi + xi[jx] * yr;
-                    const double2 f = s_fxy[slot * NP + p];
-                    axr[p] = __builtin_fma(f.x, er, axr[p]);
-                    axi[p] = __builtin_fma(f.x, ei, axi[p]);
-                    ayr[p] = __builtin_fma(f.y, er, ayr[p]);
-                    ayi[p] = __builtin_fma(f.y, ei, ayi[p]);
+                    axr[p] = __builtin_fma(f[jx].x, er, axr[p]);
+                    axi[p] = __builtin_fma(f[jx].x, ei, axi[p]);
+                    ayr[p] = __builtin_fma(f[jx].y, er, ayr[p]);
+                    ayi[p] = __builtin_fma(f[jx].y, ei, ayi[p]);
                     if constexpr (WITHJ) {
-                        const double q = s_fq[slot * NP + p];
-                        jr[p] = __builtin_fma(q, er, jr[p]);
-                        ji[p] = __builtin_fma(q, ei, ji[p]);
+                        jr[p] = __builtin_fma(q[jx], er, jr[p]);
+                        ji[p] = __builtin_fma(q[jx], ei, ji[p]);
+                    }
+                }
+                if (jy + 1 < TY) {
+#pragma unroll
+                    for (int jx = 0; jx < TX; ++jx) {
+                        fn[jx] = s_fxy[slot * NP + (jy + 1) * TX + jx];
+                        if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + (jy + 1) * TX + jx];
                     }
                 }
             }

@@ -80,14 +80,14 @@ def main(argv=None):
     gamma = cfg.energy_eV / channeling.ME_EV
     t_start = time.time()
     report = dict(config=dict(workload="positron_spinhalf_sampler", particles_train=a.train,
-                              particles_val=a.val, particles_test=a.test, n_w=int(pg.hw.size), fine=64,
+                              particles_val=a.val, particles_test=a.test, n_w=int(pg.hw_eV.size), fine=64,
                               cell=8, coverage=a.coverage, cap=a.cap, steps=a.steps, batch=a.batch))
     if a.load:
-        smp = Sampler.load(a.load, pg.hw, gamma)
+        smp = Sampler.load(a.load, pg.hw_eV, gamma)
         smp.coverage, smp.cap = a.coverage, a.cap
         grids = smp.grids
     else:
-        grids = Grids(pg.hw, gamma, n_fine=64, half_width_over_gamma=5.0)
+        grids = Grids(pg.hw_eV, gamma, n_fine=64, half_width_over_gamma=5.0)
         t0 = time.time()
         feat, W, Y = training_set(cfg, a.train, grids, n_w_train=64, first=40000, verbose=True)
         torch.cuda.synchronize()

@@ -57,6 +57,21 @@ def test_forward_folded_matches_cpu_reference(M):
     assert err < 5e-3
 
 
+@pytest.mark.parametrize("nf,npnt,B,n_traj", [(34, 3, 1, 1), (34, 3, 31, 2), (34, 3, 4099, 7), (1, 8, 200, 1),
+                                             (34, 9, 333, 3)])
+def test_forward_paths_match_cpu_reference(M, nf, npnt, B, n_traj):
+    """Inference at ragged sizes: n_point <= 8 runs the fused kernel (activations never
+    leave the registers), n_point = 9 the layer-by-layer path; both against the CPU
+    reference with BF16 rounding."""
+    net = M.MLP(nf, npnt, seed=5 + npnt)
+    (feat, traj, x, target), dev = _data(6 + B, nf=nf, npnt=npnt, B=B, n_traj=n_traj)
+    y = net.forward(dev[0], dev[1], dev[2]).cpu().numpy().astype(np.float64)
+    yr, _ = ref.forward(net.get_params().astype(np.float64), feat, traj, x, bf=True)
+    err = np.max(np.abs(y - yr)) / max(np.max(np.abs(yr)), 1e-30)
+    print("forward nf %d np %d B %d: rel err %.2e" % (nf, npnt, B, err), flush=True)
+    assert err < 5e-3
+
+
 def test_adam_step_matches_cpu_reference(M):
     import torch
     net = M.MLP(34, 3, seed=7)
