@@ -70,6 +70,9 @@ rad_status rad_traj_lengths(const rad_traj_params *p, int64_t first, int n_parti
 /* DEVICE workspace bytes of rad_traj_generate for n_particles. */
 size_t rad_traj_workspace_bytes(int n_particles);
 
+/* DEVICE workspace bytes of rad_traj_sections (40 bytes per section). */
+size_t rad_traj_sections_workspace_bytes(int n_particles, int n_sections);
+
 /*
  * Generate particles first .. first + n_particles - 1 into cols (DEVICE double
  * [RAD_TRAJ_NCOL][total_samples], column-major over all samples: column c of
@@ -81,6 +84,26 @@ size_t rad_traj_workspace_bytes(int n_particles);
  */
 rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_particles, double *cols,
                              int64_t total_samples, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Cut the trajectories that rad_traj_generate wrote into `cols` into n_sections
+ * sections each (the paper's sections, Sec. II: the energy is fixed per section and
+ * the section spectra add).  Section s of particle i holds samples k_s .. k_{s+1}
+ * (both ends; k_s = floor(s n_i / n_sections)), with gamma_s = E(k_s) / m_e and dz,
+ * dvz re-referenced to beta_s = 1 - 1/(2 gamma_s^2): dvz += 1/(2 gamma_s^2) -
+ * 1/(2 gamma_ref^2), dz += (the same) t; t, x, y, vx, vy and the accelerations are
+ * copied.  sec_cols (DEVICE double [RAD_TRAJ_NCOL][total_section_samples]) receives
+ * the sections in (particle, section) order, packed like cols; total_section_samples
+ * must equal sum_i (n_i + n_sections).  entry_energy (HOST double
+ * [n_particles][n_sections]) receives E(k_s), from which the caller forms the
+ * segments' gamma and energy.  Needs n_min >= n_sections.  ws: DEVICE workspace of
+ * rad_traj_sections_workspace_bytes(n_particles, n_sections) bytes.  Synchronises
+ * `stream` (the entry energies are copied to the host).
+ */
+rad_status rad_traj_sections(const rad_traj_params *p, int64_t first, int n_particles, int n_sections,
+                             const double *cols, int64_t total_samples, double *sec_cols,
+                             int64_t total_section_samples, double *entry_energy, void *ws, size_t ws_bytes,
+                             void *stream);
 
 #ifdef __cplusplus
 }

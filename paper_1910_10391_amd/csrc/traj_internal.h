@@ -62,6 +62,23 @@ struct TrajLaunch {
     double *cols;   // [RAD_TRAJ_NCOL][total]
 };
 
+// One section: source samples [k0, k1] of the trajectory at src_off, destination offset.
+struct SecDesc {
+    int64_t src_off, k0, k1, dst_off;
+};
+
+struct SecLaunch {
+    const SecDesc *desc;
+    int n_sec;
+    double g_ref;
+    const double *cols;     // [RAD_TRAJ_NCOL][total]
+    int64_t total;
+    double *sec_cols;       // [RAD_TRAJ_NCOL][sec_total]
+    int64_t sec_total;
+    double *entry_energy;   // [n_sec] (device)
+};
+
 hipError_t launch_traj(const TrajLaunch &L, hipStream_t st);
+hipError_t launch_sections(const SecLaunch &L, hipStream_t st);
 
 }  // namespace radtraj

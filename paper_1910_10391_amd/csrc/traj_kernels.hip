@@ -114,6 +114,37 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
     }
 }
 
+// One block per section: the entry energy, then the columns of samples k0..k1 with dvz
+// and dz re-referenced to the section's own gamma (same operation order as the
+// host-side cut of the CPU generator's trajectories).
+__global__ __launch_bounds__(256) void sections_kernel(SecLaunch L)
+{
+    const SecDesc D = L.desc[blockIdx.x];
+    const double *src = L.cols + D.src_off;
+    double *dst = L.sec_cols + D.dst_off;
+    const double E = src[10 * L.total + D.k0];
+    const double g = E / kMe_eV;
+    const double shift = 0.5 / (g * g) - 0.5 / (L.g_ref * L.g_ref);
+    if (threadIdx.x == 0) L.entry_energy[blockIdx.x] = E;
+    const int64_t n = D.k1 - D.k0 + 1;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        const int64_t i = D.k0 + k;
+#pragma unroll
+        for (int c = 0; c < 11; ++c) {
+            double v = src[c * L.total + i];
+            if (c == 6) v = v + shift;                                 // dvz
+            if (c == 3) v = v + shift * src[i];                        // dz + shift t
+            dst[c * L.sec_total + k] = v;
+        }
+    }
+}
+
+hipError_t launch_sections(const SecLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(sections_kernel, dim3((unsigned)L.n_sec), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
 hipError_t launch_traj(const TrajLaunch &L, hipStream_t st)
 {
     hipLaunchKernelGGL(traj_kernel, dim3((unsigned)((L.n_particles + 63) / 64)), dim3(64), 0, st, L);

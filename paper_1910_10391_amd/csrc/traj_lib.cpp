@@ -112,4 +112,62 @@ rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_part
     return RAD_OK;
 }
 
+size_t rad_traj_sections_workspace_bytes(int n_particles, int n_sections)
+{
+    if (n_particles <= 0 || n_sections <= 0) return 0;
+    return (sizeof(SecDesc) + sizeof(double)) * (size_t)n_particles * (size_t)n_sections;
+}
+
+rad_status rad_traj_sections(const rad_traj_params *p, int64_t first, int n_particles, int n_sections,
+                             const double *cols, int64_t total_samples, double *sec_cols,
+                             int64_t total_section_samples, double *entry_energy, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    rad_status rs = check_params(p);
+    if (rs != RAD_OK) return rs;
+    if (n_particles <= 0 || first < 0 || n_sections <= 0 || !entry_energy)
+        return tfail(RAD_EINVAL, "need n_particles > 0, first >= 0, n_sections > 0, entry_energy");
+    if (p->n_min < n_sections) return tfail(RAD_EINVAL, "n_min (%lld) < n_sections (%d)", (long long)p->n_min, n_sections);
+    const int64_t n_sec = (int64_t)n_particles * n_sections;
+    if (n_sec > (1 << 30)) return tfail(RAD_EINVAL, "too many sections");
+    std::vector<SecDesc> desc((size_t)n_sec);
+    int64_t src = 0, dst = 0;
+    for (int i = 0; i < n_particles; ++i) {
+        Stream r = particle_stream(p->seed, first + i);
+        const int64_t n = draw_steps(*p, r);
+        for (int s = 0; s < n_sections; ++s) {
+            const int64_t k0 = ((int64_t)s * n) / n_sections, k1 = ((int64_t)(s + 1) * n) / n_sections;
+            desc[(size_t)i * n_sections + s] = SecDesc{src, k0, k1, dst};
+            dst += k1 - k0 + 1;
+        }
+        src += n + 1;
+    }
+    if (src != total_samples)
+        return tfail(RAD_EINVAL, "total_samples is %lld, the particles have %lld", (long long)total_samples,
+                     (long long)src);
+    if (dst != total_section_samples)
+        return tfail(RAD_EINVAL, "total_section_samples is %lld, the sections have %lld",
+                     (long long)total_section_samples, (long long)dst);
+    const size_t need = rad_traj_sections_workspace_bytes(n_particles, n_sections);
+    if (ws_bytes < need) return tfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if ((rs = trange(ws, need, "workspace")) != RAD_OK) return rs;
+    if ((rs = trange(cols, (size_t)RAD_TRAJ_NCOL * (size_t)total_samples * sizeof(double), "cols")) != RAD_OK)
+        return rs;
+    if ((rs = trange(sec_cols, (size_t)RAD_TRAJ_NCOL * (size_t)total_section_samples * sizeof(double),
+                     "sec_cols")) != RAD_OK)
+        return rs;
+    hipStream_t st = (hipStream_t)stream;
+    SecDesc *d_desc = (SecDesc *)ws;
+    double *d_energy = (double *)((char *)ws + sizeof(SecDesc) * (size_t)n_sec);
+    hipError_t e = hipMemcpyAsync(d_desc, desc.data(), sizeof(SecDesc) * (size_t)n_sec, hipMemcpyHostToDevice, st);
+    SecLaunch L{d_desc, (int)n_sec, p->energy_eV / kMe_eV, cols, total_samples, sec_cols, total_section_samples,
+                d_energy};
+    if (e == hipSuccess) e = launch_sections(L, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(entry_energy, d_energy, sizeof(double) * (size_t)n_sec, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return tfail(RAD_EDEVICE, "trajectory sections: %s", hipGetErrorString(e));
+    return RAD_OK;
+}
+
 }  // extern "C"

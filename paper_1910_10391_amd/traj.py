@@ -35,6 +35,10 @@ def _lib():
         L.rad_traj_workspace_bytes.argtypes = [I]
         L.rad_traj_generate.restype = I
         L.rad_traj_generate.argtypes = [PP, I64, I, P, I64, P, S, P]
+        L.rad_traj_sections_workspace_bytes.restype = S
+        L.rad_traj_sections_workspace_bytes.argtypes = [I, I]
+        L.rad_traj_sections.restype = I
+        L.rad_traj_sections.argtypes = [PP, I64, I, I, P, I64, P, I64, ctypes.POINTER(ctypes.c_double), P, S, P]
         _bound = True
     return L
 
@@ -58,28 +62,58 @@ def lengths(cfg, n_particles, first=0):
 
 
 class DeviceTrajectories(rad.DeviceSegments):
-    """Trajectories generated on the GPU, one segment per particle (the whole crystal,
-    gamma and energy of the entry), usable wherever rad.DeviceSegments is."""
+    """Trajectories generated on the GPU, usable wherever rad.DeviceSegments is.  With
+    ``cfg.n_sections`` > 1 the segments are the sections (cut on the GPU, each with its
+    entry gamma and energy) and ``out_index`` gives each section's particle; otherwise
+    one segment per particle."""
 
     def __init__(self, cfg, n_particles, first=0, stream=None, device="cuda"):
         import torch
-        if int(getattr(cfg, "n_sections", 1)) != 1:
-            raise ValueError("the GPU generator makes one section per particle")
         p = params(cfg)
         steps = lengths(cfg, n_particles, first)
-        self.n = [int(s) + 1 for s in steps]
-        total = int(sum(self.n))
-        self.data = torch.empty((NCOL, total), dtype=torch.float64, device=device)
+        n_full = [int(s_) + 1 for s_ in steps]
+        total = int(sum(n_full))
+        self.traj_data = torch.empty((NCOL, total), dtype=torch.float64, device=device)
         ws = torch.empty(max(1, int(_lib().rad_traj_workspace_bytes(int(n_particles)))), dtype=torch.uint8,
                          device=device)
-        rad._check(_lib().rad_traj_generate(ctypes.byref(p), int(first), int(n_particles), rad._dptr(self.data),
-                                            total, rad._dptr(ws), ws.numel(), rad._stream(stream)),
-                   "rad_traj_generate")
+        rad._check(_lib().rad_traj_generate(ctypes.byref(p), int(first), int(n_particles),
+                                            rad._dptr(self.traj_data), total, rad._dptr(ws), ws.numel(),
+                                            rad._stream(stream)), "rad_traj_generate")
         self._ws = ws
+        self.traj_n = n_full
+        self.traj_offsets = np.concatenate([[0], np.cumsum(n_full)[:-1]]).astype(np.int64)
+        ns = int(getattr(cfg, "n_sections", 1))
+        me = 0.51099895e6
+        if ns <= 1:
+            self.data = self.traj_data
+            self.n = list(n_full)
+            gammas = [float(cfg.energy_eV) / me] * n_particles
+            energies = [float(cfg.energy_eV)] * n_particles
+            self.out_index = list(range(n_particles))
+        else:
+            sec_n = []
+            for n in steps:
+                n = int(n)
+                sec_n += [((s_ + 1) * n) // ns - (s_ * n) // ns + 1 for s_ in range(ns)]
+            sec_total = int(sum(sec_n))
+            self.data = torch.empty((NCOL, sec_total), dtype=torch.float64, device=device)
+            wss = torch.empty(max(1, int(_lib().rad_traj_sections_workspace_bytes(int(n_particles), ns))),
+                              dtype=torch.uint8, device=device)
+            entry = np.zeros(n_particles * ns)
+            rad._check(_lib().rad_traj_sections(ctypes.byref(p), int(first), int(n_particles), ns,
+                                                rad._dptr(self.traj_data), total, rad._dptr(self.data), sec_total,
+                                                entry.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                rad._dptr(wss), wss.numel(), rad._stream(stream)),
+                       "rad_traj_sections")
+            self.n = sec_n
+            energies = [float(e) for e in entry]
+            gammas = [e / me for e in energies]
+            self.out_index = [i for i in range(n_particles) for _ in range(ns)]
+        self.entry_energy = np.array(energies)
+        total_seg = int(sum(self.n))
         base = self.data.data_ptr()
-        row = total * 8
-        gamma = float(cfg.energy_eV) / (0.51099895e6)
-        self.structs = (rad.Segment * n_particles)()
+        row = total_seg * 8
+        self.structs = (rad.Segment * len(self.n))()
         off = 0
         for k, n in enumerate(self.n):
             st = self.structs[k]
@@ -87,13 +121,21 @@ class DeviceTrajectories(rad.DeviceSegments):
             for i, c in enumerate(rad.COLUMNS):
                 setattr(st, c, base + i * row + off * 8)
             st.w = None
-            st.gamma = gamma
-            st.energy_eV = float(cfg.energy_eV)
+            st.gamma = gammas[k]
+            st.energy_eV = energies[k]
             off += n
         self.offsets = np.concatenate([[0], np.cumsum(self.n)[:-1]]).astype(np.int64)
 
     def host(self, i):
-        """Particle i as a dict of host arrays (the columns of the generator)."""
-        o, n = int(self.offsets[i]), self.n[i]
-        a = self.data[:, o:o + n].cpu().numpy()
+        """Particle i's whole trajectory as a dict of host arrays (the generator's columns)."""
+        o, n = int(self.traj_offsets[i]), self.traj_n[i]
+        a = self.traj_data[:, o:o + n].cpu().numpy()
         return {c: a[j].copy() for j, c in enumerate(COLUMNS)}
+
+    def segment_host(self, j):
+        """Segment j (a section, or a whole trajectory) as a dict of host arrays."""
+        o, n = int(self.offsets[j]), self.n[j]
+        a = self.data[:, o:o + n].cpu().numpy()
+        d = {c: a[k].copy() for k, c in enumerate(COLUMNS)}
+        d.update(gamma=float(self.structs[j].gamma), energy_eV=float(self.structs[j].energy_eV), w=None)
+        return d

@@ -125,3 +125,36 @@ def test_spectrum_of_gpu_trajectories_matches_oracle(T):
               "generator's)" % (i, err, err_cpu), flush=True)
         assert err < 1e-9
         assert err_cpu < 1e-6
+
+
+def test_sections_match_cpu_cut(T):
+    """Sections cut on the GPU (entry gamma per section, dz and dvz re-referenced)
+    against the CPU cut of the CPU generator's trajectories; then the incoherent
+    section sum of the spectrum against the oracle on the GPU's own sections."""
+    from paper_1910_10391_amd import rad
+    cfg = dataclasses.replace(presets.electron_50gev_config(seed=6), length_m=40e-6, n_min=3000, n_max=7000)
+    assert cfg.n_sections == 10
+    dt = T.DeviceTrajectories(cfg, 3, first=2)
+    assert dt.out_index == [i for i in range(3) for _ in range(10)]
+    assert len(dt.n) == 30
+    for i in range(3):
+        cpu_secs = channeling.sections(cfg, channeling.trajectory(cfg, 2 + i))
+        assert len(cpu_secs) == 10
+        for s in range(10):
+            g = dt.segment_host(10 * i + s)
+            c = cpu_secs[s]
+            assert g["t"].size == c["t"].size
+            assert abs(g["gamma"] / c["gamma"] - 1.0) < 1e-9 and abs(g["energy_eV"] / c["energy_eV"] - 1.0) < 1e-9
+            c = dict(c, energy=np.zeros_like(c["t"]))
+            g["energy"] = np.zeros_like(g["t"])
+            _compare(g, c, 1e-11, "particle %d section %d" % (i, s), d=cfg.d_m)
+    g0 = cfg.energy_eV / oracle.ME_EV
+    hw = analytic.log_omega(21, 1e6, 20e9)
+    th = analytic.cell_centred(5, 4.0 / g0)
+    grid = rad.Grid(hw, th, th)
+    got = rad.batch(grid, dt, dt.out_index, 3, rad.SPINHALF, rad.FP64).cpu().numpy()[:, 0]
+    segs = [dt.segment_host(j) for j in range(30)]
+    ref = oracle.batch(segs, dt.out_index, 3, hw, th, th, oracle.KIND_SPINHALF)[:, 0]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print("sections spectrum: M1 %.2e" % err, flush=True)
+    assert err < 1e-9

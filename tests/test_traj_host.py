@@ -42,3 +42,25 @@ def test_generate_rejects_wrong_total_before_any_device_call(T):
     st = L.rad_traj_generate(ctypes.byref(p), 0, 4, None, 12345, None, 0, None)
     assert st == 1
     assert b"total_samples" in rad.lib().rad_last_error()
+
+
+def test_sections_validation_before_any_device_call(T):
+    from paper_1910_10391_amd import rad
+    import numpy as np
+    cfg = dataclasses.replace(presets.electron_50gev_config(), n_min=5, n_max=9)
+    p = T.params(cfg)
+    L = T._lib()
+    e = np.zeros(40)
+    D = ctypes.POINTER(ctypes.c_double)
+    # n_min below the section count
+    assert L.rad_traj_sections(ctypes.byref(p), 0, 4, 10, None, 0, None, 0, e.ctypes.data_as(D), None, 0, None) == 1
+    assert b"n_sections" in rad.lib().rad_last_error()
+    # wrong totals
+    n = T.lengths(cfg, 4)
+    total = int((n + 1).sum())
+    assert L.rad_traj_sections(ctypes.byref(p), 0, 4, 5, None, total + 1, None, 0, e.ctypes.data_as(D), None, 0,
+                               None) == 1
+    assert L.rad_traj_sections(ctypes.byref(p), 0, 4, 5, None, total, None, 7, e.ctypes.data_as(D), None, 0,
+                               None) == 1
+    assert b"total_section_samples" in rad.lib().rad_last_error()
+    assert L.rad_traj_sections_workspace_bytes(4, 5) == 40 * 20
