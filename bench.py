@@ -15,6 +15,7 @@ CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -336,6 +337,17 @@ def bench_traj(args):
     }
 
 
+def _finite(o):
+    """JSON-safe copy: non-finite floats become None."""
+    if isinstance(o, dict):
+        return {k: _finite(v) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_finite(v) for v in o]
+    if isinstance(o, float) and not math.isfinite(o):
+        return None
+    return o
+
+
 def bench_sampler(args):
     """The learned angular sampler on held-out positron trajectories: train (spectra
     computed by the library, BF16 MLP on the GPU), tune tau on validation trajectories,
@@ -348,7 +360,7 @@ def bench_sampler(args):
         rep = train_sampler.main(["--report", os.path.join(d, "r.json"), "--test", str(args.particles or 64)])
     t = rep["test"]
     L = t["learned"]
-    return {
+    return _finite({
         "metric": METRIC, "value": L["evals_full"] / L["seconds"], "unit": "evals/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": L["seconds"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16", "data": "synthetic",
@@ -356,10 +368,11 @@ def bench_sampler(args):
                                "64x64 within 5/gamma, 8x8 cells; network trained on %d x 64 spectra"
                                % (rep["config"]["particles_test"], rep["config"]["particles_train"])},
         "speedup_vs_full_grid": L["speedup_vs_full"], "max_rel_err": L["max_rel_err"],
-        "accepted_1pct": rep["accepted"], "tau": rep["tau"], "evals_frac": L["evals_frac"],
+        "accepted_1pct": rep["accepted"], "tau": rep["tau"], "fill": rep.get("fill"), "evals_frac": L["evals_frac"],
         "coarse_guided": t["coarse"], "coarse_only": t["coarse_only"],
         "full_grid_s": t["full_grid_seconds"], "training_s": rep.get("training_seconds"),
-    }
+        "coverage": rep.get("coverage"),
+    })
 
 
 def sample_points(segs, grid):

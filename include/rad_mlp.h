@@ -80,6 +80,16 @@ rad_status rad_mlp_adam(rad_mlp *mlp, const float *grad, float lr, float beta1, 
 rad_status rad_mlp_forward(const rad_mlp *mlp, const float *feat, int n_traj, const int *traj, const float *x,
                            int batch, float *y, void *ws, size_t ws_bytes, void *stream);
 
+/* Inference over every (trajectory, point) pair without per-point inputs: x (DEVICE
+ * float [n_pts][n_point]) is one table of point inputs shared by all trajectories, y
+ * (DEVICE float [n_traj][n_pts]) receives the output of trajectory t at point i in
+ * y[t * n_pts + i].  Needs n_point <= 8 (the fused kernel; RAD_EUNSUPPORTED
+ * otherwise); ws: DEVICE workspace of rad_mlp_grid_workspace_bytes(mlp, n_traj)
+ * bytes (the folded biases). */
+size_t rad_mlp_grid_workspace_bytes(const rad_mlp *mlp, int n_traj);
+rad_status rad_mlp_forward_grid(const rad_mlp *mlp, const float *feat, int n_traj, const float *x, int64_t n_pts,
+                                float *y, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

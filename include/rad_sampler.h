@@ -6,9 +6,9 @@
  * (rad_batch on a coarse grid), (2) the MLP's predicted log intensity at every
  * fine direction (include/rad_mlp.h), (3) exact cell integrals on the cells the
  * prediction selects (rad_cells in include/rad.h); cells left out count as their
- * centre value times their area.  A mismatch between the predicted and the
- * coarse angle-integrated intensity makes a photon energy fall back to the full
- * grid, the exact reference.  Conventions as in rad.h.
+ * predicted mass or their centre value times their area.  A prediction that
+ * disagrees with the exact centre values makes a photon energy fall back to the
+ * full grid, the exact reference.  Conventions as in rad.h.
  */
 #ifndef RAD_SAMPLER_H
 #define RAD_SAMPLER_H
@@ -22,46 +22,56 @@
 extern "C" {
 #endif
 
-#define RAD_N_FEATURES 34
+#define RAD_N_FEATURES 38
 
 /*
  * Trajectory features for the network, one row of RAD_N_FEATURES floats per
- * segment (DEVICE feat [n_segs][34]): log(gamma / 1e4); a 32-bin histogram, over
+ * segment (DEVICE feat [n_segs][38]): log(gamma / 1e4); a 32-bin histogram, over
  * [0, d/2] with d = plane_spacing_m, of the transverse oscillation amplitudes
  * (half the distance between consecutive sign changes of v_x; amplitudes >= d/2,
- * over-barrier motion, fall in the last bin), normalised to sum 1; and
+ * over-barrier motion, fall in the last bin), normalised to sum 1;
  * log(omega_osc / 1e5 m^-1) with omega_osc = pi (sign changes of v_x) / (t_end -
- * t_0).  Uses only t, x, vx, n and gamma of each segment.  ws: DEVICE workspace of
- * at least n_segs * 40 bytes.  Synchronises `stream` (one upload).
+ * t_0); and the direction of motion in units of 1/gamma: gamma mean(v_x),
+ * gamma mean(v_y), gamma std(v_x), gamma std(v_y) over the samples.  Uses t, x,
+ * vx, vy, n and gamma of each segment.  ws: DEVICE workspace of at least
+ * n_segs * 48 bytes.  Synchronises `stream` (one upload).
  */
 rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacing_m, float *feat, void *ws,
                         size_t ws_bytes, void *stream);
 
 /*
  * Cell selection per (trajectory, photon energy) of the fine grid `fine`:
- * pred (DEVICE float [n_traj][n_w][n_y][n_x]) is the network's output, the log
- * intensity being mu + sigma * pred; coarse (DEVICE double [n_traj][n_w][n_cells])
- * the exact spectrum at the cell centres.  Writes mask (DEVICE uint8
- * [n_traj][n_w][n_cells]) and fallback (DEVICE uint8 [n_traj][n_w]):
- * fallback = |M_pred / M_coarse - 1| > tau (or M_coarse = 0), then every cell is
- * selected; otherwise cells are taken in decreasing predicted mass while the
- * predicted mass before them is below coverage * M_pred, at most `cap` cells.
- * The selection is then widened to whole blocks of 64 photon energies (w / 64):
- * a cell selected for one energy of a block is selected for all of them, since
- * rad_cells evaluates a cell for a whole block at the cost of one.
- * Needs n_cells = (n_x/cx)(n_y/cy) <= 64.
+ * pred (DEVICE float [n_traj][n_w][n_y][n_x]) is the network's output, the
+ * predicted angular shape being exp(mu + sigma * pred) up to a scale; coarse
+ * (DEVICE double [n_traj][n_w][n_cells]) the exact spectrum at the cell centres.
+ * The predicted centre value P_c of a cell is the mean predicted value of the fine
+ * directions nearest its centre (the central 2 x 2 of an even cell); the scale is
+ * lambda = sum_c coarse_c A_c / sum_c P_c A_c (A_c the cell area).  Check: the
+ * energy falls back to the full grid (every cell selected) when
+ * sum_c |lambda P_c - coarse_c| A_c > tau * sum_c coarse_c A_c, or a sum is 0.
+ * Otherwise cells are taken in decreasing predicted mass (lambda times the sum over
+ * the cell's fine directions of the predicted value x dthx dthy) while the predicted
+ * mass before them is below coverage * the total, at most `cap` cells.  The
+ * selection is then widened to whole blocks of 64 photon energies (w / 64): a cell
+ * selected for one energy of a block is selected for all of them, since rad_cells
+ * evaluates a cell for a whole block at the cost of one.  Writes mask (DEVICE uint8
+ * [n_traj][n_w][n_cells]), fallback (DEVICE uint8 [n_traj][n_w]) and, if cell_pred
+ * is not NULL, the scaled predicted cell masses (DEVICE double
+ * [n_traj][n_w][n_cells]).  Needs n_cells = (n_x/cx)(n_y/cy) <= 64.
  */
 rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
                               const double *coarse, int cx, int cy, float coverage, int cap, float tau,
-                              uint8_t *mask, uint8_t *fallback, void *stream);
+                              uint8_t *mask, uint8_t *fallback, double *cell_pred, void *stream);
 
 /*
  * dIdw (DEVICE double [n_traj][n_w]) = sum over cells of the exact cell integral
- * (cells, DEVICE [n_traj][n_w][n_cells], from rad_cells) where mask is set, else
- * the coarse centre value times the cell's area.
+ * (cells, DEVICE [n_traj][n_w][n_cells], from rad_cells) where mask is set; else
+ * the predicted cell mass (cell_pred from rad_sampler_select) if cell_pred is not
+ * NULL, else the coarse centre value times the cell's area.
  */
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
-                               const uint8_t *mask, const double *coarse, double *dIdw, void *stream);
+                               const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,
+                               void *stream);
 
 #ifdef __cplusplus
 }

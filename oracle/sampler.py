@@ -6,7 +6,8 @@ Plain NumPy loops over the definitions:
 * ``features``  -- trajectory features: log(gamma/1e4); the histogram of the
                    transverse oscillation amplitudes over [0, d/2] (32 bins,
                    amplitudes at or above d/2 in the last bin), normalised to
-                   sum 1; log(omega_osc / 1e5 m^-1).  A turning point is a sign
+                   sum 1; log(omega_osc / 1e5 m^-1); gamma times the mean and the
+                   standard deviation of v_x and of v_y over the samples.  A turning point is a sign
                    change of v_x between samples k and k+1 (v_x >= 0 counts as
                    positive), located at x[k+1]; an amplitude is half the
                    distance between consecutive turning points; omega_osc is pi
@@ -15,13 +16,18 @@ Plain NumPy loops over the definitions:
                    the total excursion of x.  Only the first 4096 turning points
                    enter the histogram, stored in single precision (the
                    kernel's bounded buffer); the count for omega_osc is total.
-* ``select``    -- cells in decreasing predicted mass while the predicted mass
-                   ahead of a cell is below coverage x the total, at most ``cap``
-                   cells; every cell when |M_pred/M_coarse - 1| > tau or
-                   M_coarse is not positive; then widened to whole blocks of 64
-                   photon energies.
-* ``combine``   -- exact cell integrals where selected, coarse centre value x
-                   cell area elsewhere.
+* ``select``    -- the prediction gives the angular shape; its scale lambda is
+                   fitted to the exact centre values (ratio of the area-weighted
+                   sums of exact and predicted centre values, the predicted centre
+                   value being the mean predicted intensity of the fine directions
+                   nearest the centre).  Every cell is selected when the scaled
+                   centre values deviate from the exact ones by more than tau in
+                   area-weighted relative L1 norm (or a sum is zero); otherwise
+                   cells in decreasing (scaled) predicted mass while the mass ahead
+                   of a cell is below coverage x the total, at most ``cap`` cells;
+                   then widened to whole blocks of 64 photon energies.
+* ``combine``   -- exact cell integrals where selected; elsewhere the predicted
+                   cell mass, or the coarse centre value x cell area.
 
 These steps are the sampler's bookkeeping around the radiation integrals of
 Sec. II (the integrals themselves are the direct-sum oracle in ``oracle``); the
@@ -34,12 +40,13 @@ from __future__ import annotations
 import numpy as np
 
 HIST_BINS = 32
+N_FEATURES = HIST_BINS + 6
 MAX_TURNING = 4096
 WBLOCK = 64
 
 
-def features(t, x, vx, gamma, plane_spacing):
-    """34 features of one trajectory (FP64, as defined in the module docstring)."""
+def features(t, x, vx, vy, gamma, plane_spacing):
+    """38 features of one trajectory (FP64, as defined in the module docstring)."""
     t = np.asarray(t, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     vx = np.asarray(vx, dtype=np.float64)
@@ -57,10 +64,15 @@ def features(t, x, vx, gamma, plane_spacing):
         hist[min(max(b, 0), HIST_BINS - 1)] += 1.0
     span = t[-1] - t[0]
     w_osc = np.pi * total / span if span > 0 else 0.0
-    out = np.empty(2 + HIST_BINS)
+    vy = np.asarray(vy, dtype=np.float64)
+    out = np.empty(N_FEATURES)
     out[0] = np.log(gamma / 1e4)
     out[1:1 + HIST_BINS] = hist / len(amps)
-    out[-1] = np.log(max(w_osc, 1.0) / 1e5)
+    out[1 + HIST_BINS] = np.log(max(w_osc, 1.0) / 1e5)
+    out[2 + HIST_BINS] = gamma * vx.mean()
+    out[3 + HIST_BINS] = gamma * vy.mean()
+    out[4 + HIST_BINS] = gamma * vx.std()
+    out[5 + HIST_BINS] = gamma * vy.std()
     return out
 
 
@@ -83,22 +95,47 @@ def cell_areas(wx, wy, cx, cy):
     return cell_sums(np.ones((len(wy), len(wx))), wx, wy, cx, cy)
 
 
+def centre_values(values, cx, cy):
+    """Mean of values[..., y, x] over the fine directions nearest each cell centre (the
+    central 2 x 2 of an even cell, the middle point of an odd one) -> [..., n_cells]."""
+    v = np.asarray(values, dtype=np.float64)
+    ny, nx = v.shape[-2:]
+    ncx, ncy = nx // cx, ny // cy
+    xs = sorted({(cx - 1) // 2, cx // 2})
+    ys = sorted({(cy - 1) // 2, cy // 2})
+    out = np.zeros(v.shape[:-2] + (ncx * ncy,))
+    for cj in range(ncy):
+        for ci in range(ncx):
+            pts = [v[..., cj * cy + y, ci * cx + x] for y in ys for x in xs]
+            out[..., cj * ncx + ci] = sum(pts) / len(pts)
+    return out
+
+
 def select(pred, mu, sigma, coarse, wx, wy, cx, cy, coverage, cap, tau):
-    """Selection mask [n_traj, n_w, n_cells] (uint8) and fallback flags [n_traj, n_w]."""
+    """Selection mask [n_traj, n_w, n_cells] (uint8), fallback flags [n_traj, n_w] and the
+    scaled predicted cell masses [n_traj, n_w, n_cells]."""
     pred = np.asarray(pred, dtype=np.float64)
     n_traj, n_w = pred.shape[:2]
-    pm = cell_sums(np.exp(mu + sigma * pred), wx, wy, cx, cy)
-    cm = np.asarray(coarse, dtype=np.float64) * cell_areas(wx, wy, cx, cy)
+    intensity = np.exp(mu + sigma * pred)
+    pm = cell_sums(intensity, wx, wy, cx, cy)
+    pc = centre_values(intensity, cx, cy)
+    area = cell_areas(wx, wy, cx, cy)
+    coarse = np.asarray(coarse, dtype=np.float64)
     n_cells = pm.shape[-1]
     mask = np.zeros((n_traj, n_w, n_cells), dtype=np.uint8)
     fb = np.zeros((n_traj, n_w), dtype=np.uint8)
     for s in range(n_traj):
         for w in range(n_w):
-            Mp, Mc = pm[s, w].sum(), cm[s, w].sum()
-            if not Mc > 0 or abs(Mp / Mc - 1.0) > tau:
+            C = (coarse[s, w] * area).sum()
+            P = (pc[s, w] * area).sum()
+            lam = C / P if P > 0 else 0.0
+            pm[s, w] *= lam
+            D = (np.abs(lam * pc[s, w] - coarse[s, w]) * area).sum()
+            if not C > 0 or not P > 0 or D > tau * C:
                 fb[s, w] = 1
                 mask[s, w, :] = 1
                 continue
+            Mp = pm[s, w].sum()
             order = sorted(range(n_cells), key=lambda c: (-pm[s, w, c], c))
             ahead = 0.0
             for r, c in enumerate(order):
@@ -109,11 +146,12 @@ def select(pred, mu, sigma, coarse, wx, wy, cx, cy, coverage, cap, tau):
     for b0 in range(0, n_w, WBLOCK):
         blk = mask[:, b0:b0 + WBLOCK, :]
         mask[:, b0:b0 + WBLOCK, :] = np.repeat(blk.max(axis=1, keepdims=True), blk.shape[1], axis=1)
-    return mask, fb
+    return mask, fb, pm
 
 
-def combine(cells, mask, coarse, wx, wy, cx, cy):
-    """dI/dhw [n_traj, n_w]."""
-    area = cell_areas(wx, wy, cx, cy)
-    per = np.where(np.asarray(mask) > 0, cells, np.asarray(coarse) * area)
+def combine(cells, mask, coarse, wx, wy, cx, cy, cell_pred=None):
+    """dI/dhw [n_traj, n_w]: exact cells where selected, else the predicted cell mass
+    (``cell_pred``) or the coarse centre value x area."""
+    other = cell_pred if cell_pred is not None else np.asarray(coarse) * cell_areas(wx, wy, cx, cy)
+    per = np.where(np.asarray(mask) > 0, cells, other)
     return per.sum(axis=-1)

@@ -48,9 +48,11 @@ hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n
 hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uint16_t *W2, uint16_t *W2T,
                           uint16_t *W3, uint16_t *W3T, uint16_t *W3P, uint16_t *W4, hipStream_t st);
 // Fused inference (n_point <= 8): y for B points, cb from fold_bias; one block per CU.
+// traj null: grid form, point m is (trajectory m / n_pts, point m % n_pts of x).
 constexpr int kFusedMaxPointHost = 8;
 hipError_t launch_infer_fused(const uint16_t *W1p, const uint16_t *W2, const uint16_t *W3P, const uint16_t *W4,
                               const float *cb, const float *b2, const float *b3, const float *b4, const int *traj,
-                              const float *x, int nf, int np, int B, float *y, int n_cu, hipStream_t st);
+                              const float *x, int nf, int np, int64_t B, int64_t n_pts, float *y, int n_cu,
+                              hipStream_t st);
 
 }  // namespace radmlp

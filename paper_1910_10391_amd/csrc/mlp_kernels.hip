@@ -292,9 +292,11 @@ constexpr int kFusedMaxPoint = 8;
 struct FusedArgs {
     const uint16_t *W1p, *W2, *W3P, *W4;
     const float *cb, *b2, *b3, *b4;
-    const int *traj;
-    const float *x;
-    int nf, np, B;
+    const int *traj;    // per-point trajectory, or null for the grid form
+    const float *x;     // [B][np], or the point table [n_pts][np] of the grid form
+    int nf, np;
+    int64_t B;          // points (grid form: n_traj * n_pts, point m = (m / n_pts, m % n_pts))
+    int64_t n_pts;
     float *y;
 };
 
@@ -326,14 +328,22 @@ __global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
     }
     __syncthreads();
     const int r = lane & 31, hs = lane >> 5;
-    const int n_tiles = (a.B + 31) / 32;
-    for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
-        const int pt = tile * 32 + r;
-        const int pc = pt < a.B ? pt : a.B - 1;      // padding lanes recompute the last point
-        const float *cbt = a.cb + (size_t)a.traj[pc] * kWidth;
+    const int64_t n_tiles = (a.B + 31) / 32;
+    for (int64_t tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t pt = tile * 32 + r;
+        const int64_t pc = pt < a.B ? pt : a.B - 1;      // padding lanes recompute the last point
+        int64_t t, xi;
+        if (a.traj) {
+            t = a.traj[pc];
+            xi = pc;
+        } else {
+            t = pc / a.n_pts;
+            xi = pc - t * a.n_pts;
+        }
+        const float *cbt = a.cb + (size_t)t * kWidth;
         float xv[kFusedMaxPoint];
 #pragma unroll
-        for (int j = 0; j < kFusedMaxPoint; ++j) xv[j] = j < a.np ? bf2f(f2bf(a.x[(size_t)pc * a.np + j])) : 0.0f;
+        for (int j = 0; j < kFusedMaxPoint; ++j) xv[j] = j < a.np ? bf2f(f2bf(a.x[(size_t)xi * a.np + j])) : 0.0f;
         // layer 1: units ks*16 + 8 hs + j of this lane's point, in operand layout
         bf16x8 h1[kWidth / 16];
 #pragma unroll
@@ -492,12 +502,13 @@ hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uin
 
 hipError_t launch_infer_fused(const uint16_t *W1p, const uint16_t *W2, const uint16_t *W3P, const uint16_t *W4,
                               const float *cb, const float *b2, const float *b3, const float *b4, const int *traj,
-                              const float *x, int nf, int np, int B, float *y, int n_cu, hipStream_t st)
+                              const float *x, int nf, int np, int64_t B, int64_t n_pts, float *y, int n_cu,
+                              hipStream_t st)
 {
-    if (np > kFusedMaxPoint || np < 1 || B < 1) return hipErrorInvalidValue;
-    FusedArgs a{W1p, W2, W3P, W4, cb, b2, b3, b4, traj, x, nf, np, B, y};
-    const int tiles = (B + 31) / 32;
-    const int blocks = std::max(1, std::min(n_cu, (tiles + 3) / 4));
+    if (np > kFusedMaxPoint || np < 1 || B < 1 || (!traj && n_pts < 1)) return hipErrorInvalidValue;
+    FusedArgs a{W1p, W2, W3P, W4, cb, b2, b3, b4, traj, x, nf, np, B, n_pts, y};
+    const int64_t tiles = (B + 31) / 32;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (tiles + 3) / 4));
     hipLaunchKernelGGL(infer_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }

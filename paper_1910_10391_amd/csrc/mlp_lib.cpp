@@ -402,7 +402,7 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
     if (fused_ok(m)) {
         if (e == hipSuccess)
             e = launch_infer_fused(m->W1p, m->W2, m->W3P, m->W4, w.cb, m->p + L.b2, m->p + L.b3, m->p + L.b4, traj, x,
-                                   L.n_feat, L.n_point, batch, y, m->n_cu, st);
+                                   L.n_feat, L.n_point, batch, 0, y, m->n_cu, st);
         return e == hipSuccess ? RAD_OK : mhip(e, "MLP forward");
     }
     if (e == hipSuccess) e = launch_layer1_points(m->W1p, w.cb, L.n_feat, traj, x, L.n_point, batch, Bp, w.h1, st);
@@ -415,6 +415,37 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
                           nullptr, st);
     if (e == hipSuccess) e = hipMemcpyAsync(y, w.y, (size_t)batch * 4, hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? RAD_OK : mhip(e, "MLP forward");
+}
+
+size_t rad_mlp_grid_workspace_bytes(const rad_mlp *m, int n_traj)
+{
+    if (!m || n_traj < 1) return 0;
+    return carve_infer(nullptr, 0, n_traj, true).total;
+}
+
+rad_status rad_mlp_forward_grid(const rad_mlp *m, const float *feat, int n_traj, const float *x, int64_t n_pts,
+                                float *y, void *ws, size_t ws_bytes, void *stream)
+{
+    rad_status rs = check_mlp(m);
+    if (rs != RAD_OK) return rs;
+    if (!fused_ok(m)) return mfail(RAD_EUNSUPPORTED, "the grid form needs n_point <= %d", kFusedMaxPointHost);
+    if (n_traj < 1 || n_pts < 1) return mfail(RAD_EINVAL, "need n_traj >= 1 and n_pts >= 1");
+    const int64_t B = (int64_t)n_traj * n_pts;
+    if (B > ((int64_t)1 << 40)) return mfail(RAD_EINVAL, "too many points");
+    const size_t need = rad_mlp_grid_workspace_bytes(m, n_traj);
+    if (ws_bytes < need) return mfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if ((rs = check_range(ws, need, "workspace")) != RAD_OK) return rs;
+    if (m->L.n_feat > 0 && (rs = check_range(feat, (size_t)n_traj * m->L.n_feat * 4, "feat")) != RAD_OK) return rs;
+    if ((rs = check_range(x, (size_t)n_pts * m->L.n_point * 4, "x")) != RAD_OK) return rs;
+    if ((rs = check_range(y, (size_t)B * 4, "y")) != RAD_OK) return rs;
+    const MWs w = carve_infer((char *)ws, 0, n_traj, true);
+    const MlpLayout &L = m->L;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_fold_bias(m->W1p, m->p + L.b1, feat, L.n_feat, n_traj, w.cb, st);
+    if (e == hipSuccess)
+        e = launch_infer_fused(m->W1p, m->W2, m->W3P, m->W4, w.cb, m->p + L.b2, m->p + L.b3, m->p + L.b4, nullptr,
+                               x, L.n_feat, L.n_point, B, n_pts, y, m->n_cu, st);
+    return e == hipSuccess ? RAD_OK : mhip(e, "MLP grid forward");
 }
 
 }  // extern "C"

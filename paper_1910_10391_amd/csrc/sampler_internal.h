@@ -7,13 +7,13 @@
 namespace radsmp {
 
 constexpr int kHistBins = 32;
-constexpr int kFeatures = 2 + kHistBins;   // log gamma, histogram, log omega_osc
+constexpr int kFeatures = 6 + kHistBins;   // log gamma, histogram, log omega_osc, 4 direction moments
 constexpr int kMaxTurning = 4096;           // turning points kept per trajectory
 constexpr int kWBlock = 64;                 // photon energies rad_cells evaluates together
 constexpr double kPi = 3.14159265358979323846;
 
 struct FeatSeg {
-    const double *t, *x, *vx;
+    const double *t, *x, *vx, *vy;
     int64_t n;
     double gamma;
 };
@@ -34,10 +34,12 @@ struct SelectLaunch {
     int cap;
     uint8_t *mask;         // [n_traj][n_w][n_cells]
     uint8_t *fallback;     // [n_traj][n_w]
+    double *cell_pred;     // [n_traj][n_w][n_cells] predicted cell masses, or null
 };
 
 struct CombineLaunch {
     const double *cells, *coarse, *wx, *wy;
+    const double *cell_pred;   // null: unselected cells count as centre value x area
     const uint8_t *mask;
     int n_traj, n_w, n_x, cx, cy, n_cells;
     double *out;           // [n_traj][n_w]

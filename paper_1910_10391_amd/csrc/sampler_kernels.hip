@@ -15,12 +15,15 @@ namespace radsmp {
 // over [0, d/2] (amplitudes >= d/2, over-barrier motion, fall in the last bin),
 // normalised to sum 1 (with fewer than two turning points the only entry is half
 // the total x excursion); log(omega_osc / 1e5 m^-1) with
-// omega_osc = pi (number of sign changes) / (t_end - t_0).
+// omega_osc = pi (number of sign changes) / (t_end - t_0); and the direction of
+// motion in units of 1/gamma: gamma mean(v_x), gamma mean(v_y), gamma std(v_x),
+// gamma std(v_y) over the samples (the radiation cone follows the direction).
 __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
 {
     __shared__ int s_cnt[256];
     __shared__ float s_tp[kMaxTurning];
     __shared__ double s_min[256], s_max[256];
+    __shared__ double s_mom[4][256];
     const FeatSeg &S = F.segs[blockIdx.x];
     const int64_t n = S.n;
     const int tid = threadIdx.x;
@@ -32,15 +35,22 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
         const bool a = S.vx[k] >= 0.0, b = S.vx[k + 1] >= 0.0;
         cnt += (a != b);
     }
+    double m[4] = {0.0, 0.0, 0.0, 0.0};   // sums of vx, vy, vx^2, vy^2
     for (int64_t k = tid; k < n; k += 256) {
         xmn = fmin(xmn, S.x[k]);
         xmx = fmax(xmx, S.x[k]);
+        const double vx = S.vx[k], vy = S.vy[k];
+        m[0] += vx;
+        m[1] += vy;
+        m[2] += vx * vx;
+        m[3] += vy * vy;
     }
     s_cnt[tid] = cnt;
     s_min[tid] = xmn;
     s_max[tid] = xmx;
+    for (int j = 0; j < 4; ++j) s_mom[j][tid] = m[j];
     __syncthreads();
-    // exclusive prefix of the counts (in chunk order = time order) and the extrema
+    // exclusive prefix of the counts (in chunk order = time order), extrema, moments
     if (tid == 0) {
         int acc = 0;
         for (int i = 0; i < 256; ++i) {
@@ -55,6 +65,11 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
         }
         s_min[0] = a;
         s_max[0] = b;
+        for (int j = 0; j < 4; ++j) {
+            double t = 0.0;
+            for (int i = 0; i < 256; ++i) t += s_mom[j][i];
+            s_mom[j][0] = t;
+        }
     }
     __syncthreads();
     int o = s_cnt[tid];
@@ -91,16 +106,26 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
     const double span = S.t[n - 1] - S.t[0];
     const double w_osc = span > 0.0 ? kPi * (double)total / span : 0.0;
     f[1 + kHistBins] = (float)log(fmax(w_osc, 1.0) / 1e5);
+    const double mx = s_mom[0][0] / (double)n, my = s_mom[1][0] / (double)n;
+    const double vxx = fmax(s_mom[2][0] / (double)n - mx * mx, 0.0), vyy = fmax(s_mom[3][0] / (double)n - my * my, 0.0);
+    f[2 + kHistBins] = (float)(S.gamma * mx);
+    f[3 + kHistBins] = (float)(S.gamma * my);
+    f[4 + kHistBins] = (float)(S.gamma * sqrt(vxx));
+    f[5 + kHistBins] = (float)(S.gamma * sqrt(vyy));
 }
 
 // ---------------------------------------------------------------- selection
-// One wave per (trajectory, photon energy); lane c < n_cells owns cell c.
-// Predicted cell mass: sum over the cell's fine directions of
-// exp(mu + sigma * yhat) dthx dthy.  Coarse cell mass: the exact spectrum at the
-// cell centre times the cell's area.  Fallback (every cell refined) when
-// |M_pred / M_coarse - 1| > tau.  Otherwise cells are taken in decreasing
-// predicted mass (ties by index) while the mass before them is below
-// coverage * M_pred, at most `cap` of them.
+// One wave per (trajectory, photon energy); lane c < n_cells owns cell c.  The
+// network predicts the angular shape, exp(mu + sigma * yhat) up to a scale; the
+// scale lambda comes from the exact spectrum at the cell centres C_c:
+// lambda = sum_c C_c A_c / sum_c P_c A_c, with P_c the mean predicted value of the
+// fine directions nearest the centre (the central 2 x 2 of an even cell, the middle
+// point of an odd one) and A_c the cell area.  Check: the energy falls back to the
+// full grid (every cell selected) when sum_c |lambda P_c - C_c| A_c exceeds
+// tau sum_c C_c A_c (or either sum is 0).  Otherwise cells are taken in decreasing
+// predicted mass (lambda times the sum over the cell's fine directions of the
+// predicted value times dthx dthy; ties by index) while the mass before them is
+// below coverage times the total, at most `cap` of them.
 __global__ __launch_bounds__(256) void select_kernel(SelectLaunch L)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -109,25 +134,41 @@ __global__ __launch_bounds__(256) void select_kernel(SelectLaunch L)
     const int ncx = L.n_x / L.cx;
     const int c = lane;
     const bool live = c < L.n_cells;
-    double pm = 0.0, cm = 0.0, area = 0.0;
+    double pm = 0.0, pc = 0.0, cc = 0.0, area = 0.0;
     if (live) {
         const int ci = c % ncx, cj = c / ncx;
         const float *pred = L.pred + item * (int64_t)L.n_x * L.n_y;
+        const int xa = (L.cx - 1) / 2, xb = L.cx / 2, ya = (L.cy - 1) / 2, yb = L.cy / 2;
+        int npc = 0;
         for (int jy = 0; jy < L.cy; ++jy)
             for (int jx = 0; jx < L.cx; ++jx) {
                 const int gx = ci * L.cx + jx, gy = cj * L.cy + jy;
+                const double v = exp((double)L.mu + (double)L.sigma * (double)pred[(int64_t)gy * L.n_x + gx]);
                 const double dA = L.wx[gx] * L.wy[gy];
-                pm += exp((double)L.mu + (double)L.sigma * (double)pred[(int64_t)gy * L.n_x + gx]) * dA;
+                pm += v * dA;
                 area += dA;
+                if ((jx == xa || jx == xb) && (jy == ya || jy == yb)) {
+                    pc += v;
+                    ++npc;
+                }
             }
-        cm = L.coarse[item * L.n_cells + c] * area;
+        pc /= (double)npc;
+        cc = L.coarse[item * L.n_cells + c];
     }
-    double Mp = pm, Mc = cm;
+    double P = pc * area, C = cc * area;
     for (int off = 32; off > 0; off >>= 1) {
-        Mp += __shfl_xor(Mp, off, 64);
-        Mc += __shfl_xor(Mc, off, 64);
+        P += __shfl_xor(P, off, 64);
+        C += __shfl_xor(C, off, 64);
     }
-    const bool fb = !(Mc > 0.0) || fabs(Mp / Mc - 1.0) > (double)L.tau;
+    const double lambda = P > 0.0 ? C / P : 0.0;
+    pm *= lambda;
+    double D = fabs(lambda * pc - cc) * area, Mp = pm;
+    for (int off = 32; off > 0; off >>= 1) {
+        D += __shfl_xor(D, off, 64);
+        Mp += __shfl_xor(Mp, off, 64);
+    }
+    if (live && L.cell_pred) L.cell_pred[item * L.n_cells + c] = pm;
+    const bool fb = !(C > 0.0) || !(P > 0.0) || D > (double)L.tau * C;
     // rank and predicted mass ahead of this cell
     int rank = 0;
     double ahead = 0.0;
@@ -166,7 +207,9 @@ __global__ __launch_bounds__(256) void widen_kernel(uint8_t *mask, int n_traj, i
 }
 
 // ---------------------------------------------------------------- combine
-// dI/dhw[traj][w] = sum_c (mask ? exact cell integral : coarse value x cell area).
+// dI/dhw[traj][w] = sum_c (mask ? exact cell integral : estimate), the estimate
+// being the predicted cell mass when cell_pred is given, else the coarse centre
+// value times the cell's area.
 __global__ __launch_bounds__(256) void combine_kernel(CombineLaunch L)
 {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,6 +220,8 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineLaunch L)
         const int64_t i = item * L.n_cells + c;
         if (L.mask[i]) {
             acc += L.cells[i];
+        } else if (L.cell_pred) {
+            acc += L.cell_pred[i];
         } else {
             const int ci = c % ncx, cj = c / ncx;
             double ax = 0.0, ay = 0.0;

@@ -12,7 +12,7 @@
 
 using namespace radsmp;
 
-static_assert(sizeof(FeatSeg) == 40, "rad_features documents 40 workspace bytes per segment");
+static_assert(sizeof(FeatSeg) == 48, "rad_features documents 48 workspace bytes per segment");
 
 namespace {
 
@@ -81,9 +81,9 @@ rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacin
         if (!(sg.gamma > 0.0)) return sfail(RAD_EINVAL, "segment %d: gamma must be > 0", s);
         const size_t b = (size_t)sg.n * sizeof(double);
         if ((rs = srange(sg.t, b, "t")) != RAD_OK || (rs = srange(sg.x, b, "x")) != RAD_OK ||
-            (rs = srange(sg.vx, b, "vx")) != RAD_OK)
+            (rs = srange(sg.vx, b, "vx")) != RAD_OK || (rs = srange(sg.vy, b, "vy")) != RAD_OK)
             return rs;
-        h[s] = FeatSeg{sg.t, sg.x, sg.vx, sg.n, sg.gamma};
+        h[s] = FeatSeg{sg.t, sg.x, sg.vx, sg.vy, sg.n, sg.gamma};
     }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(ws, h.data(), need, hipMemcpyHostToDevice, st);
@@ -96,7 +96,7 @@ rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacin
 
 rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
                               const double *coarse, int cx, int cy, float coverage, int cap, float tau,
-                              uint8_t *mask, uint8_t *fallback, void *stream)
+                              uint8_t *mask, uint8_t *fallback, double *cell_pred, void *stream)
 {
     rad::GridView v;
     rad_status rs = view_of(fine, v);
@@ -112,15 +112,17 @@ rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pre
     if ((rs = srange(coarse, items * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
     if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
     if ((rs = srange(fallback, items, "fallback")) != RAD_OK) return rs;
+    if (cell_pred && (rs = srange(cell_pred, items * n_cells * sizeof(double), "cell_pred")) != RAD_OK) return rs;
     SelectLaunch L{pred, mu, sigma, coarse, v.wx, v.wy, n_traj, v.n_w, v.n_x, v.n_y, cx, cy, n_cells,
-                   coverage, tau, cap, mask, fallback};
+                   coverage, tau, cap, mask, fallback, cell_pred};
     hipError_t e = launch_select(L, (hipStream_t)stream);
     if (e == hipSuccess) e = launch_widen(mask, n_traj, v.n_w, n_cells, (hipStream_t)stream);
     return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "select: %s", hipGetErrorString(e));
 }
 
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
-                               const uint8_t *mask, const double *coarse, double *dIdw, void *stream)
+                               const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,
+                               void *stream)
 {
     rad::GridView v;
     rad_status rs = view_of(fine, v);
@@ -133,7 +135,8 @@ rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy,
     if ((rs = srange(coarse, items * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
     if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
     if ((rs = srange(dIdw, items * sizeof(double), "dIdw")) != RAD_OK) return rs;
-    CombineLaunch L{cells, coarse, v.wx, v.wy, mask, n_traj, v.n_w, v.n_x, cx, cy, n_cells, dIdw};
+    if (cell_pred && (rs = srange(cell_pred, items * n_cells * sizeof(double), "cell_pred")) != RAD_OK) return rs;
+    CombineLaunch L{cells, coarse, v.wx, v.wy, cell_pred, mask, n_traj, v.n_w, v.n_x, cx, cy, n_cells, dIdw};
     hipError_t e = launch_combine(L, (hipStream_t)stream);
     return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "combine: %s", hipGetErrorString(e));
 }

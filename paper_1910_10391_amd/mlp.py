@@ -32,6 +32,8 @@ def _lib():
             "rad_mlp_grad": (I, [P, P, I, P, P, P, I, P, P, P, S, P]),
             "rad_mlp_adam": (I, [P, P, F, F, F, F, P]),
             "rad_mlp_forward": (I, [P, P, I, P, P, I, P, P, S, P]),
+            "rad_mlp_grid_workspace_bytes": (S, [P, I]),
+            "rad_mlp_forward_grid": (I, [P, P, I, P, I64, P, P, S, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -156,6 +158,28 @@ class MLP:
         rad._check(_lib().rad_mlp_forward(self.handle, rad._dptr(feat), feat.shape[0], rad._dptr(traj),
                                           rad._dptr(x), B, rad._dptr(y), rad._dptr(ws), ws.numel(),
                                           rad._stream(stream)), "rad_mlp_forward")
+        return y
+
+    def forward_grid(self, feat, x, y=None, stream=None):
+        """Inference at every (trajectory, point) pair: feat [n_traj, n_feat], x the point
+        table [n_pts, n_point]; returns y [n_traj, n_pts] (fused kernel, n_point <= 8)."""
+        import torch
+        for t in (feat, x):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError("feat and x must be contiguous float32 CUDA tensors")
+        if x.dim() != 2 or x.shape[1] != self.n_point or feat.dim() != 2:
+            raise ValueError("x must be [n_pts, n_point] and feat [n_traj, n_feat]")
+        n_traj, n_pts = feat.shape[0], x.shape[0]
+        if y is None:
+            y = torch.empty((n_traj, n_pts), dtype=torch.float32, device="cuda")
+        if tuple(y.shape) != (n_traj, n_pts) or not y.is_contiguous() or y.dtype != torch.float32:
+            raise ValueError("y must be a contiguous float32 [n_traj, n_pts] tensor")
+        nb = int(_lib().rad_mlp_grid_workspace_bytes(self.handle, int(n_traj)))
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+        rad._check(_lib().rad_mlp_forward_grid(self.handle, rad._dptr(feat), int(n_traj), rad._dptr(x), int(n_pts),
+                                               rad._dptr(y), rad._dptr(self._ws), self._ws.numel(),
+                                               rad._stream(stream)), "rad_mlp_forward_grid")
         return y
 
     def close(self):

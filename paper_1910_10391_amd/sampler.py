@@ -5,16 +5,18 @@ n x n grid of directions within +-H/gamma from
 
 1. the exact spectrum at the centres of the (n/8) x (n/8) cells (``rad.batch`` on a
    coarse grid),
-2. the network's predicted log intensity at every fine direction
-   (``rad_mlp_forward``; inputs: 34 trajectory features from ``rad_features`` and
-   (log hw, gamma thx, gamma thy)),
+2. the network's predicted angular shape (log intensity up to a constant) at every
+   fine direction (``rad_mlp_forward_grid``; inputs: 38 trajectory features from
+   ``rad_features`` and (log hw, gamma thx, gamma thy)), scaled to the exact centre
+   values,
 3. exact integrals over the cells the prediction ranks highest, until 99 % of the
    predicted intensity is covered (``rad_sampler_select``, ``rad_cells``),
-4. the coarse value times the area for the remaining cells
-   (``rad_sampler_combine``).
+4. for the remaining cells the predicted cell mass (``fill="pred"``) or the coarse
+   value times the area (``fill="coarse"``) (``rad_sampler_combine``).
 
-When the predicted and the coarse angle-integrated intensity disagree by more
-than ``tau`` a photon energy falls back to the full grid.  The full-grid integral
+When the scaled prediction at the cell centres deviates from the exact centre
+values by more than ``tau`` (relative L1 norm) a photon energy falls back to the
+full grid.  The full-grid integral
 (``rad.batch`` on the fine grid) is the reference that judges the error.  The
 network is trained on spectra the method itself computes (``training_set``) with
 the library's BF16 forward/backward kernels and Adam (``train``).
@@ -32,7 +34,7 @@ import numpy as np
 from . import rad
 from .mlp import MLP
 
-N_FEATURES = 34
+N_FEATURES = 38
 CELL = 8
 KIND = rad.SPINHALF
 _bound = False
@@ -45,8 +47,8 @@ def _lib():
         P, I, S, F, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_float, ctypes.c_double
         sig = {
             "rad_features": (I, [ctypes.POINTER(rad.Segment), I, D, P, P, S, P]),
-            "rad_sampler_select": (I, [P, I, P, F, F, P, I, I, F, I, F, P, P, P]),
-            "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P]),
+            "rad_sampler_select": (I, [P, I, P, F, F, P, I, I, F, I, F, P, P, P, P]),
+            "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -92,18 +94,19 @@ class Grids:
 
 
 def features(dsegs, plane_spacing_m, stream=None):
-    """[n_segs, 34] float32 features (rad_features)."""
+    """[n_segs, 38] float32 features (rad_features)."""
     import torch
     n = len(dsegs)
     feat = torch.empty((n, N_FEATURES), dtype=torch.float32, device="cuda")
-    ws = torch.empty(max(64 * n, 256), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(48 * n, 256), dtype=torch.uint8, device="cuda")
     rad._check(_lib().rad_features(dsegs.structs, n, float(plane_spacing_m), rad._dptr(feat),
                                    rad._dptr(ws), ws.numel(), rad._stream(stream)), "rad_features")
     return feat
 
 
-def predict(mlp, grids, feat, chunk_points=1 << 22):
-    """Normalised log-intensity prediction [n_traj, n_w, n, n] for every fine point."""
+def predict(mlp, grids, feat, chunk_points=1 << 27):
+    """Normalised log-intensity prediction [n_traj, n_w, n, n] for every fine point
+    (rad_mlp_forward_grid: no per-point inputs are materialised)."""
     import torch
     n_traj = feat.shape[0]
     ppt = grids.points_per_traj
@@ -111,20 +114,20 @@ def predict(mlp, grids, feat, chunk_points=1 << 22):
     per_call = max(1, chunk_points // ppt)
     for t0 in range(0, n_traj, per_call):
         t1 = min(n_traj, t0 + per_call)
-        k = t1 - t0
-        traj = torch.arange(t0, t1, dtype=torch.int32, device="cuda").repeat_interleave(ppt)
-        x = grids.point_x.repeat(k, 1)
-        out[t0:t1] = mlp.forward(feat, traj, x).view(k, ppt)
+        mlp.forward_grid(feat[t0:t1].contiguous(), grids.point_x, y=out[t0:t1])
     return out.view(n_traj, grids.hw.size, grids.n, grids.n)
 
 
 class Sampler:
     """The learned sampler for one kind of workload (fixed grids and normalisation)."""
 
-    def __init__(self, mlp, norm, grids, plane_spacing_m, coverage=0.99, cap=16, tau=0.25):
+    def __init__(self, mlp, norm, grids, plane_spacing_m, coverage=0.99, cap=16, tau=0.25, fill="pred"):
         self.mlp, self.norm, self.grids = mlp, dict(norm), grids
         self.d = float(plane_spacing_m)
         self.coverage, self.cap, self.tau = float(coverage), int(cap), float(tau)
+        if fill not in ("pred", "coarse"):
+            raise ValueError("fill must be 'pred' or 'coarse'")
+        self.fill = fill
 
     def coarse(self, dsegs, precision):
         n = len(dsegs)
@@ -132,25 +135,29 @@ class Sampler:
         return c.view(n, self.grids.hw.size, self.grids.n_cells)
 
     def select(self, pred, coarse, coverage=None, cap=None, tau=None, mu=None, sigma=None):
+        """mask, fallback flags and predicted cell masses (rad_sampler_select)."""
         import torch
         n = pred.shape[0]
         g = self.grids
         mask = torch.empty((n, g.hw.size, g.n_cells), dtype=torch.uint8, device="cuda")
         fb = torch.empty((n, g.hw.size), dtype=torch.uint8, device="cuda")
+        pm = torch.empty((n, g.hw.size, g.n_cells), dtype=torch.float64, device="cuda")
         rad._check(_lib().rad_sampler_select(
             g.fine.handle, n, rad._dptr(pred), float(self.norm["mu"] if mu is None else mu),
             float(self.norm["sigma"] if sigma is None else sigma), rad._dptr(coarse), CELL, CELL,
             float(self.coverage if coverage is None else coverage), int(self.cap if cap is None else cap),
-            float(self.tau if tau is None else tau), rad._dptr(mask), rad._dptr(fb), rad._stream(None)),
-            "rad_sampler_select")
-        return mask, fb
+            float(self.tau if tau is None else tau), rad._dptr(mask), rad._dptr(fb), rad._dptr(pm),
+            rad._stream(None)), "rad_sampler_select")
+        return mask, fb, pm
 
-    def combine(self, cells, mask, coarse):
+    def combine(self, cells, mask, coarse, cell_pred=None):
+        """dI/dhw: exact cells where selected, else cell_pred (if given) or centre x area."""
         import torch
         n = cells.shape[0]
         out = torch.empty((n, self.grids.hw.size), dtype=torch.float64, device="cuda")
         rad._check(_lib().rad_sampler_combine(self.grids.fine.handle, n, CELL, CELL, rad._dptr(cells),
-                                              rad._dptr(mask), rad._dptr(coarse), rad._dptr(out),
+                                              rad._dptr(mask), rad._dptr(coarse),
+                                              None if cell_pred is None else rad._dptr(cell_pred), rad._dptr(out),
                                               rad._stream(None)), "rad_sampler_combine")
         return out
 
@@ -178,19 +185,21 @@ class Sampler:
             feat = features(dsegs, self.d)
             pred = predict(self.mlp, g, feat)
             t = mark("features_predict", t)
-            mask, fb = self.select(pred, coarse)
+            mask, fb, pm = self.select(pred, coarse)
+            fill = pm if self.fill == "pred" else None
         elif rule == "coarse":
             k = g.n // CELL
             lc = torch.log(coarse.float()).view(len(dsegs), g.hw.size, k, k)
             pred = lc.repeat_interleave(CELL, dim=2).repeat_interleave(CELL, dim=3).contiguous()
-            mask, fb = self.select(pred, coarse, tau=float("inf"), mu=0.0, sigma=1.0)
+            mask, fb, _ = self.select(pred, coarse, tau=float("inf"), mu=0.0, sigma=1.0)
+            fill = None
         else:
             raise ValueError("rule must be 'learned' or 'coarse'")
         mask_h = mask.cpu().numpy()
         t = mark("select", t)
         cells = rad.cells(g.fine, dsegs, KIND, mask_h, precision)
         t = mark("cells", t)
-        dIdw = self.combine(cells, mask, coarse)
+        dIdw = self.combine(cells, mask, coarse, fill)
         mark("combine", t)
         dt = time.perf_counter() - t0
         n_t = np.array(dsegs.n, dtype=np.float64)
@@ -218,7 +227,7 @@ class Sampler:
         np.savez(path, params=theta, mu=self.norm["mu"], sigma=self.norm["sigma"],
                  logw_mean=self.grids.logw_norm[0], logw_std=self.grids.logw_norm[1],
                  n_fine=self.grids.n, half_width=self.grids.H, plane_spacing=self.d,
-                 coverage=self.coverage, cap=self.cap, tau=self.tau)
+                 coverage=self.coverage, cap=self.cap, tau=self.tau, fill=self.fill)
 
     @classmethod
     def load(cls, path, hw_eV, gamma):
@@ -228,15 +237,19 @@ class Sampler:
             mlp = MLP(N_FEATURES, 3)
             mlp.set_params(z["params"])
             return cls(mlp, dict(mu=float(z["mu"]), sigma=float(z["sigma"])), grids, float(z["plane_spacing"]),
-                       float(z["coverage"]), int(z["cap"]), float(z["tau"]))
+                       float(z["coverage"]), int(z["cap"]), float(z["tau"]), str(z["fill"]))
 
 
 # ---------------------------------------------------------------- training
-def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64, first=0, verbose=False):
+def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64, first=0, floor_rel=1e-3,
+                 verbose=False):
     """Spectra produced by the method itself: for each trajectory, n_w_train of the grid's
     photon energies (every k-th, offset by the trajectory index so that all energies are
-    covered) on the full fine grid.  Returns features [N, 34], the point-table index of each
-    energy [N, n_w_train] and log targets log(S + 1e-6 max S) [N, n_w_train, n, n] (float32)."""
+    covered) on the full fine grid.  Returns features [N, 38], the point-table index of each
+    energy [N, n_w_train] and, as the target, the angular shape of each map,
+    log(S / max S + floor_rel) with the maximum over the map's directions
+    [N, n_w_train, n, n] (float32); the scale comes from the exact centre values when
+    cells are selected."""
     import torch
     from .synth import channeling
     n_w = grids.hw.size
@@ -260,8 +273,8 @@ def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64
             cube = rad.batch(grid_cache[off], sub, list(range(len(members))), len(members), KIND,
                              precision)[:, 0].float()
             S = cube.clamp_min(0)
-            floor = 1e-6 * S.amax(dim=(1, 2, 3), keepdim=True)
-            y = torch.log(S + floor)
+            peak = S.amax(dim=(2, 3), keepdim=True).clamp_min(1e-300)
+            y = torch.log(S / peak + floor_rel)
             for j, i in enumerate(members):
                 targets.append((c0 + i, y[j]))
                 tw.append((c0 + i, torch.from_numpy(iw.astype(np.int64))))

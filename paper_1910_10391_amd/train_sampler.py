@@ -8,7 +8,9 @@
    on the full 64 x 64 grid within +-5/gamma.
 2. Training: Adam on minibatches of (trajectory, energy, direction) points with the
    library's BF16 MLP kernels.
-3. Tuning: the mass-mismatch tolerance tau on ``--val`` held-out trajectories.
+3. Tuning on ``--val`` held-out trajectories: the check tolerance tau and how the
+   cells left out are counted (predicted mass, or centre value x area), for the
+   fewest evaluations within the error target.
 4. Evaluation on ``--test`` further held-out trajectories against the full-grid angle
    integral: relative error of dI/d hw, evaluations and time, next to refinement
    ranked by the coarse values alone (no network) and the coarse grid alone.
@@ -62,16 +64,18 @@ def main(argv=None):
     ap.add_argument("--train", type=int, default=782, help="training trajectories (x 64 energies each)")
     ap.add_argument("--val", type=int, default=32)
     ap.add_argument("--test", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--coverage", type=float, default=0.99)
-    ap.add_argument("--cap", type=int, default=16)
+    ap.add_argument("--coverage", type=float, default=0.0, help="0: tuned on the validation set")
+    ap.add_argument("--cap", type=int, default=64)
     ap.add_argument("--target", type=float, default=0.01, help="error bound tau is tuned for")
     ap.add_argument("--out", default=None, help="checkpoint (.npz)")
     ap.add_argument("--report", default=None, help="JSON report")
     ap.add_argument("--load", default=None, help="skip training, load this checkpoint")
+    ap.add_argument("--fill", default="auto", choices=["auto", "pred", "coarse"],
+                    help="estimate of the cells left out (auto: chosen on the validation set)")
     a = ap.parse_args(argv)
     import torch
 
@@ -104,25 +108,35 @@ def main(argv=None):
         smp = Sampler(mlp, norm, grids, cfg.d_m, a.coverage, a.cap, tau=0.25)
     prec = rad.MIXED
 
-    # tau on held-out validation trajectories: the largest tolerance that keeps every
-    # validation error within the target
+    # coverage, tau and the fill rule on held-out validation trajectories: the setting with
+    # the fewest evaluations whose largest validation error stays within the target; the
+    # same search for refinement ranked by the coarse values alone (no network)
     dv = _device_segments(cfg, a.val, 60000)
     fv, _ = smp.full_grid(dv, prec)
     fv = fv.cpu().numpy()
+    coverages = (a.coverage,) if a.coverage > 0 else (0.9, 0.95, 0.98, 0.99, 0.995)
+    fills = ("pred", "coarse") if a.fill == "auto" else (a.fill,)
     tune = []
-    chosen = 0.0
-    for tau in (0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0):
-        smp.tau = tau
-        r = evaluate(smp, dv, fv, prec)
-        tune.append(dict(tau=tau, max_rel_err=r["max_rel_err"], fallback_frac=r["fallback_frac"],
-                         evals_frac=r["evals"] / r["evals_full"]))
-        print("tau %.2f: max rel err %.4f fallback %.3f evals %.3f" % (
-            tau, r["max_rel_err"], r["fallback_frac"], r["evals"] / r["evals_full"]), flush=True)
-        if r["max_rel_err"] <= a.target:
-            chosen = tau
-    smp.tau = chosen
-    report["tau_scan"] = tune
-    report["tau"] = chosen
+    best = {}
+    for rule in ("learned", "coarse"):
+        for cov in coverages:
+            for fill in (fills if rule == "learned" else ("coarse",)):
+                for tau in ((0.3, 0.5, 1.0, float("inf")) if rule == "learned" else (float("inf"),)):
+                    smp.coverage, smp.fill, smp.tau = cov, fill, tau
+                    r = evaluate(smp, dv, fv, prec, rule=rule)
+                    frac = r["evals"] / r["evals_full"]
+                    tune.append(dict(rule=rule, coverage=cov, fill=fill, tau=tau, max_rel_err=r["max_rel_err"],
+                                     fallback_frac=r["fallback_frac"], evals_frac=frac))
+                    print("%s coverage %.3f fill %s tau %.2f: max rel err %.4f fallback %.3f evals %.3f" % (
+                        rule, cov, fill, tau, r["max_rel_err"], r["fallback_frac"], frac), flush=True)
+                    if r["max_rel_err"] <= a.target and (rule not in best or frac < best[rule][0]):
+                        best[rule] = (frac, cov, fill, tau)
+    report["tune"] = tune
+    report["chosen"] = {k: dict(evals_frac=v[0], coverage=v[1], fill=v[2], tau=v[3]) for k, v in best.items()}
+    settings = {}
+    for rule in ("learned", "coarse"):
+        # nothing within the target: every energy falls back (learned) / every cell refined
+        settings[rule] = best.get(rule, (1.0, 1.0, "coarse", 0.0))[1:]
 
     # test: held-out trajectories
     dt_ = _device_segments(cfg, a.test, 70000)
@@ -134,7 +148,10 @@ def main(argv=None):
     full = f.cpu().numpy()
     res = {}
     for rule in ("learned", "coarse"):
+        smp.coverage, smp.fill, smp.tau = settings[rule]
         res[rule] = evaluate(smp, dt_, full, prec, rule=rule, reps=2)
+        res[rule]["settings"] = dict(coverage=smp.coverage, fill=smp.fill, tau=smp.tau)
+    smp.coverage, smp.fill, smp.tau = settings["learned"]
     # the coarse grid alone: every cell at its centre value x area
     c = smp.coarse(dt_, prec)
     area = float((2 * 5.0 / gamma / 8) ** 2)
@@ -146,6 +163,7 @@ def main(argv=None):
         res[k]["evals_frac"] = res[k]["evals"] / res[k]["evals_full"]
     report["test"] = res
     report["accepted"] = res["learned"]["max_rel_err"] <= a.target
+    report["tau"], report["fill"], report["coverage"] = smp.tau, smp.fill, smp.coverage
     report["total_seconds"] = time.time() - t_start
     print(json.dumps(res, indent=1), flush=True)
     if a.out:

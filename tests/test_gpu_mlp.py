@@ -72,6 +72,20 @@ def test_forward_paths_match_cpu_reference(M, nf, npnt, B, n_traj):
     assert err < 5e-3
 
 
+def test_forward_grid_equals_forward(M):
+    """The grid form (every trajectory at every point of one table) gives exactly what the
+    per-point form gives on the materialised inputs."""
+    import torch
+    net = M.MLP(38, 3, seed=17)
+    rng = np.random.default_rng(18)
+    feat = torch.from_numpy((0.5 * rng.normal(size=(5, 38))).astype(np.float32)).cuda()
+    table = torch.from_numpy(rng.normal(size=(1000, 3)).astype(np.float32)).cuda()
+    yg = net.forward_grid(feat, table)
+    traj = torch.arange(5, dtype=torch.int32, device="cuda").repeat_interleave(1000)
+    yp = net.forward(feat, traj, table.repeat(5, 1).contiguous()).view(5, 1000)
+    assert torch.equal(yg, yp)
+
+
 def test_adam_step_matches_cpu_reference(M):
     import torch
     net = M.MLP(34, 3, seed=7)

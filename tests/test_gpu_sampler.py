@@ -24,9 +24,10 @@ def S():
     return sampler
 
 
-def _seg(t, x, vx, gamma):
+def _seg(t, x, vx, gamma, vy=None):
     z = np.zeros_like(t)
-    return dict(t=t, x=x, y=z, dz=z, vx=vx, vy=z, dvz=z, ax=z, ay=z, az=z, gamma=gamma, energy_eV=0.0)
+    vy = z if vy is None else vy
+    return dict(t=t, x=x, y=z, dz=z, vx=vx, vy=vy, dvz=z, ax=z, ay=z, az=z, gamma=gamma, energy_eV=0.0)
 
 
 def _sinusoid(a, W, periods, per_period=64):
@@ -44,17 +45,20 @@ def test_features_match_oracle(S):
     from paper_1910_10391_amd import rad
     cfg = dataclasses.replace(presets.positron_config(seed=9), length_m=30e-6, n_min=6000, n_max=20000)
     segs = [tr[0] for tr in channeling.generate(cfg, 3, threads=8)]
-    segs.append(_seg(*_sinusoid(0.3 * D / 2, 2e6, 10), gamma=3e4))
+    t_, x_, v_ = _sinusoid(0.3 * D / 2, 2e6, 10)
+    segs.append(_seg(t_, x_, v_, gamma=3e4, vy=1e-5 + 0.3 * v_))
     segs.append(_seg(*_sinusoid(0.7 * D / 2, 2e6, 3000), gamma=1e4))       # more turning points than kept
     tl = np.linspace(0.0, 1e-5, 500)
     segs.append(_seg(tl, 3 * D * tl / tl[-1], np.full_like(tl, 1.0), gamma=2e4))   # no turning point
     ds = rad.DeviceSegments(segs)
     got = S.features(ds, D).cpu().numpy().astype(np.float64)
     for i, sg in enumerate(segs):
-        ref = osm.features(sg["t"], sg["x"], sg["vx"], sg["gamma"], D)
+        ref = osm.features(sg["t"], sg["x"], sg["vx"], sg["vy"], sg["gamma"], D)
         print("features %d: max abs diff %.2e" % (i, np.abs(got[i] - ref).max()), flush=True)
+        assert got.shape[1] == osm.N_FEATURES == S.N_FEATURES
         np.testing.assert_allclose(got[i, 1:33], ref[1:33], rtol=0, atol=1e-6)
-        np.testing.assert_allclose(got[i, [0, 33]], ref[[0, 33]], rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(got[i, [0, 33, 34, 35, 36, 37]], ref[[0, 33, 34, 35, 36, 37]], rtol=1e-5,
+                                   atol=1e-6)
 
 
 def _fine(n=64, gamma=2e4, n_w=130):
@@ -66,7 +70,6 @@ def _fine(n=64, gamma=2e4, n_w=130):
 
 def test_select_matches_oracle(S):
     import torch
-    from paper_1910_10391_amd import rad
     rng = np.random.default_rng(21)
     grid, th = _fine()
     n_w = grid.shape[0]
@@ -77,27 +80,29 @@ def test_select_matches_oracle(S):
     P = rng.normal(size=(n_traj, blocks, 64, 64)).astype(np.float32) * 2.0
     pred = np.repeat(P, 64, axis=1)[:, :n_w].copy()
     mu, sigma = np.float32(-3.0), np.float32(1.5)
-    pm = osm.cell_sums(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), w, w, 8, 8)
-    area = osm.cell_areas(w, w, 8, 8)
-    scale = 1.0 + 0.05 * rng.normal(size=(n_traj, n_w, 1))
-    scale[0, 5] = 2.0           # -> fallback (1/2 - 1 beyond tau)
-    scale[2, 100] = 0.5         # -> fallback
-    coarse = pm / area * scale
-    coarse[1, 7, :] = 0.0       # no coarse mass -> fallback
+    inten = np.exp(float(mu) + float(sigma) * pred.astype(np.float64))
+    centre = osm.centre_values(inten, 8, 8)
+    scale = 1.0 + 0.05 * rng.normal(size=(n_traj, n_w, 64))
+    scale[0, 5, :32] = 3.0      # half the cells tripled: a shape mismatch -> fallback
+    scale[2, 100, ::2] = 0.2    # checkerboard -> fallback
+    scale[1, 9] = 4.0           # a uniform rescaling: the prediction is a shape -> no fallback
+    coarse = centre * scale
+    coarse[1, 7, :] = 0.0       # no coarse value -> fallback
     for cov, cap, tau in ((0.99, 16, 0.25), (0.5, 64, 0.25), (0.9, 3, 0.2)):
-        mask, fb = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, cov, cap, tau).select(
+        mask, fb, pm = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, cov, cap, tau).select(
             torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda())
-        rm, rf = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, cov, cap, tau)
+        rm, rf, rpm = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, cov, cap, tau)
         assert np.array_equal(fb.cpu().numpy(), rf)
         assert np.array_equal(mask.cpu().numpy(), rm), (cov, cap, tau)
+        assert np.allclose(pm.cpu().numpy(), rpm, rtol=1e-12, atol=0)
         print("select cov %.2f cap %d: %d cells of %d, %d fallbacks" % (cov, cap, rm.sum(), rm.size, rf.sum()))
     # per-energy predictions: the widening itself
     pred = (rng.normal(size=(n_traj, n_w, 64, 64)) * 2.0).astype(np.float32)
-    pm = osm.cell_sums(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), w, w, 8, 8)
-    coarse = pm / area
-    mask, fb = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, 0.6, 4, 0.25).select(
+    coarse = osm.centre_values(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), 8, 8)
+    mask, fb, _ = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, 0.6, 4, 0.25).select(
         torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda())
-    rm, rf = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, 0.6, 4, 0.25)
+    rm, rf, _ = osm.select(pred, float(mu), float(sigma), coarse, w, w, 8, 8, 0.6, 4, 0.25)
+    assert not rf.any()
     assert np.array_equal(fb.cpu().numpy(), rf) and np.array_equal(mask.cpu().numpy(), rm)
 
 
@@ -119,12 +124,17 @@ def test_combine_matches_oracle(S):
     cells = rng.random((2, 70, 64))
     coarse = rng.random((2, 70, 64))
     mask = (rng.random((2, 70, 64)) < 0.3).astype(np.uint8)
-    got = S.Sampler(None, dict(mu=0.0, sigma=1.0), _G(grid), D).combine(
-        torch.from_numpy(cells).cuda(), torch.from_numpy(mask).cuda(), torch.from_numpy(coarse).cuda())
+    smp = S.Sampler(None, dict(mu=0.0, sigma=1.0), _G(grid), D)
+    dev = [torch.from_numpy(a).cuda() for a in (cells, mask, coarse)]
+    got = smp.combine(*dev)
     ref = osm.combine(cells, mask, coarse, w, w, 8, 8)
     err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
     print("combine: max rel err %.2e" % err)
     assert err < 1e-13
+    pm = rng.random((2, 70, 64))
+    got = smp.combine(*dev, cell_pred=torch.from_numpy(pm).cuda())
+    ref = osm.combine(cells, mask, coarse, w, w, 8, 8, cell_pred=pm)
+    assert np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max() < 1e-13
 
 
 def test_estimate_matches_oracle(S):
@@ -139,7 +149,7 @@ def test_estimate_matches_oracle(S):
     hw = analytic.log_omega(70, 1e6, 150e6)
     grids = S.Grids(hw, gamma, n_fine=16, half_width_over_gamma=5.0)
     smp = S.Sampler(MLP(S.N_FEATURES, 3, seed=3), dict(mu=-8.0, sigma=2.0), grids, cfg.d_m,
-                    coverage=0.6, cap=2, tau=1e30)
+                    coverage=0.6, cap=2, tau=1e30, fill="coarse")
     ds = rad.DeviceSegments(segs)
     th = grids.fine.thx
     thc = grids.coarse.thx
@@ -152,13 +162,16 @@ def test_estimate_matches_oracle(S):
     feat = S.features(ds, cfg.d_m)
     pred = S.predict(smp.mlp, grids, feat).cpu().numpy()
     for prec, tol in ((rad.FP64, 1e-9), (rad.MIXED, 1e-4)):
-        res = smp.estimate(ds, precision=prec)
-        rm, rf = osm.select(pred, -8.0, 2.0, coarse, w, w, 8, 8, 0.6, 2, 1e30)
-        assert np.array_equal(res["mask"], rm) and not rf.any()
-        ref = osm.combine(cells, rm, coarse, w, w, 8, 8)
-        err = np.abs(res["dIdw"].cpu().numpy() - ref).max() / np.abs(ref).max()
-        print("estimate prec %d: %.2e (refined %.2f of 4 cells)" % (prec, err, res["refined_cells_mean"]))
-        assert err < tol
+        rm, rf, rpm = osm.select(pred, -8.0, 2.0, coarse, w, w, 8, 8, 0.6, 2, 1e30)
+        for fill in ("coarse", "pred"):
+            smp.fill = fill
+            res = smp.estimate(ds, precision=prec)
+            assert np.array_equal(res["mask"], rm) and not rf.any()
+            ref = osm.combine(cells, rm, coarse, w, w, 8, 8, cell_pred=rpm if fill == "pred" else None)
+            err = np.abs(res["dIdw"].cpu().numpy() - ref).max() / np.abs(ref).max()
+            print("estimate prec %d fill %s: %.2e (refined %.2f of 4 cells)" % (prec, fill, err,
+                                                                               res["refined_cells_mean"]))
+            assert err < tol
         smp.tau = 0.0                                   # every energy falls back: the full grid
         res = smp.estimate(ds, precision=prec)
         assert res["fallback"].all()

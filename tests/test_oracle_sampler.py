@@ -19,12 +19,18 @@ def test_features_sinusoid_closed_form():
     a = 10.5 / 32 * (D / 2)              # the middle of bin 10
     W = 3.0e6                            # rad per metre of ct
     t, x, vx = _sinusoid(a, W, periods=50)
-    f = osm.features(t, x, vx, gamma=2e4, plane_spacing=D)
-    assert f.shape == (34,)
+    vy = np.full_like(t, 2.5e-5)
+    f = osm.features(t, x, vx, vy, gamma=2e4, plane_spacing=D)
+    assert f.shape == (38,)
     assert abs(f[0] - np.log(2.0)) < 1e-15
     hist = f[1:33]
     assert hist[10] == 1.0 and hist.sum() == 1.0
     assert abs(np.exp(f[33]) * 1e5 / W - 1.0) < 1.0 / 50
+    # direction moments in units of 1/gamma: a whole number of periods (plus the
+    # closing sample) averages cos to ~0; the spread of a W cos is a W / sqrt(2)
+    assert abs(f[34]) < 0.05 * a * W * 2e4
+    assert abs(f[35] - 2e4 * 2.5e-5) < 1e-12 and abs(f[37]) < 1e-9
+    assert abs(f[36] / (2e4 * a * W / np.sqrt(2)) - 1.0) < 0.01
 
 
 def test_features_two_amplitudes():
@@ -37,7 +43,7 @@ def test_features_two_amplitudes():
     t = np.concatenate([t1, t2[1:]])
     x = np.concatenate([x1, x2[1:] - x2[0] + x1[-1]])
     vx = np.concatenate([v1, v2[1:]])
-    f = osm.features(t, x, vx, gamma=1e4, plane_spacing=D)
+    f = osm.features(t, x, vx, np.zeros_like(t), gamma=1e4, plane_spacing=D)
     hist = f[1:33]
     # one half-oscillation straddles the junction; it falls between the two bins
     assert abs(hist[3] - 0.5) < 0.05 and abs(hist[20] - 0.5) < 0.05
@@ -49,32 +55,61 @@ def test_features_over_barrier_and_no_turning():
     t = np.linspace(0.0, 1e-4, 1000)
     x = 5 * D * t / t[-1]
     vx = np.full_like(t, 5 * D / t[-1])
-    f = osm.features(t, x, vx, gamma=1e4, plane_spacing=D)
+    f = osm.features(t, x, vx, -vx, gamma=1e4, plane_spacing=D)
     assert f[32] == 1.0 and f[1:32].sum() == 0.0
     assert f[33] == np.log(1.0 / 1e5)
+    assert abs(f[34] + f[35]) < 1e-15 and f[36] == 0.0 and f[37] == 0.0
 
 
-def _unit_grid_select(masses, coarse_masses, coverage, cap, tau):
-    """1 trajectory, 1 energy, 2 x 2 fine grid with unit widths, 1 x 1 cells."""
+def _unit_grid_select(masses, coarse_values, coverage, cap, tau):
+    """1 trajectory, 1 energy, 2 x 2 fine grid with unit widths, 1 x 1 cells (each cell's
+    centre value is its single fine point)."""
     pred = np.log(np.asarray(masses, dtype=np.float64)).reshape(1, 1, 2, 2)
-    coarse = np.asarray(coarse_masses, dtype=np.float64).reshape(1, 1, 4)
+    coarse = np.asarray(coarse_values, dtype=np.float64).reshape(1, 1, 4)
     w = np.ones(2)
     return osm.select(pred, 0.0, 1.0, coarse, w, w, 1, 1, coverage, cap, tau)
 
 
 def test_select_hand_worked():
     m = [0.125, 0.5, 0.125, 0.25]                           # ranks: 1, 3, then 0 and 2 (ties by index)
-    mask, fb = _unit_grid_select(m, m, coverage=0.75, cap=4, tau=0.25)
-    assert fb[0, 0] == 0
+    mask, fb, pm = _unit_grid_select(m, m, coverage=0.75, cap=4, tau=0.25)
+    assert fb[0, 0] == 0 and np.allclose(pm[0, 0], m, rtol=1e-15)
     assert mask[0, 0].tolist() == [0, 1, 0, 1]              # mass ahead of cell 0 is 0.75: not below 0.75
-    mask, _ = _unit_grid_select(m, m, coverage=0.8, cap=4, tau=0.25)
+    mask, _, _ = _unit_grid_select(m, m, coverage=0.8, cap=4, tau=0.25)
     assert mask[0, 0].tolist() == [1, 1, 0, 1]              # cell 0 before cell 2 (equal mass)
-    mask, _ = _unit_grid_select(m, m, coverage=1.0, cap=2, tau=0.25)
+    mask, _, _ = _unit_grid_select(m, m, coverage=1.0, cap=2, tau=0.25)
     assert mask[0, 0].tolist() == [0, 1, 0, 1]              # the cap
-    mask, fb = _unit_grid_select(m, [2 * v for v in m], coverage=0.5, cap=1, tau=0.25)
-    assert fb[0, 0] == 1 and mask[0, 0].tolist() == [1, 1, 1, 1]   # |0.5 - 1| > tau
-    mask, fb = _unit_grid_select(m, [0.0] * 4, coverage=0.5, cap=1, tau=10.0)
-    assert fb[0, 0] == 1 and mask.all()                     # no coarse mass
+    # the prediction is a shape: a uniform rescaling of the exact values passes, and the
+    # predicted masses come out at the exact scale
+    mask, fb, pm = _unit_grid_select(m, [2 * v for v in m], coverage=0.5, cap=1, tau=1e-9)
+    assert fb[0, 0] == 0 and mask[0, 0].tolist() == [0, 1, 0, 0]
+    assert np.allclose(pm[0, 0], [2 * v for v in m], rtol=1e-14)
+    # shape mismatch: exact [0.5, 0.125, 0.25, 0.125] against the shape of m (same total):
+    # lambda = 1, sum |P - C| = 1.0 against sum C = 1.0
+    mask, fb, _ = _unit_grid_select(m, [0.5, 0.125, 0.25, 0.125], coverage=0.5, cap=1, tau=0.99)
+    assert fb[0, 0] == 1 and mask.all()
+    mask, fb, _ = _unit_grid_select(m, [0.5, 0.125, 0.25, 0.125], coverage=0.5, cap=1, tau=1.01)
+    assert fb[0, 0] == 0
+    # a partial mismatch: exact = m except cell 3 doubled (sum 1.25): lambda = 1.25,
+    # deviations |1.25 m - C| = [0.03125, 0.125, 0.03125, 0.1875], sum 0.375 = 0.3 x 1.25
+    c3 = list(m)
+    c3[3] *= 2
+    _, fb, _ = _unit_grid_select(m, c3, coverage=0.5, cap=1, tau=0.31)
+    assert fb[0, 0] == 0
+    _, fb, _ = _unit_grid_select(m, c3, coverage=0.5, cap=1, tau=0.29)
+    assert fb[0, 0] == 1
+    mask, fb, _ = _unit_grid_select(m, [0.0] * 4, coverage=0.5, cap=1, tau=10.0)
+    assert fb[0, 0] == 1 and mask.all()                     # no coarse value
+
+
+def test_centre_values_of_even_and_odd_cells():
+    v = np.arange(36.0).reshape(6, 6)
+    # 2 x 2 cells: every point is central
+    assert np.allclose(osm.centre_values(v, 2, 2), osm.cell_sums(v, np.ones(6), np.ones(6), 2, 2) / 4)
+    # 3 x 3 cells: the middle point
+    assert osm.centre_values(v, 3, 3).tolist() == [v[1, 1], v[1, 4], v[4, 1], v[4, 4]]
+    # 6 x 6: the central 2 x 2
+    assert osm.centre_values(v, 6, 6).tolist() == [(v[2, 2] + v[2, 3] + v[3, 2] + v[3, 3]) / 4]
 
 
 def test_select_widens_to_energy_blocks():
@@ -84,7 +119,7 @@ def test_select_widens_to_energy_blocks():
     pred[0, 70, 1, 0] = 0.0                                 # energy 70: only cell 2
     coarse = np.exp(pred).reshape(1, n_w, 4)
     w = np.ones(2)
-    mask, fb = osm.select(pred, 0.0, 1.0, coarse, w, w, 1, 1, 0.25, 4, 0.25)
+    mask, fb, _ = osm.select(pred, 0.0, 1.0, coarse, w, w, 1, 1, 0.25, 4, 0.25)
     assert not fb.any()
     assert mask[0, :64, 1].all() and not mask[0, 64:, 1].any()
     assert mask[0, 64:, 2].all() and not mask[0, :64, 2].any()
@@ -111,6 +146,11 @@ def test_combine_exact_and_coarse():
     got = osm.combine(cells, mask, coarse, wx, wy, 2, 2)
     area = osm.cell_areas(wx, wy, 2, 2)
     ref = sum(cells[..., c] * mask[..., c] + coarse[..., c] * area[c] * (1 - mask[..., c]) for c in range(4))
+    assert np.allclose(got, ref, rtol=1e-14)
+    # with predicted cell masses the unselected cells take those
+    pm = rng.random((2, 5, 4))
+    got = osm.combine(cells, mask, coarse, wx, wy, 2, 2, cell_pred=pm)
+    ref = sum(cells[..., c] * mask[..., c] + pm[..., c] * (1 - mask[..., c]) for c in range(4))
     assert np.allclose(got, ref, rtol=1e-14)
 
 
