@@ -56,7 +56,7 @@ VALU_PER_EVAL_44 = {True: 358.0 / 16.0, False: 329.0 / 16.0}
 # for the kernel sources they were measured on (sha256 prefix below).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "8dd2645e53f05520", "particles": 256, "bytes_per_launch": 2.087e10}
+MEASURED_TRAFFIC = {"sources_sha256": "46f007ec4b1ba03a", "particles": 256, "bytes_per_launch": 2.0872e10}
 
 
 def kernel_sources_sha():
@@ -75,7 +75,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--particles", type=int, default=0, help="0: the workload's own count")
     p.add_argument("--workload", default="positron_spinhalf",
-                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep", "traj", "sampler"])
+                   choices=["positron_spinhalf", "electron_50gev_sections", "pm_mixed", "sweep", "traj", "sampler", "mlp"])
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
@@ -375,6 +375,46 @@ def bench_sampler(args):
     })
 
 
+def bench_mlp(args):
+    """The sampler's network on the GPU: fused inference over every (trajectory, point) pair
+    of the sampler's grid (64 trajectories x 512 energies x 64 x 64 directions) and training
+    steps of 65 536 points; random weights and inputs of the sampler's shapes."""
+    import torch
+    from paper_1910_10391_amd.mlp import MLP
+    n_traj, n_pts = (args.particles or 64), 512 * 64 * 64
+    rng = np.random.default_rng(0)
+    net = MLP(38, 3, seed=1)
+    feat = torch.from_numpy((0.5 * rng.normal(size=(n_traj, 38))).astype(np.float32)).cuda()
+    table = torch.from_numpy(rng.uniform(-1, 1, size=(n_pts, 3)).astype(np.float32)).cuda()
+    y = torch.empty((n_traj, n_pts), dtype=torch.float32, device="cuda")
+    net.forward_grid(feat, table, y=y)
+    dt = timed(lambda: net.forward_grid(feat, table, y=y), max(1, args.steps), torch.cuda.synchronize)
+    pts = n_traj * n_pts
+    # dense products per point: two 256 x 256 layers on the MFMA units, 3 -> 256 and 256 -> 1 on the VALU
+    mfma_flops = 2.0 * 2 * 256 * 256
+    all_flops = mfma_flops + 2.0 * (3 * 256 + 256)
+    B = 65536
+    traj = torch.from_numpy(rng.integers(0, n_traj, B).astype(np.int32)).cuda()
+    x = torch.from_numpy(rng.uniform(-1, 1, size=(B, 3)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(size=B).astype(np.float32)).cuda()
+    net.train_step(feat, traj, x, t, 1e-4)
+    dt_tr = timed(lambda: net.train_step(feat, traj, x, t, 1e-4), 50, torch.cuda.synchronize)
+    print("bench mlp: inference %.1f ms for %d points (%.3e points/s); training step %.2f ms" % (
+        dt * 1e3, pts, pts / dt, dt_tr * 1e3), file=sys.stderr, flush=True)
+    tf = pts * mfma_flops / dt / 1e12
+    return {
+        "metric": "network evaluations (points) per second", "value": pts / dt, "unit": "points/s", "n_gpus": 1,
+        "steps": max(1, args.steps), "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "mlp: 38 features + 3 point inputs -> 256 -> 256 -> 256 -> 1, fused inference over "
+                               "%d trajectories x %d points; training batches of %d" % (n_traj, n_pts, B)},
+        "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
+                     "traffic": None},
+        "all_flops_tflops": pts * all_flops / dt / 1e12,
+        "training_step_ms": dt_tr * 1e3, "training_points_per_s": B / dt_tr,
+    }
+
+
 def sample_points(segs, grid):
     """The bounded sample: 2 shortest + 2 longest trajectories, every 8th photon
     energy, an 8 x 8 strided subset of directions."""
@@ -431,7 +471,7 @@ def main():
     if args.workload != "positron_spinhalf":
         fn = {"electron_50gev_sections": bench_sections, "pm_mixed": bench_pm,
               "sweep": bench_sweep, "traj": bench_traj,
-              "sampler": bench_sampler}[args.workload]
+              "sampler": bench_sampler, "mlp": bench_mlp}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     t_gen = time.perf_counter()
