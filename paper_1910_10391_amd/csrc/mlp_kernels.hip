@@ -288,6 +288,8 @@ __global__ __launch_bounds__(256) void refresh_bf16(const float *__restrict__ p,
 // (w3_fused_column).  BF16 rounding points as in the unfused path.
 constexpr int kFusedRow = kWidth + 8;
 constexpr int kFusedMaxPoint = 8;
+constexpr int kFusedWaves = 8;                     // 2 per SIMD: one block per CU holds the LDS
+constexpr int kFusedThreads = 64 * kFusedWaves;
 
 struct FusedArgs {
     const uint16_t *W1p, *W2, *W3P, *W4;
@@ -300,28 +302,38 @@ struct FusedArgs {
     float *y;
 };
 
+// Round to BF16 (nearest even; the gfx950 conversion instruction) and pack 8 values.
 __device__ __forceinline__ bf16x8 pack_bf16x8(const float v[8])
 {
-    uint32_t w[4];
+    bf16x8 r;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
-    return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+    for (int k = 0; k < 8; ++k) r[k] = (__bf16)v[k];
+    return r;
 }
 
-__global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
+__device__ __forceinline__ float round_bf16(float v) { return (float)(__bf16)v; }
+
+// SiLU with the hardware reciprocal (1 ulp) instead of an IEEE division.
+__device__ __forceinline__ float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+template <int NPMAX>
+__global__ __launch_bounds__(kFusedThreads, 1) void infer_fused_kernel(FusedArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sW2[kWidth * kFusedRow];
     __shared__ float sW1[kWidth * kFusedMaxPoint];
     __shared__ float sb2[kWidth], sb3[kWidth], sW4[kWidth];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < kWidth * (kWidth / 8); i += 256) {
+    for (int i = tid; i < kWidth * (kWidth / 8); i += kFusedThreads) {
         const int r = i / (kWidth / 8), c8 = i % (kWidth / 8);
         *reinterpret_cast<uint4 *>(&sW2[r * kFusedRow + c8 * 8]) =
             *reinterpret_cast<const uint4 *>(&a.W2[r * kWidth + c8 * 8]);
     }
-    for (int i = tid; i < kWidth * a.np; i += 256)
-        sW1[(i / a.np) * kFusedMaxPoint + i % a.np] = bf2f(a.W1p[(i / a.np) * kIn1 + a.nf + i % a.np]);
-    for (int i = tid; i < kWidth; i += 256) {
+    // point weights of layer 1, zero beyond n_point so that every unit runs NPMAX products
+    for (int i = tid; i < kWidth * kFusedMaxPoint; i += kFusedThreads) {
+        const int u = i / kFusedMaxPoint, q = i % kFusedMaxPoint;
+        sW1[i] = q < a.np ? bf2f(a.W1p[u * kIn1 + a.nf + q]) : 0.0f;
+    }
+    for (int i = tid; i < kWidth; i += kFusedThreads) {
         sb2[i] = a.b2[i];
         sb3[i] = a.b3[i];
         sW4[i] = bf2f(a.W4[i]);
@@ -329,7 +341,8 @@ __global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
     __syncthreads();
     const int r = lane & 31, hs = lane >> 5;
     const int64_t n_tiles = (a.B + 31) / 32;
-    for (int64_t tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+    for (int64_t tile = (int64_t)blockIdx.x * kFusedWaves + wave; tile < n_tiles;
+         tile += (int64_t)gridDim.x * kFusedWaves) {
         const int64_t pt = tile * 32 + r;
         const int64_t pc = pt < a.B ? pt : a.B - 1;      // padding lanes recompute the last point
         int64_t t, xi;
@@ -343,18 +356,21 @@ __global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
         const float *cbt = a.cb + (size_t)t * kWidth;
         float xv[kFusedMaxPoint];
 #pragma unroll
-        for (int j = 0; j < kFusedMaxPoint; ++j) xv[j] = j < a.np ? bf2f(f2bf(a.x[(size_t)xi * a.np + j])) : 0.0f;
+        for (int j = 0; j < kFusedMaxPoint; ++j) xv[j] = j < a.np ? round_bf16(a.x[(size_t)xi * a.np + j]) : 0.0f;
         // layer 1: units ks*16 + 8 hs + j of this lane's point, in operand layout
         bf16x8 h1[kWidth / 16];
 #pragma unroll
         for (int ks = 0; ks < kWidth / 16; ++ks) {
+            // one group of 8 units at a time (hoisting all 128 bias loads exhausts registers)
+            __builtin_amdgcn_sched_barrier(0);
             float v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int u = ks * 16 + 8 * hs + j;
                 float z = cbt[u];
-                for (int q = 0; q < a.np; ++q) z += sW1[u * kFusedMaxPoint + q] * xv[q];
-                v[j] = silu(z);
+#pragma unroll
+                for (int q = 0; q < NPMAX; ++q) z += sW1[u * kFusedMaxPoint + q] * xv[q];
+                v[j] = silu_fast(z);
             }
             h1[ks] = pack_bf16x8(v);
         }
@@ -379,27 +395,35 @@ __global__ __launch_bounds__(256, 1) void infer_fused_kernel(FusedArgs a)
                 for (int j = 0; j < 8; ++j) {
                     const int i = 8 * s2 + j;
                     const int u = mt * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
-                    v[j] = silu(acc[i] + sb2[u]);
+                    v[j] = silu_fast(acc[i] + sb2[u]);
                 }
                 h2[2 * mt + s2] = pack_bf16x8(v);
             }
         }
-        // layer 3 with W3's columns in the same order, then the output dot product
+        // layer 3 with W3's columns in the same order, then the output dot product; the W3
+        // operands come from L2 (the second wave on each SIMD covers their latency)
+        __builtin_amdgcn_sched_barrier(0);
+        // this lane's W3 row base, re-derived every tile: the empty asm keeps the compiler
+        // from hoisting the 128 operand addresses out of the tile loop (which would hold
+        // them in registers for the whole kernel)
+        const __attribute__((address_space(1))) uint16_t *w3base =
+            (const __attribute__((address_space(1))) uint16_t *)(a.W3P + (size_t)r * kWidth + 8 * hs);
+        asm volatile("" : "+v"(w3base));
         float ys = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < kWidth / 32; ++mt) {
             __builtin_amdgcn_sched_barrier(0);
+            const __attribute__((address_space(1))) uint16_t *w3 = w3base + (size_t)mt * 32 * kWidth;
             floatx16 acc = {};
-            const uint16_t *w3 = a.W3P + (size_t)(mt * 32 + r) * kWidth + 8 * hs;
 #pragma unroll
-            for (int ks = 0; ks < kWidth / 16; ++ks) {
-                const bf16x8 w = *reinterpret_cast<const bf16x8 *>(w3 + ks * 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, h2[ks], acc, 0, 0, 0);
-            }
+            for (int ks = 0; ks < kWidth / 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    *reinterpret_cast<const __attribute__((address_space(1))) bf16x8 *>(w3 + ks * 16), h2[ks], acc, 0,
+                    0, 0);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int u = mt * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
-                ys += sW4[u] * bf2f(f2bf(silu(acc[i] + sb3[u])));
+                ys += sW4[u] * round_bf16(silu_fast(acc[i] + sb3[u]));
             }
         }
         ys += __shfl_xor(ys, 32, 64);
@@ -508,8 +532,11 @@ hipError_t launch_infer_fused(const uint16_t *W1p, const uint16_t *W2, const uin
     if (np > kFusedMaxPoint || np < 1 || B < 1 || (!traj && n_pts < 1)) return hipErrorInvalidValue;
     FusedArgs a{W1p, W2, W3P, W4, cb, b2, b3, b4, traj, x, nf, np, B, n_pts, y};
     const int64_t tiles = (B + 31) / 32;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (tiles + 3) / 4));
-    hipLaunchKernelGGL(infer_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (tiles + kFusedWaves - 1) / kFusedWaves));
+    if (np <= 4)
+        hipLaunchKernelGGL(infer_fused_kernel<4>, dim3((unsigned)blocks), dim3(kFusedThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(infer_fused_kernel<kFusedMaxPoint>, dim3((unsigned)blocks), dim3(kFusedThreads), 0, st, a);
     return hipGetLastError();
 }
 
