@@ -181,3 +181,42 @@ def test_estimate_matches_oracle(S):
         smp.tau = 1e30
     dIdw, _ = smp.full_grid(ds, precision=rad.FP64)
     assert np.abs(dIdw.cpu().numpy() - full).max() / np.abs(full).max() < 1e-9
+
+
+def test_error_paths(S):
+    """Invalid arguments come back as errors before any launch."""
+    import ctypes
+    import torch
+    from paper_1910_10391_amd import rad
+    from paper_1910_10391_amd.mlp import MLP
+    grid, th = _fine(n=64, n_w=8)
+    pred = torch.zeros((1, 8, 64, 64), dtype=torch.float32, device="cuda")
+    coarse = torch.ones((1, 8, 64), dtype=torch.float64, device="cuda")
+    mask = torch.zeros((1, 8, 64), dtype=torch.uint8, device="cuda")
+    fb = torch.zeros((1, 8), dtype=torch.uint8, device="cuda")
+    L = S._lib()
+    P = rad._dptr
+    args = [grid.handle, 1, P(pred), 0.0, 1.0, P(coarse), 8, 8, 0.99, 16, 0.5, P(mask), P(fb), None, None]
+    assert L.rad_sampler_select(*args) == 0
+    bad = list(args)
+    bad[6] = 3                                            # cells of 3 do not tile 64
+    assert L.rad_sampler_select(*bad) == 1
+    bad = list(args)
+    bad[8] = 1.5                                          # coverage above 1
+    assert L.rad_sampler_select(*bad) == 1
+    big = rad.Grid(grid.hw, analytic.cell_centred(128, 5.0 / 2e4), analytic.cell_centred(128, 5.0 / 2e4))
+    bad = list(args)
+    bad[0] = big.handle                                   # 256 cells: more than one wave
+    assert L.rad_sampler_select(*bad) == 4
+    bad = list(args)
+    bad[5] = None                                         # no coarse values
+    assert L.rad_sampler_select(*bad) == 1
+    seg = _seg(np.linspace(0, 1e-6, 10), np.zeros(10), np.ones(10), 2e4)
+    ds = rad.DeviceSegments([seg])
+    feat = torch.empty((1, S.N_FEATURES), dtype=torch.float32, device="cuda")
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    assert L.rad_features(ds.structs, 1, 0.0, P(feat), P(ws), 256, None) == 1
+    assert L.rad_features(ds.structs, 1, D, P(feat), P(ws), 8, None) == 2
+    net = MLP(34, 9, seed=1)                              # more than 8 point inputs: no grid form
+    with pytest.raises(rad.RadError):
+        net.forward_grid(torch.zeros((2, 34), device="cuda"), torch.zeros((5, 9), device="cuda"))
