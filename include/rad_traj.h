@@ -67,8 +67,11 @@ typedef struct {
  * particle i has n_i + 1 samples.  Pure host computation. */
 rad_status rad_traj_lengths(const rad_traj_params *p, int64_t first, int n_particles, int64_t *out);
 
-/* DEVICE workspace bytes of rad_traj_generate for n_particles. */
-size_t rad_traj_workspace_bytes(int n_particles);
+/* DEVICE workspace bytes of rad_traj_generate for particles first .. first +
+ * n_particles - 1: their descriptors and, with scattering on, the unit normals of
+ * every kick (16 bytes per step and particle, drawn in parallel before the
+ * integration).  0 for invalid arguments. */
+size_t rad_traj_workspace_bytes(const rad_traj_params *p, int64_t first, int n_particles);
 
 /* DEVICE workspace bytes of rad_traj_sections (40 bytes per section). */
 size_t rad_traj_sections_workspace_bytes(int n_particles, int n_sections);
@@ -77,9 +80,10 @@ size_t rad_traj_sections_workspace_bytes(int n_particles, int n_sections);
  * Generate particles first .. first + n_particles - 1 into cols (DEVICE double
  * [RAD_TRAJ_NCOL][total_samples], column-major over all samples: column c of
  * particle i starts at cols + c * total_samples + off_i, off_i = sum_{j<i} (n_j + 1)).
- * total_samples must equal sum_i (n_i + 1) (rad_traj_lengths).  One GPU thread
- * runs each particle; asynchronous on `stream` (returns once the small descriptor
- * upload has completed); deterministic.
+ * total_samples must equal sum_i (n_i + 1) (rad_traj_lengths).  The kick normals
+ * are drawn first, in parallel over (step, particle) (splitmix64 is counter-based),
+ * then one GPU thread integrates each particle; asynchronous on `stream` (returns
+ * once the small descriptor upload has completed); deterministic.
  * RAD_EINVAL on invalid parameters or sizes.
  */
 rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_particles, double *cols,

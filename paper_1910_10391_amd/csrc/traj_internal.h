@@ -31,6 +31,14 @@ struct Stream {
     __host__ __device__ inline double uniform() { return ((double)(next() >> 11) + 1.0) * 0x1.0p-53; }
 };
 
+// splitmix64 is counter-based: draw j (0-based) after a state s is mix(s + (j + 1) g),
+// which lets the kicks of every step be drawn in parallel.
+__host__ __device__ inline double uniform_at(uint64_t s, uint64_t j)
+{
+    Stream r{s + j * 0x9E3779B97F4A7C15ull};
+    return r.uniform();
+}
+
 __host__ __device__ inline Stream particle_stream(uint64_t seed, int64_t particle)
 {
     Stream r;
@@ -60,7 +68,16 @@ struct TrajLaunch {
     int64_t total;
     const TrajDesc *desc;
     double *cols;   // [RAD_TRAJ_NCOL][total]
+    double *kicks;  // [max_steps][n_particles][2] unit normals of the scattering kicks, or null
+    int64_t max_steps;
 };
+
+// Index of a particle's first kick draw in its stream: the step count (when drawn),
+// the entry x, two normals for the entry angles.
+__host__ __device__ inline uint64_t first_kick_draw(const rad_traj_params &p)
+{
+    return (p.n_max > p.n_min ? 1u : 0u) + 5u;
+}
 
 // One section: source samples [k0, k1] of the trajectory at src_off, destination offset.
 struct SecDesc {
@@ -79,6 +96,7 @@ struct SecLaunch {
 };
 
 hipError_t launch_traj(const TrajLaunch &L, hipStream_t st);
+hipError_t launch_kicks(const TrajLaunch &L, hipStream_t st);
 hipError_t launch_sections(const SecLaunch &L, hipStream_t st);
 
 }  // namespace radtraj

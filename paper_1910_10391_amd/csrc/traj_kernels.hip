@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "traj_internal.h"
 
 #pragma clang fp contract(off)
@@ -27,6 +29,26 @@ __device__ inline double gaussian(Stream &r)
 {
     const double u1 = r.uniform(), u2 = r.uniform();
     return sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+}
+
+// The unit normals of every scattering kick, in parallel over (step, particle): the
+// same draws (Box-Muller on uniforms j, j+1 and j+2, j+3 of the particle's stream) that
+// the sequential integration would make, so the trajectories do not change.
+__global__ __launch_bounds__(256) void kicks_kernel(TrajLaunch L)
+{
+    const int64_t total = L.max_steps * L.n_particles;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int pi = (int)(i % L.n_particles);
+        const int64_t k = i / L.n_particles;
+        if (k >= L.desc[pi].n) continue;
+        const uint64_t s = particle_stream(L.p.seed, L.first + pi).s;
+        const uint64_t j = first_kick_draw(L.p) + 4u * (uint64_t)k;
+        const double u1 = uniform_at(s, j), u2 = uniform_at(s, j + 1);
+        const double u3 = uniform_at(s, j + 2), u4 = uniform_at(s, j + 3);
+        L.kicks[2 * i] = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+        L.kicks[2 * i + 1] = sqrt(-2.0 * log(u3)) * cos(2.0 * kPi * u4);
+    }
 }
 
 __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
@@ -103,7 +125,16 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
         }
         if (p.ms_on) {
             const double sig = (p.eps_s_eV / E) * sqrt(h / p.X0_m);
-            const double dtx = sig * gaussian(r), dty = sig * gaussian(r);
+            double gx, gy;
+            if (L.kicks) {
+                const double *kk = L.kicks + 2 * (k * L.n_particles + i);
+                gx = kk[0];
+                gy = kk[1];
+            } else {
+                gx = gaussian(r);
+                gy = gaussian(r);
+            }
+            const double dtx = sig * gx, dty = sig * gy;
             vx += dtx;
             vy += dty;
             if (p.loss_on) E -= kMe_eV * kAlpha / (2.0 * kPi) * g * g * g * (dtx * dtx + dty * dty);
@@ -142,6 +173,14 @@ __global__ __launch_bounds__(256) void sections_kernel(SecLaunch L)
 hipError_t launch_sections(const SecLaunch &L, hipStream_t st)
 {
     hipLaunchKernelGGL(sections_kernel, dim3((unsigned)L.n_sec), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_kicks(const TrajLaunch &L, hipStream_t st)
+{
+    const int64_t total = L.max_steps * L.n_particles;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(kicks_kernel, dim3(blocks), dim3(256), 0, st, L);
     return hipGetLastError();
 }
 

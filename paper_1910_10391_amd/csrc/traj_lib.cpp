@@ -1,6 +1,7 @@
 // librad: host side of the trajectory generator C ABI (include/rad_traj.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -71,9 +72,22 @@ rad_status rad_traj_lengths(const rad_traj_params *p, int64_t first, int n_parti
     return RAD_OK;
 }
 
-size_t rad_traj_workspace_bytes(int n_particles)
+namespace {
+// Workspace: the descriptors, then (with scattering) the kick normals [max_steps][n][2].
+size_t desc_bytes(int n_particles) { return ((sizeof(TrajDesc) * (size_t)n_particles + 255) / 256) * 256; }
+}  // namespace
+
+size_t rad_traj_workspace_bytes(const rad_traj_params *p, int64_t first, int n_particles)
 {
-    return n_particles > 0 ? sizeof(TrajDesc) * (size_t)n_particles : 0;
+    if (!p || n_particles <= 0 || first < 0 || check_params(p) != RAD_OK) return 0;
+    int64_t max_steps = 0;
+    for (int i = 0; i < n_particles; ++i) {
+        Stream r = particle_stream(p->seed, first + i);
+        max_steps = std::max<int64_t>(max_steps, draw_steps(*p, r));
+    }
+    size_t b = desc_bytes(n_particles);
+    if (p->ms_on) b += sizeof(double) * 2 * (size_t)max_steps * (size_t)n_particles;
+    return b;
 }
 
 rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_particles, double *cols,
@@ -83,27 +97,31 @@ rad_status rad_traj_generate(const rad_traj_params *p, int64_t first, int n_part
     if (rs != RAD_OK) return rs;
     if (n_particles <= 0 || first < 0) return tfail(RAD_EINVAL, "need n_particles > 0 and first >= 0");
     std::vector<TrajDesc> desc(n_particles);
-    int64_t off = 0;
+    int64_t off = 0, max_steps = 0;
     for (int i = 0; i < n_particles; ++i) {
         Stream r = particle_stream(p->seed, first + i);
         desc[i].n = draw_steps(*p, r);
         desc[i].off = off;
         off += desc[i].n + 1;
+        max_steps = std::max<int64_t>(max_steps, desc[i].n);
     }
     if (off != total_samples)
         return tfail(RAD_EINVAL, "total_samples is %lld, the particles have %lld", (long long)total_samples,
                      (long long)off);
-    const size_t need = rad_traj_workspace_bytes(n_particles);
+    const size_t need = rad_traj_workspace_bytes(p, first, n_particles);
     if (ws_bytes < need) return tfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     if ((rs = trange(ws, need, "workspace")) != RAD_OK) return rs;
     if ((rs = trange(cols, (size_t)RAD_TRAJ_NCOL * (size_t)total_samples * sizeof(double), "cols")) != RAD_OK)
         return rs;
+    double *kicks = p->ms_on ? (double *)((char *)ws + desc_bytes(n_particles)) : nullptr;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t copied = nullptr;
     hipError_t e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws, desc.data(), need, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws, desc.data(), sizeof(TrajDesc) * desc.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(copied, st);
-    TrajLaunch L{*p, first, n_particles, total_samples, (const TrajDesc *)ws, cols};
+    TrajLaunch L{*p, first, n_particles, total_samples, (const TrajDesc *)ws, cols, kicks, max_steps};
+    if (e == hipSuccess && kicks) e = launch_kicks(L, st);
     if (e == hipSuccess) e = launch_traj(L, st);
     // the descriptors are pageable host memory: wait for their copy (not the kernel)
     if (e == hipSuccess) e = hipEventSynchronize(copied);

@@ -32,7 +32,7 @@ def _lib():
         L.rad_traj_lengths.restype = I
         L.rad_traj_lengths.argtypes = [PP, I64, I, ctypes.POINTER(ctypes.c_int64)]
         L.rad_traj_workspace_bytes.restype = S
-        L.rad_traj_workspace_bytes.argtypes = [I]
+        L.rad_traj_workspace_bytes.argtypes = [PP, I64, I]
         L.rad_traj_generate.restype = I
         L.rad_traj_generate.argtypes = [PP, I64, I, P, I64, P, S, P]
         L.rad_traj_sections_workspace_bytes.restype = S
@@ -74,8 +74,9 @@ class DeviceTrajectories(rad.DeviceSegments):
         n_full = [int(s_) + 1 for s_ in steps]
         total = int(sum(n_full))
         self.traj_data = torch.empty((NCOL, total), dtype=torch.float64, device=device)
-        ws = torch.empty(max(1, int(_lib().rad_traj_workspace_bytes(int(n_particles)))), dtype=torch.uint8,
-                         device=device)
+        ws = torch.empty(max(1, int(_lib().rad_traj_workspace_bytes(ctypes.byref(p), int(first),
+                                                                       int(n_particles)))),
+                         dtype=torch.uint8, device=device)
         rad._check(_lib().rad_traj_generate(ctypes.byref(p), int(first), int(n_particles),
                                             rad._dptr(self.traj_data), total, rad._dptr(ws), ws.numel(),
                                             rad._stream(stream)), "rad_traj_generate")

@@ -64,3 +64,16 @@ def test_sections_validation_before_any_device_call(T):
                                None) == 1
     assert b"total_section_samples" in rad.lib().rad_last_error()
     assert L.rad_traj_sections_workspace_bytes(4, 5) == 40 * 20
+
+
+def test_workspace_holds_descriptors_and_kicks(T):
+    L = T._lib()
+    cfg = presets.positron_config()
+    p = T.params(cfg)
+    n = T.lengths(cfg, 10, 3)
+    got = L.rad_traj_workspace_bytes(ctypes.byref(p), 3, 10)
+    desc = ((16 * 10 + 255) // 256) * 256
+    assert got == desc + 16 * int(n.max()) * 10
+    p = T.params(dataclasses.replace(cfg, ms_on=False))
+    assert L.rad_traj_workspace_bytes(ctypes.byref(p), 3, 10) == desc
+    assert L.rad_traj_workspace_bytes(ctypes.byref(p), 3, 0) == 0
