@@ -26,14 +26,23 @@ Plain NumPy loops over the definitions:
                    cells in decreasing (scaled) predicted mass while the mass ahead
                    of a cell is below coverage x the total, at most ``cap`` cells;
                    then widened to whole blocks of 64 photon energies.
+* ``select_error`` -- error-driven selection: the network's sub-cell shape corrects
+                   each exact centre value, E_c = C_c M_c / P_c (M_c the predicted
+                   cell mass, P_c the predicted centre value; C_c A_c where P_c is
+                   0), whose distance from the plain midpoint value, e_c =
+                   |E_c - C_c A_c|, estimates the error of leaving the cell out.
+                   Cells are taken in decreasing e_c while the estimated error of
+                   the cells not yet taken exceeds eps x sum_c E_c, at most ``cap``;
+                   widened to blocks of 64 energies as in ``select``.
 * ``combine``   -- exact cell integrals where selected; elsewhere the predicted
-                   cell mass, or the coarse centre value x cell area.
+                   cell mass (or E_c), or the coarse centre value x cell area.
 
 These steps are the sampler's bookkeeping around the radiation integrals of
 Sec. II (the integrals themselves are the direct-sum oracle in ``oracle``); the
 network's prediction is an input here.  Pinned in ``tests/test_oracle_sampler.py``
 by closed forms (a pure sinusoid's amplitude and frequency), hand-worked
-selections and the exactness of the combination when every cell is selected.
+selections, the exactness of the combination when every cell is selected, and the
+exactness of the error-driven estimate when the prediction is the true map.
 """
 from __future__ import annotations
 
@@ -143,10 +152,44 @@ def select(pred, mu, sigma, coarse, wx, wy, cx, cy, coverage, cap, tau):
                     break
                 mask[s, w, c] = 1
                 ahead += pm[s, w, c]
-    for b0 in range(0, n_w, WBLOCK):
+    return widen(mask), fb, pm
+
+
+def widen(mask):
+    """A cell selected for one energy of a block of 64 is selected for all of them (in place)."""
+    for b0 in range(0, mask.shape[1], WBLOCK):
         blk = mask[:, b0:b0 + WBLOCK, :]
         mask[:, b0:b0 + WBLOCK, :] = np.repeat(blk.max(axis=1, keepdims=True), blk.shape[1], axis=1)
-    return mask, fb, pm
+    return mask
+
+
+def select_error(pred, mu, sigma, coarse, wx, wy, cx, cy, eps, cap):
+    """Error-driven selection: mask [n_traj, n_w, n_cells] (uint8) and the cell estimates E_c
+    [n_traj, n_w, n_cells] that stand in for the cells left out."""
+    pred = np.asarray(pred, dtype=np.float64)
+    n_traj, n_w = pred.shape[:2]
+    intensity = np.exp(mu + sigma * pred)
+    pm = cell_sums(intensity, wx, wy, cx, cy)
+    pc = centre_values(intensity, cx, cy)
+    area = cell_areas(wx, wy, cx, cy)
+    coarse = np.asarray(coarse, dtype=np.float64)
+    n_cells = pm.shape[-1]
+    mask = np.zeros((n_traj, n_w, n_cells), dtype=np.uint8)
+    est = np.zeros((n_traj, n_w, n_cells))
+    for s in range(n_traj):
+        for w in range(n_w):
+            for c in range(n_cells):
+                mid = coarse[s, w, c] * area[c]
+                est[s, w, c] = coarse[s, w, c] * pm[s, w, c] / pc[s, w, c] if pc[s, w, c] > 0 else mid
+            e = [abs(est[s, w, c] - coarse[s, w, c] * area[c]) for c in range(n_cells)]
+            budget = eps * est[s, w].sum()
+            order = sorted(range(n_cells), key=lambda c: (-e[c], c))
+            for r, c in enumerate(order):
+                left = sum(e[j] for j in order[r:])      # estimated error of the cells not yet taken
+                if r >= cap or not left > budget:
+                    break
+                mask[s, w, c] = 1
+    return widen(mask), est
 
 
 def combine(cells, mask, coarse, wx, wy, cx, cy, cell_pred=None):

@@ -160,3 +160,87 @@ def test_cell_sums_order():
     v[3, 4] = 1.0                                           # row 3, column 4 -> cj 1, ci 2
     c = osm.cell_sums(v, np.ones(6), np.ones(4), 2, 2)
     assert c.tolist() == [0, 0, 0, 0, 0, 1.0]
+
+
+def _two_odd_cells(cell0, cell1):
+    """1 trajectory, 1 energy, a 6 x 3 fine grid of unit widths split into two 3 x 3 cells;
+    cellN gives the 3 x 3 intensities (row-major) of cell N."""
+    v = np.zeros((3, 6))
+    v[:, :3] = np.asarray(cell0, dtype=np.float64).reshape(3, 3)
+    v[:, 3:] = np.asarray(cell1, dtype=np.float64).reshape(3, 3)
+    return v.reshape(1, 1, 3, 6)
+
+
+def test_select_error_hand_worked():
+    """Cell 0 flat, cell 1 with its centre at 1 and the other eight directions at 2: the
+    corrected estimate of cell 1 is C_1 x 17 / 1 against the midpoint C_1 x 9, an estimated
+    error of 8 C_1; cell 0 has none.  With C = (1, 1), sum E = 9 + 17 = 26."""
+    v = _two_odd_cells(np.ones(9), [2, 2, 2, 2, 1, 2, 2, 2, 2])
+    pred = np.log(v)
+    coarse = np.array([1.0, 1.0]).reshape(1, 1, 2)
+    wx, wy = np.ones(6), np.ones(3)
+    mask, est = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.3, cap=2)
+    assert np.allclose(est[0, 0], [9.0, 17.0], rtol=1e-15)
+    assert mask[0, 0].tolist() == [0, 1]                    # 8 > 0.3 x 26 = 7.8
+    mask, _ = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.31, cap=2)
+    assert mask[0, 0].tolist() == [0, 0]                    # 8 <= 0.31 x 26 = 8.06
+    # the prediction is a shape: mu changes nothing; the exact centre values set the scale
+    mask, est = osm.select_error(pred - 7.0, 7.0, 1.0, 3.0 * coarse, wx, wy, 3, 3, eps=0.3, cap=2)
+    assert np.allclose(est[0, 0], [27.0, 51.0], rtol=1e-14) and mask[0, 0].tolist() == [0, 1]
+    # sigma sharpens the shape: sigma = 2 squares it, cell 1 -> (8 x 4 + 1) / 1 = 33
+    _, est = osm.select_error(pred, 0.0, 2.0, coarse, wx, wy, 3, 3, eps=0.3, cap=2)
+    assert np.allclose(est[0, 0], [9.0, 33.0], rtol=1e-14)
+    # a centre predicted at zero intensity: the midpoint value stands in, no estimated error
+    pred0 = pred.copy()
+    pred0[0, 0, 1, 4] = -np.inf
+    mask, est = osm.select_error(pred0, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.0, cap=2)
+    assert est[0, 0].tolist() == [9.0, 9.0] and mask[0, 0].tolist() == [0, 0]
+
+
+def test_select_error_ranking_and_cap():
+    """Three odd cells with estimated errors 8, 4 and 0 (C = 1): with eps = 0 every cell with
+    an error is taken, largest first, within the cap."""
+    v = np.zeros((3, 9))
+    v[:, 0:3] = 1.0
+    v[:, 3:6] = [[2, 2, 2], [2, 1, 2], [2, 2, 2]]           # 17 vs 9: error 8
+    v[:, 6:9] = [[1.5, 1.5, 1.5], [1.5, 1, 1.5], [1.5, 1.5, 1.5]]   # 13 vs 9: error 4
+    pred = np.log(v).reshape(1, 1, 3, 9)
+    coarse = np.ones((1, 1, 3))
+    wx, wy = np.ones(9), np.ones(3)
+    mask, est = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.0, cap=3)
+    assert np.allclose(est[0, 0], [9.0, 17.0, 13.0], rtol=1e-15)
+    assert mask[0, 0].tolist() == [0, 1, 1]
+    mask, _ = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.0, cap=1)
+    assert mask[0, 0].tolist() == [0, 1, 0]
+    # left after taking cell 1: 4 > eps x 39 for eps < 4/39; before: 12 > eps x 39
+    mask, _ = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.1, cap=3)
+    assert mask[0, 0].tolist() == [0, 1, 1]
+    mask, _ = osm.select_error(pred, 0.0, 1.0, coarse, wx, wy, 3, 3, eps=0.11, cap=3)
+    assert mask[0, 0].tolist() == [0, 1, 0]
+
+
+def test_select_error_exact_for_a_perfect_prediction():
+    """When the prediction is the true map (odd cells: the centre value is the middle
+    direction), every corrected estimate is the exact cell integral, so the combination is
+    exact with no cell refined."""
+    rng = np.random.default_rng(3)
+    n_w, cx = 5, 3
+    v = rng.random((2, n_w, 9, 12)) + 0.05
+    wx, wy = rng.random(12) + 0.5, rng.random(9) + 0.5
+    coarse = v[:, :, 1::3, 1::3].reshape(2, n_w, 12)        # the middle direction of each cell
+    mask, est = osm.select_error(np.log(v), 0.0, 1.0, coarse, wx, wy, cx, cx, eps=1.0, cap=12)
+    assert not mask.any()
+    exact = np.einsum("swyx,y,x->sw", v, wy, wx)
+    got = osm.combine(np.zeros_like(est), mask, coarse, wx, wy, cx, cx, cell_pred=est)
+    assert np.allclose(got, exact, rtol=1e-13)
+
+
+def test_select_error_widens_to_energy_blocks():
+    """A cell taken at one energy of a 64-energy block is taken at all of them."""
+    v = np.ones((1, 70, 3, 6))
+    v[0, 10, :, 3:] = [[2, 2, 2], [2, 1, 2], [2, 2, 2]]
+    v[0, 66, :, :3] = [[2, 2, 2], [2, 1, 2], [2, 2, 2]]
+    coarse = np.ones((1, 70, 2))
+    mask, _ = osm.select_error(np.log(v), 0.0, 1.0, coarse, np.ones(6), np.ones(3), 3, 3, eps=0.01, cap=2)
+    assert mask[0, :64, 1].all() and not mask[0, :64, 0].any()
+    assert mask[0, 64:, 0].all() and not mask[0, 64:, 1].any()
