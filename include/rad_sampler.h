@@ -6,9 +6,12 @@
  * (rad_batch on a coarse grid), (2) the MLP's predicted log intensity at every
  * fine direction (include/rad_mlp.h), (3) exact cell integrals on the cells the
  * prediction selects (rad_cells in include/rad.h); cells left out count as their
- * predicted mass or their centre value times their area.  A prediction that
- * disagrees with the exact centre values makes a photon energy fall back to the
- * full grid, the exact reference.  Conventions as in rad.h.
+ * predicted mass, their centre value times their area, or their centre value
+ * corrected by the predicted sub-cell shape.  Two selection rules: by predicted
+ * mass (rad_sampler_select, where a prediction that disagrees with the exact centre
+ * values makes a photon energy fall back to the full grid, the exact reference),
+ * and by the predicted error of the midpoint value (rad_sampler_select_error).
+ * Conventions as in rad.h.
  */
 #ifndef RAD_SAMPLER_H
 #define RAD_SAMPLER_H
@@ -64,10 +67,33 @@ rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pre
                               uint8_t *mask, uint8_t *fallback, double *cell_pred, void *stream);
 
 /*
+ * Error-driven cell selection, with the inputs of rad_sampler_select.  The
+ * predicted sub-cell shape corrects each exact centre value: with M_c the predicted
+ * cell mass (sum over the cell's fine directions of exp(mu + sigma pred) x dthx
+ * dthy) and P_c the predicted centre value, the cell estimate is
+ * E_c = coarse_c M_c / P_c (coarse_c A_c where P_c is 0); it does not depend on the
+ * prediction's scale, and it is the exact cell integral when the prediction is the
+ * true map and the centre value is a fine direction (odd cells).  e_c = |E_c -
+ * coarse_c A_c| estimates the error of leaving the cell at its midpoint value.
+ * Cells are taken in decreasing e_c (ties by index) while the estimated error of
+ * the cells not yet taken (e_c plus that of every cell after it) exceeds
+ * eps * sum_c E_c, at most `cap` cells; then widened to blocks of 64 photon
+ * energies as in rad_sampler_select.  Writes mask (DEVICE uint8
+ * [n_traj][n_w][n_cells]) and cell_est (DEVICE double [n_traj][n_w][n_cells],
+ * E_c, to pass to rad_sampler_combine as cell_pred).  No fallback check.  eps >= 0,
+ * cap >= 1; n_cells <= 64.  This rule is not in the paper (it extends the angular
+ * grid of Sec. IV).
+ */
+rad_status rad_sampler_select_error(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
+                                    const double *coarse, int cx, int cy, float eps, int cap, uint8_t *mask,
+                                    double *cell_est, void *stream);
+
+/*
  * dIdw (DEVICE double [n_traj][n_w]) = sum over cells of the exact cell integral
  * (cells, DEVICE [n_traj][n_w][n_cells], from rad_cells) where mask is set; else
- * the predicted cell mass (cell_pred from rad_sampler_select) if cell_pred is not
- * NULL, else the coarse centre value times the cell's area.
+ * cell_pred (the predicted cell masses of rad_sampler_select or the estimates E_c of
+ * rad_sampler_select_error) if it is not NULL, else the coarse centre value times
+ * the cell's area.
  */
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
                                const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,

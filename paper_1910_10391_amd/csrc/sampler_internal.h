@@ -30,11 +30,11 @@ struct SelectLaunch {
     const double *coarse;  // [n_traj][n_w][n_cells] spectrum at the cell centres
     const double *wx, *wy; // direction cell widths of the fine grid
     int n_traj, n_w, n_x, n_y, cx, cy, n_cells;
-    float coverage, tau;
+    float coverage, tau;   // coverage: eps in the error-driven selection
     int cap;
     uint8_t *mask;         // [n_traj][n_w][n_cells]
     uint8_t *fallback;     // [n_traj][n_w]
-    double *cell_pred;     // [n_traj][n_w][n_cells] predicted cell masses, or null
+    double *cell_pred;     // [n_traj][n_w][n_cells] predicted cell masses (or estimates E_c), or null
 };
 
 struct CombineLaunch {
@@ -47,6 +47,7 @@ struct CombineLaunch {
 
 hipError_t launch_features(const FeatLaunch &F, int n_segs, hipStream_t st);
 hipError_t launch_select(const SelectLaunch &L, hipStream_t st);
+hipError_t launch_select_error(const SelectLaunch &L, hipStream_t st);
 hipError_t launch_widen(uint8_t *mask, int n_traj, int n_w, int n_cells, hipStream_t st);
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t st);
 

@@ -115,58 +115,66 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
 }
 
 // ---------------------------------------------------------------- selection
+// The network's view of cell c of item (trajectory, photon energy), from the
+// predicted intensities exp(mu + sigma * pred) of its fine directions: the mass
+// pm (sum of value x dthx dthy), the centre value pc (mean value of the fine
+// directions nearest the centre: the central 2 x 2 of an even cell, the middle
+// point of an odd one) and the cell area.
+__device__ __forceinline__ void cell_prediction(const SelectLaunch &L, int64_t item, int c, double &pm,
+                                                double &pc, double &area)
+{
+    const int ncx = L.n_x / L.cx;
+    const int ci = c % ncx, cj = c / ncx;
+    const float *pred = L.pred + item * (int64_t)L.n_x * L.n_y;
+    const int xa = (L.cx - 1) / 2, xb = L.cx / 2, ya = (L.cy - 1) / 2, yb = L.cy / 2;
+    int npc = 0;
+    pm = pc = area = 0.0;
+    for (int jy = 0; jy < L.cy; ++jy)
+        for (int jx = 0; jx < L.cx; ++jx) {
+            const int gx = ci * L.cx + jx, gy = cj * L.cy + jy;
+            const double v = exp((double)L.mu + (double)L.sigma * (double)pred[(int64_t)gy * L.n_x + gx]);
+            const double dA = L.wx[gx] * L.wy[gy];
+            pm += v * dA;
+            area += dA;
+            if ((jx == xa || jx == xb) && (jy == ya || jy == yb)) {
+                pc += v;
+                ++npc;
+            }
+        }
+    pc /= (double)npc;
+}
+
+// Wave-wide sums over the cells of one item.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // One wave per (trajectory, photon energy); lane c < n_cells owns cell c.  The
-// network predicts the angular shape, exp(mu + sigma * yhat) up to a scale; the
-// scale lambda comes from the exact spectrum at the cell centres C_c:
-// lambda = sum_c C_c A_c / sum_c P_c A_c, with P_c the mean predicted value of the
-// fine directions nearest the centre (the central 2 x 2 of an even cell, the middle
-// point of an odd one) and A_c the cell area.  Check: the energy falls back to the
-// full grid (every cell selected) when sum_c |lambda P_c - C_c| A_c exceeds
-// tau sum_c C_c A_c (or either sum is 0).  Otherwise cells are taken in decreasing
-// predicted mass (lambda times the sum over the cell's fine directions of the
-// predicted value times dthx dthy; ties by index) while the mass before them is
-// below coverage times the total, at most `cap` of them.
+// network predicts the angular shape up to a scale; the scale lambda comes from
+// the exact spectrum at the cell centres C_c: lambda = sum_c C_c A_c / sum_c P_c A_c
+// (P_c the predicted centre value, A_c the cell area).  Check: the energy falls
+// back to the full grid (every cell selected) when sum_c |lambda P_c - C_c| A_c
+// exceeds tau sum_c C_c A_c (or either sum is 0).  Otherwise cells are taken in
+// decreasing predicted mass (lambda times the predicted cell mass; ties by index)
+// while the mass before them is below coverage times the total, at most `cap`.
 __global__ __launch_bounds__(256) void select_kernel(SelectLaunch L)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;   // traj * n_w + w
     if (item >= (int64_t)L.n_traj * L.n_w) return;
-    const int ncx = L.n_x / L.cx;
     const int c = lane;
     const bool live = c < L.n_cells;
     double pm = 0.0, pc = 0.0, cc = 0.0, area = 0.0;
     if (live) {
-        const int ci = c % ncx, cj = c / ncx;
-        const float *pred = L.pred + item * (int64_t)L.n_x * L.n_y;
-        const int xa = (L.cx - 1) / 2, xb = L.cx / 2, ya = (L.cy - 1) / 2, yb = L.cy / 2;
-        int npc = 0;
-        for (int jy = 0; jy < L.cy; ++jy)
-            for (int jx = 0; jx < L.cx; ++jx) {
-                const int gx = ci * L.cx + jx, gy = cj * L.cy + jy;
-                const double v = exp((double)L.mu + (double)L.sigma * (double)pred[(int64_t)gy * L.n_x + gx]);
-                const double dA = L.wx[gx] * L.wy[gy];
-                pm += v * dA;
-                area += dA;
-                if ((jx == xa || jx == xb) && (jy == ya || jy == yb)) {
-                    pc += v;
-                    ++npc;
-                }
-            }
-        pc /= (double)npc;
+        cell_prediction(L, item, c, pm, pc, area);
         cc = L.coarse[item * L.n_cells + c];
     }
-    double P = pc * area, C = cc * area;
-    for (int off = 32; off > 0; off >>= 1) {
-        P += __shfl_xor(P, off, 64);
-        C += __shfl_xor(C, off, 64);
-    }
+    const double P = wave_sum(pc * area), C = wave_sum(cc * area);
     const double lambda = P > 0.0 ? C / P : 0.0;
     pm *= lambda;
-    double D = fabs(lambda * pc - cc) * area, Mp = pm;
-    for (int off = 32; off > 0; off >>= 1) {
-        D += __shfl_xor(D, off, 64);
-        Mp += __shfl_xor(Mp, off, 64);
-    }
+    const double D = wave_sum(fabs(lambda * pc - cc) * area), Mp = wave_sum(pm);
     if (live && L.cell_pred) L.cell_pred[item * L.n_cells + c] = pm;
     const bool fb = !(C > 0.0) || !(P > 0.0) || D > (double)L.tau * C;
     // rank and predicted mass ahead of this cell
@@ -184,6 +192,43 @@ __global__ __launch_bounds__(256) void select_kernel(SelectLaunch L)
     const bool sel = live && (fb || (rank < L.cap && ahead < (double)L.coverage * Mp));
     if (live) L.mask[item * L.n_cells + c] = sel ? 1 : 0;
     if (lane == 0) L.fallback[item] = fb ? 1 : 0;
+}
+
+// Error-driven selection, same layout: the predicted sub-cell shape corrects the
+// exact centre value, E_c = C_c pm_c / pc_c (C_c A_c where pc_c is 0; the ratio
+// does not depend on the prediction's scale), and e_c = |E_c - C_c A_c| estimates
+// the error of leaving the cell at its midpoint value.  Cells are taken in
+// decreasing e_c (ties by index) while the estimated error of the cells not yet
+// taken, sum of e_j over this cell and those after it, exceeds eps sum_c E_c, at
+// most `cap`.  E_c goes to cell_pred for the combination.
+__global__ __launch_bounds__(256) void select_error_kernel(SelectLaunch L)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    if (item >= (int64_t)L.n_traj * L.n_w) return;
+    const int c = lane;
+    const bool live = c < L.n_cells;
+    double est = 0.0, e = 0.0;
+    if (live) {
+        double pm, pc, area;
+        cell_prediction(L, item, c, pm, pc, area);
+        const double cc = L.coarse[item * L.n_cells + c];
+        const double mid = cc * area;
+        est = pc > 0.0 ? cc * pm / pc : mid;
+        e = fabs(est - mid);
+        L.cell_pred[item * L.n_cells + c] = est;
+    }
+    const double budget = (double)L.coverage * wave_sum(est);
+    int rank = 0;
+    double left = 0.0;
+    for (int j = 0; j < 64; ++j) {
+        const double ej = __shfl(e, j, 64);
+        const bool lj = j < L.n_cells;
+        const bool before = lj && (ej > e || (ej == e && j < c));
+        if (before) ++rank;
+        else if (lj) left += ej;
+    }
+    if (live) L.mask[item * L.n_cells + c] = (rank < L.cap && left > budget) ? 1 : 0;
 }
 
 // Widen the selection to whole blocks of kWBlock photon energies: rad_cells
@@ -243,6 +288,13 @@ hipError_t launch_select(const SelectLaunch &L, hipStream_t st)
 {
     const int64_t items = (int64_t)L.n_traj * L.n_w;
     hipLaunchKernelGGL(select_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_error(const SelectLaunch &L, hipStream_t st)
+{
+    const int64_t items = (int64_t)L.n_traj * L.n_w;
+    hipLaunchKernelGGL(select_error_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, L);
     return hipGetLastError();
 }
 

@@ -120,6 +120,30 @@ rad_status rad_sampler_select(const rad_grid *fine, int n_traj, const float *pre
     return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "select: %s", hipGetErrorString(e));
 }
 
+rad_status rad_sampler_select_error(const rad_grid *fine, int n_traj, const float *pred, float mu, float sigma,
+                                    const double *coarse, int cx, int cy, float eps, int cap, uint8_t *mask,
+                                    double *cell_est, void *stream)
+{
+    rad::GridView v;
+    rad_status rs = view_of(fine, v);
+    if (rs != RAD_OK) return rs;
+    int n_cells = 0;
+    if ((rs = cells_shape(v, cx, cy, n_cells)) != RAD_OK) return rs;
+    if (n_traj <= 0) return sfail(RAD_EINVAL, "n_traj must be > 0");
+    if (!(eps >= 0.0f) || !std::isfinite(eps) || cap < 1 || !std::isfinite(mu) || !std::isfinite(sigma))
+        return sfail(RAD_EINVAL, "invalid eps, cap, mu or sigma");
+    const size_t items = (size_t)n_traj * v.n_w;
+    if ((rs = srange(pred, items * v.n_x * v.n_y * sizeof(float), "pred")) != RAD_OK) return rs;
+    if ((rs = srange(coarse, items * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
+    if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
+    if ((rs = srange(cell_est, items * n_cells * sizeof(double), "cell_est")) != RAD_OK) return rs;
+    SelectLaunch L{pred, mu, sigma, coarse, v.wx, v.wy, n_traj, v.n_w, v.n_x, v.n_y, cx, cy, n_cells,
+                   eps, 0.0f, cap, mask, nullptr, cell_est};
+    hipError_t e = launch_select_error(L, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_widen(mask, n_traj, v.n_w, n_cells, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "select_error: %s", hipGetErrorString(e));
+}
+
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
                                const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,
                                void *stream)

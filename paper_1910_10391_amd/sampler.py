@@ -10,9 +10,12 @@ n x n grid of directions within +-H/gamma from
    ``rad_features`` and (log hw, gamma thx, gamma thy)), scaled to the exact centre
    values,
 3. exact integrals over the cells the prediction ranks highest, until 99 % of the
-   predicted intensity is covered (``rad_sampler_select``, ``rad_cells``),
-4. for the remaining cells the predicted cell mass (``fill="pred"``) or the coarse
-   value times the area (``fill="coarse"``) (``rad_sampler_combine``).
+   predicted intensity is covered (``rad_sampler_select``, ``rad_cells``), or over
+   the cells whose midpoint value the predicted sub-cell shape says is furthest off,
+   until the estimated error left is small (``rad_sampler_select_error``),
+4. for the remaining cells the predicted cell mass (``fill="pred"``), the coarse
+   value times the area (``fill="coarse"``) or, with the error-driven rule, the
+   centre value corrected by the predicted sub-cell shape (``rad_sampler_combine``).
 
 When the scaled prediction at the cell centres deviates from the exact centre
 values by more than ``tau`` (relative L1 norm) a photon energy falls back to the
@@ -48,6 +51,7 @@ def _lib():
         sig = {
             "rad_features": (I, [ctypes.POINTER(rad.Segment), I, D, P, P, S, P]),
             "rad_sampler_select": (I, [P, I, P, F, F, P, I, I, F, I, F, P, P, P, P]),
+            "rad_sampler_select_error": (I, [P, I, P, F, F, P, I, I, F, I, P, P, P]),
             "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -121,13 +125,16 @@ def predict(mlp, grids, feat, chunk_points=1 << 27):
 class Sampler:
     """The learned sampler for one kind of workload (fixed grids and normalisation)."""
 
-    def __init__(self, mlp, norm, grids, plane_spacing_m, coverage=0.99, cap=16, tau=0.25, fill="pred"):
+    def __init__(self, mlp, norm, grids, plane_spacing_m, coverage=0.99, cap=16, tau=0.25, fill="pred",
+                 select="mass", eps=1e-3):
         self.mlp, self.norm, self.grids = mlp, dict(norm), grids
         self.d = float(plane_spacing_m)
         self.coverage, self.cap, self.tau = float(coverage), int(cap), float(tau)
         if fill not in ("pred", "coarse"):
             raise ValueError("fill must be 'pred' or 'coarse'")
-        self.fill = fill
+        if select not in ("mass", "error"):
+            raise ValueError("select must be 'mass' or 'error'")
+        self.fill, self.select_rule, self.eps = fill, select, float(eps)
 
     def coarse(self, dsegs, precision):
         n = len(dsegs)
@@ -150,6 +157,20 @@ class Sampler:
             rad._stream(None)), "rad_sampler_select")
         return mask, fb, pm
 
+    def select_error(self, pred, coarse, eps=None, cap=None):
+        """mask and cell estimates E_c (rad_sampler_select_error)."""
+        import torch
+        n = pred.shape[0]
+        g = self.grids
+        mask = torch.empty((n, g.hw.size, g.n_cells), dtype=torch.uint8, device="cuda")
+        est = torch.empty((n, g.hw.size, g.n_cells), dtype=torch.float64, device="cuda")
+        rad._check(_lib().rad_sampler_select_error(
+            g.fine.handle, n, rad._dptr(pred), float(self.norm["mu"]), float(self.norm["sigma"]),
+            rad._dptr(coarse), CELL, CELL, float(self.eps if eps is None else eps),
+            int(self.cap if cap is None else cap), rad._dptr(mask), rad._dptr(est), rad._stream(None)),
+            "rad_sampler_select_error")
+        return mask, est
+
     def combine(self, cells, mask, coarse, cell_pred=None):
         """dI/dhw: exact cells where selected, else cell_pred (if given) or centre x area."""
         import torch
@@ -164,7 +185,10 @@ class Sampler:
     def estimate(self, dsegs, precision=rad.MIXED, rule="learned"):
         """dI/d hw [n_traj, n_w] and what it cost.
 
-        rule "learned": cells ranked by the network's prediction (the sampler);
+        rule "learned": cells chosen with the network's prediction (the sampler): by
+                        predicted mass (``select="mass"``) or by the predicted error of
+                        the midpoint value (``select="error"``, cells left out at their
+                        corrected estimate);
         rule "coarse":  cells ranked by the coarse centre value x area, with the same
                         coverage and cap and no fallback (refinement without a network,
                         the comparison the sampler has to beat)."""
@@ -185,8 +209,12 @@ class Sampler:
             feat = features(dsegs, self.d)
             pred = predict(self.mlp, g, feat)
             t = mark("features_predict", t)
-            mask, fb, pm = self.select(pred, coarse)
-            fill = pm if self.fill == "pred" else None
+            if self.select_rule == "error":
+                mask, fill = self.select_error(pred, coarse)
+                fb = torch.zeros(mask.shape[:2], dtype=torch.uint8)
+            else:
+                mask, fb, pm = self.select(pred, coarse)
+                fill = pm if self.fill == "pred" else None
         elif rule == "coarse":
             k = g.n // CELL
             lc = torch.log(coarse.float()).view(len(dsegs), g.hw.size, k, k)
@@ -227,7 +255,8 @@ class Sampler:
         np.savez(path, params=theta, mu=self.norm["mu"], sigma=self.norm["sigma"],
                  logw_mean=self.grids.logw_norm[0], logw_std=self.grids.logw_norm[1],
                  n_fine=self.grids.n, half_width=self.grids.H, plane_spacing=self.d,
-                 coverage=self.coverage, cap=self.cap, tau=self.tau, fill=self.fill)
+                 coverage=self.coverage, cap=self.cap, tau=self.tau, fill=self.fill, select=self.select_rule,
+                 eps=self.eps)
 
     @classmethod
     def load(cls, path, hw_eV, gamma):
@@ -236,8 +265,9 @@ class Sampler:
                           logw_norm=(float(z["logw_mean"]), float(z["logw_std"])))
             mlp = MLP(N_FEATURES, 3)
             mlp.set_params(z["params"])
+            extra = dict(select=str(z["select"]), eps=float(z["eps"])) if "select" in z.files else {}
             return cls(mlp, dict(mu=float(z["mu"]), sigma=float(z["sigma"])), grids, float(z["plane_spacing"]),
-                       float(z["coverage"]), int(z["cap"]), float(z["tau"]), str(z["fill"]))
+                       float(z["coverage"]), int(z["cap"]), float(z["tau"]), str(z["fill"]), **extra)
 
 
 # ---------------------------------------------------------------- training

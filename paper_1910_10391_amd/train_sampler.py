@@ -8,12 +8,14 @@
    on the full 64 x 64 grid within +-5/gamma.
 2. Training: Adam on minibatches of (trajectory, energy, direction) points with the
    library's BF16 MLP kernels.
-3. Tuning on ``--val`` held-out trajectories: the check tolerance tau and how the
-   cells left out are counted (predicted mass, or centre value x area), for the
-   fewest evaluations within the error target.
+3. Tuning on ``--val`` held-out trajectories, for the fewest evaluations within
+   the error target: for selection by predicted mass, the coverage, the check
+   tolerance tau and how the cells left out are counted (predicted mass, or centre
+   value x area); for the error-driven selection, the error budget eps.
 4. Evaluation on ``--test`` further held-out trajectories against the full-grid angle
-   integral: relative error of dI/d hw, evaluations and time, next to refinement
-   ranked by the coarse values alone (no network) and the coarse grid alone.
+   integral: relative error of dI/d hw, evaluations and time of both learned rules,
+   next to refinement ranked by the coarse values alone (no network) and the coarse
+   grid alone.
 """
 from __future__ import annotations
 
@@ -108,35 +110,44 @@ def main(argv=None):
         smp = Sampler(mlp, norm, grids, cfg.d_m, a.coverage, a.cap, tau=0.25)
     prec = rad.MIXED
 
-    # coverage, tau and the fill rule on held-out validation trajectories: the setting with
-    # the fewest evaluations whose largest validation error stays within the target; the
-    # same search for refinement ranked by the coarse values alone (no network)
+    # settings on held-out validation trajectories: for each rule, the setting with the
+    # fewest evaluations whose largest validation error stays within the target
     dv = _device_segments(cfg, a.val, 60000)
     fv, _ = smp.full_grid(dv, prec)
     fv = fv.cpu().numpy()
     coverages = (a.coverage,) if a.coverage > 0 else (0.9, 0.95, 0.98, 0.99, 0.995)
     fills = ("pred", "coarse") if a.fill == "auto" else (a.fill,)
+    inf = float("inf")
+    searches = {
+        "learned": [dict(select="mass", coverage=c, fill=f, tau=t) for c in coverages for f in fills
+                    for t in (0.3, 0.5, 1.0, inf)],
+        "learned_error": [dict(select="error", eps=e) for e in (0.02, 0.01, 0.005, 0.003, 0.002, 0.001, 5e-4)],
+        "coarse": [dict(select="mass", coverage=c, fill="coarse", tau=inf) for c in coverages],
+    }
+
+    def apply(st):
+        smp.select_rule = st["select"]
+        smp.coverage, smp.fill = st.get("coverage", 1.0), st.get("fill", "coarse")
+        smp.tau, smp.eps = st.get("tau", inf), st.get("eps", 0.0)
+
     tune = []
     best = {}
-    for rule in ("learned", "coarse"):
-        for cov in coverages:
-            for fill in (fills if rule == "learned" else ("coarse",)):
-                for tau in ((0.3, 0.5, 1.0, float("inf")) if rule == "learned" else (float("inf"),)):
-                    smp.coverage, smp.fill, smp.tau = cov, fill, tau
-                    r = evaluate(smp, dv, fv, prec, rule=rule)
-                    frac = r["evals"] / r["evals_full"]
-                    tune.append(dict(rule=rule, coverage=cov, fill=fill, tau=tau, max_rel_err=r["max_rel_err"],
-                                     fallback_frac=r["fallback_frac"], evals_frac=frac))
-                    print("%s coverage %.3f fill %s tau %.2f: max rel err %.4f fallback %.3f evals %.3f" % (
-                        rule, cov, fill, tau, r["max_rel_err"], r["fallback_frac"], frac), flush=True)
-                    if r["max_rel_err"] <= a.target and (rule not in best or frac < best[rule][0]):
-                        best[rule] = (frac, cov, fill, tau)
+    for name, settings in searches.items():
+        for st in settings:
+            apply(st)
+            r = evaluate(smp, dv, fv, prec, rule="coarse" if name == "coarse" else "learned")
+            frac = r["evals"] / r["evals_full"]
+            tune.append(dict(rule=name, **st, max_rel_err=r["max_rel_err"], fallback_frac=r["fallback_frac"],
+                             evals_frac=frac))
+            print("%s %s: max rel err %.4f fallback %.3f evals %.3f" % (name, st, r["max_rel_err"],
+                                                                      r["fallback_frac"], frac), flush=True)
+            if r["max_rel_err"] <= a.target and (name not in best or frac < best[name][0]):
+                best[name] = (frac, st)
     report["tune"] = tune
-    report["chosen"] = {k: dict(evals_frac=v[0], coverage=v[1], fill=v[2], tau=v[3]) for k, v in best.items()}
-    settings = {}
-    for rule in ("learned", "coarse"):
-        # nothing within the target: every energy falls back (learned) / every cell refined
-        settings[rule] = best.get(rule, (1.0, 1.0, "coarse", 0.0))[1:]
+    report["chosen"] = {k: dict(evals_frac=v[0], **v[1]) for k, v in best.items()}
+    # nothing within the target: every cell refined
+    chosen = {k: best[k][1] if k in best else dict(select="mass", coverage=1.0, fill="coarse", tau=0.0)
+              for k in searches}
 
     # test: held-out trajectories
     dt_ = _device_segments(cfg, a.test, 70000)
@@ -147,23 +158,26 @@ def main(argv=None):
         t_full.append(s)
     full = f.cpu().numpy()
     res = {}
-    for rule in ("learned", "coarse"):
-        smp.coverage, smp.fill, smp.tau = settings[rule]
-        res[rule] = evaluate(smp, dt_, full, prec, rule=rule, reps=2)
-        res[rule]["settings"] = dict(coverage=smp.coverage, fill=smp.fill, tau=smp.tau)
-    smp.coverage, smp.fill, smp.tau = settings["learned"]
+    for name in searches:
+        apply(chosen[name])
+        res[name] = evaluate(smp, dt_, full, prec, rule="coarse" if name == "coarse" else "learned", reps=2)
+        res[name]["settings"] = chosen[name]
     # the coarse grid alone: every cell at its centre value x area
     c = smp.coarse(dt_, prec)
     area = float((2 * 5.0 / gamma / 8) ** 2)
     rel, peak = errors((c.sum(dim=2) * area).cpu().numpy(), full)
     res["coarse_only"] = dict(max_rel_err=float(rel.max()), max_peak_err=float(peak.max()))
     res["full_grid_seconds"] = min(t_full)
-    for k in ("learned", "coarse"):
+    for k in searches:
         res[k]["speedup_vs_full"] = res["full_grid_seconds"] / res[k]["seconds"]
         res[k]["evals_frac"] = res[k]["evals"] / res[k]["evals_full"]
     report["test"] = res
-    report["accepted"] = res["learned"]["max_rel_err"] <= a.target
-    report["tau"], report["fill"], report["coverage"] = smp.tau, smp.fill, smp.coverage
+    # the checkpoint keeps the learned rule that needed fewer evaluations on validation
+    learned = min(("learned", "learned_error"), key=lambda k: best[k][0] if k in best else 2.0)
+    apply(chosen[learned])
+    report["accepted"] = res[learned]["max_rel_err"] <= a.target
+    report["learned_rule"] = learned
+    report["settings"] = chosen[learned]
     report["total_seconds"] = time.time() - t_start
     print(json.dumps(res, indent=1), flush=True)
     if a.out:

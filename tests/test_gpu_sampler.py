@@ -106,6 +106,35 @@ def test_select_matches_oracle(S):
     assert np.array_equal(fb.cpu().numpy(), rf) and np.array_equal(mask.cpu().numpy(), rm)
 
 
+def test_select_error_matches_oracle(S):
+    import torch
+    rng = np.random.default_rng(23)
+    grid, th = _fine()
+    n_w = grid.shape[0]
+    w = oracle.angle_weights(th)
+    n_traj = 3
+    blocks = (n_w + 63) // 64
+    P = rng.normal(size=(n_traj, blocks, 64, 64)).astype(np.float32) * 1.5
+    pred = np.repeat(P, 64, axis=1)[:, :n_w].copy()
+    mu, sigma = np.float32(-2.0), np.float32(1.25)
+    inten = np.exp(float(mu) + float(sigma) * pred.astype(np.float64))
+    coarse = osm.centre_values(inten, 8, 8) * np.exp(rng.normal(size=(n_traj, n_w, 64)))
+    coarse[1, 7, :] = 0.0
+    smp = S.Sampler(None, dict(mu=float(mu), sigma=float(sigma)), _G(grid), D, select="error")
+    for eps, cap in ((1e-3, 64), (0.05, 64), (0.0, 5), (0.2, 2)):
+        mask, est = smp.select_error(torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda(), eps, cap)
+        rm, rest = osm.select_error(pred, float(mu), float(sigma), coarse, w, w, 8, 8, eps, cap)
+        assert np.allclose(est.cpu().numpy(), rest, rtol=1e-12, atol=0)
+        assert np.array_equal(mask.cpu().numpy(), rm), (eps, cap)
+        print("select_error eps %.3f cap %d: %d cells of %d" % (eps, cap, rm.sum(), rm.size))
+    # per-energy predictions: the widening itself
+    pred = (rng.normal(size=(n_traj, n_w, 64, 64)) * 1.5).astype(np.float32)
+    coarse = osm.centre_values(np.exp(float(mu) + float(sigma) * pred.astype(np.float64)), 8, 8) * 1.3
+    mask, est = smp.select_error(torch.from_numpy(pred).cuda(), torch.from_numpy(coarse).cuda(), 0.02, 3)
+    rm, rest = osm.select_error(pred, float(mu), float(sigma), coarse, w, w, 8, 8, 0.02, 3)
+    assert np.array_equal(mask.cpu().numpy(), rm) and np.allclose(est.cpu().numpy(), rest, rtol=1e-12, atol=0)
+
+
 class _G:
     """Just the fine grid, for calling the selection/combination steps directly."""
 
@@ -179,6 +208,18 @@ def test_estimate_matches_oracle(S):
         print("fallback prec %d: %.2e" % (prec, err))
         assert err < tol
         smp.tau = 1e30
+    # the error-driven rule: cells left out at their corrected estimates
+    smp.select_rule, smp.eps, smp.cap = "error", 0.05, 3
+    rm, rest = osm.select_error(pred, -8.0, 2.0, coarse, w, w, 8, 8, 0.05, 3)
+    for prec, tol in ((rad.FP64, 1e-9), (rad.MIXED, 1e-4)):
+        res = smp.estimate(ds, precision=prec)
+        assert np.array_equal(res["mask"], rm)
+        ref = osm.combine(cells, rm, coarse, w, w, 8, 8, cell_pred=rest)
+        err = np.abs(res["dIdw"].cpu().numpy() - ref).max() / np.abs(ref).max()
+        print("estimate (error rule) prec %d: %.2e (refined %.2f of 4 cells)" % (prec, err,
+                                                                                res["refined_cells_mean"]))
+        assert err < tol
+    smp.select_rule = "mass"
     dIdw, _ = smp.full_grid(ds, precision=rad.FP64)
     assert np.abs(dIdw.cpu().numpy() - full).max() / np.abs(full).max() < 1e-9
 
@@ -211,6 +252,13 @@ def test_error_paths(S):
     bad = list(args)
     bad[5] = None                                         # no coarse values
     assert L.rad_sampler_select(*bad) == 1
+    est = torch.zeros((1, 8, 64), dtype=torch.float64, device="cuda")
+    eargs = [grid.handle, 1, P(pred), 0.0, 1.0, P(coarse), 8, 8, 0.01, 16, P(mask), P(est), None]
+    assert L.rad_sampler_select_error(*eargs) == 0
+    for i, v in ((8, -0.5), (8, float("inf")), (9, 0), (11, None), (6, 5)):
+        bad = list(eargs)
+        bad[i] = v                                        # eps < 0 or inf, cap 0, no estimates, bad cells
+        assert L.rad_sampler_select_error(*bad) == 1, (i, v)
     seg = _seg(np.linspace(0, 1e-6, 10), np.zeros(10), np.ones(10), 2e4)
     ds = rad.DeviceSegments([seg])
     feat = torch.empty((1, S.N_FEATURES), dtype=torch.float32, device="cuda")
