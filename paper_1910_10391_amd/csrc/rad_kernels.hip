@@ -55,10 +55,13 @@ __device__ __forceinline__ void lane_cis(double kh, double part, double &c, doub
     }
 }
 
-// LDS of one work item: the staged integrand and phase parts of kSlots
-// (time step, direction tile) pairs.
-template <int TX, int TY, bool WITHJ>
+// LDS of one work item: the staged integrand and phase parts of kSlots (time
+// step, direction tile) pairs and, in the mixed form, the trajectory columns of the
+// pass's time steps (the ten columns and the weight).
+constexpr int kRowCols = C_NCOL + 1;   // + the quadrature weight
+template <int TX, int TY, bool WITHJ, bool ROWS>
 struct AmpSmem {
+    double row[ROWS ? kRowCols : 1][ROWS ? kSlots : 1];
     double2 fxy[kSlots * TX * TY];
     double fq[WITHJ ? kSlots * TX * TY : 1];
     double px[kSlots * TX];
@@ -69,7 +72,7 @@ struct AmpSmem {
 // One work item b = (segment, time chunk, direction-tile group, photon-energy
 // block) of an amplitude launch, computed by the whole block.
 template <int TX, int TY, bool WITHJ, bool MIXED>
-__device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ> &sm)
+__device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ, MIXED> &sm)
 {
     constexpr int NP = TX * TY;
     double2 *const s_fxy = sm.fxy;
@@ -102,15 +105,6 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     const double c0 = S.c0;
     const double energy = S.energy;
     const double *__restrict__ ct = S.col[C_T];
-    const double *__restrict__ cx = S.col[C_X];
-    const double *__restrict__ cy = S.col[C_Y];
-    const double *__restrict__ cdz = S.col[C_DZ];
-    const double *__restrict__ cvx = S.col[C_VX];
-    const double *__restrict__ cvy = S.col[C_VY];
-    const double *__restrict__ cdvz = S.col[C_DVZ];
-    const double *__restrict__ cax = S.col[C_AX];
-    const double *__restrict__ cay = S.col[C_AY];
-    const double *__restrict__ caz = S.col[C_AZ];
     const double *__restrict__ cw = S.w;
     const double *__restrict__ g_hw = S.hw;
     const double *__restrict__ g_k = S.k;
@@ -162,6 +156,28 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
 
     for (int64_t k0 = k_begin; k0 < k_end; k0 += T) {
         __syncthreads();
+        // the weight of sample k: given, or the trapezoid rule on t
+        auto weight = [&](int64_t k) {
+            return cw ? cw[k] : 0.5 * (ct[k + 1 < n ? k + 1 : n - 1] - ct[k > 0 ? k - 1 : 0]);
+        };
+        if constexpr (MIXED) {
+            // ---- stage: the pass's trajectory rows, read once per time step (coalesced)
+            // instead of once per (time step, direction).  The FP64 form measured
+            // faster reading the columns directly, so only the mixed form does this.
+            for (int i = threadIdx.x; i < kRowCols * T; i += kBlock) {
+                const int c = i / T, tloc = i % T;
+                const int64_t k = k0 + tloc;
+                double v = 0.0;
+                if (k < k_end) v = c < C_NCOL ? S.col[c][k] : weight(k);
+                sm.row[c][tloc] = v;
+            }
+            __syncthreads();
+        }
+        // column c at time step k (pass position tloc)
+        auto col = [&](int c, int tloc, int64_t k) {
+            if constexpr (MIXED) return sm.row[c][tloc];
+            else return S.col[c][k];
+        };
         // ---- stage: integrand and phase parts for kSlots (t, tile) pairs
         for (int i = threadIdx.x; i < kSlots * NP; i += kBlock) {
             const int slot = i / NP, p = i % NP;
@@ -173,10 +189,11 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             double fx = 0.0, fy = 0.0, fq = 0.0;
             if (k < k_end && gt < n_tiles && jx < n_x && jy < n_y) {
                 const double thx = g_thx[jx], thy = g_thy[jy];
-                const double vx = cvx[k], vy = cvy[k], dvz = cdvz[k];
-                const double ax = cax[k], ay = cay[k], az = caz[k];
-                const double w = cw ? cw[k]
-                                    : 0.5 * (ct[k + 1 < n ? k + 1 : n - 1] - ct[k > 0 ? k - 1 : 0]);
+                const double vx = col(C_VX, tloc, k), vy = col(C_VY, tloc, k), dvz = col(C_DVZ, tloc, k);
+                const double ax = col(C_AX, tloc, k), ay = col(C_AY, tloc, k), az = col(C_AZ, tloc, k);
+                double w;
+                if constexpr (MIXED) w = sm.row[C_NCOL][tloc];
+                else w = weight(k);
                 const double th2h = 0.5 * (thx * thx + thy * thy);
                 const double D = ((c0 + th2h) - dvz) - thx * vx - thy * vy;
                 const double C = (c0 - th2h) - dvz;
@@ -208,15 +225,15 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             const int gt = grp * nt + tile;
             double v = 0.0;
             if (k < k_end && gt < n_tiles) {
-                const double t = ct[k];
+                const double t = col(C_T, tloc, k);
                 if (j < TX) {
                     const int jx = (gt % n_tx) * TX + j;
                     const double thx = jx < n_x ? g_thx[jx] : 0.0;
-                    v = (c0 * t - cdz[k]) + thx * (0.5 * thx * t - cx[k]);
+                    v = (c0 * t - col(C_DZ, tloc, k)) + thx * (0.5 * thx * t - col(C_X, tloc, k));
                 } else {
                     const int jy = (gt / n_tx) * TY + (j - TX);
                     const double thy = jy < n_y ? g_thy[jy] : 0.0;
-                    v = thy * (0.5 * thy * t - cy[k]);
+                    v = thy * (0.5 * thy * t - col(C_Y, tloc, k));
                 }
             }
             if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
@@ -303,7 +320,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
 template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
 {
-    __shared__ AmpSmem<TX, TY, WITHJ> sm;
+    __shared__ AmpSmem<TX, TY, WITHJ, MIXED> sm;
     amp_item<TX, TY, WITHJ, MIXED>(L, blockIdx.x, sm);
 }
 
@@ -315,7 +332,7 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
 template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
 {
-    __shared__ AmpSmem<TX, TY, WITHJ> sm;
+    __shared__ AmpSmem<TX, TY, WITHJ, MIXED> sm;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(L.counter, 1u);

@@ -34,14 +34,21 @@ __host__ __device__ __forceinline__ void cis_halfturns(double u, double &c, doub
     for (int k = RAD_COS_NC - 2; k >= 0; --k) pc = __builtin_fma(pc, z, RAD_COS_C[k]);
     ps *= f;
     // (-1)^q: flip the sign bit of both parts when q is odd
-    const uint64_t flip = (uint64_t)((uint32_t)(int32_t)q & 1u) << 63;
-    uint64_t bs, bc;
-    __builtin_memcpy(&bs, &ps, 8);
-    __builtin_memcpy(&bc, &pc, 8);
-    bs ^= flip;
-    bc ^= flip;
-    __builtin_memcpy(&s, &bs, 8);
-    __builtin_memcpy(&c, &bc, 8);
+    const uint32_t qi = (uint32_t)(int32_t)q;
+    uint32_t ws[2], wc[2];
+    __builtin_memcpy(ws, &ps, 8);
+    __builtin_memcpy(wc, &pc, 8);
+#if defined(__HIP_DEVICE_COMPILE__)
+    // high word + (q << 31) flips bit 31 exactly when q is odd (the carry leaves the
+    // word): one shift-and-add per part instead of a shared shift and two xors
+    __asm__("v_lshl_add_u32 %0, %1, 31, %0" : "+v"(ws[1]) : "v"(qi));
+    __asm__("v_lshl_add_u32 %0, %1, 31, %0" : "+v"(wc[1]) : "v"(qi));
+#else
+    ws[1] ^= qi << 31;
+    wc[1] ^= qi << 31;
+#endif
+    __builtin_memcpy(&s, ws, 8);
+    __builtin_memcpy(&c, wc, 8);
 }
 
 // sin, cos of 2 pi r for an FP64 revolution count r (any size < 2^52):
