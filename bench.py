@@ -48,15 +48,15 @@ def flops_per_eval(variant, with_j=True):
 
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
-# FP64 kernel (358 per 16 evals with J, 329 without), counted in the gfx950
+# FP64 kernel (351 per 16 evals with J, 319 without), counted in the gfx950
 # assembly of this build.
-VALU_PER_EVAL_44 = {True: 358.0 / 16.0, False: 329.0 / 16.0}
+VALU_PER_EVAL_44 = {True: 351.0 / 16.0, False: 319.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "46f007ec4b1ba03a", "particles": 256, "bytes_per_launch": 2.0872e10}
+MEASURED_TRAFFIC = {"sources_sha256": "aaa504a299b9bf23", "particles": 256, "bytes_per_launch": 2.0789e10}
 
 
 def kernel_sources_sha():
