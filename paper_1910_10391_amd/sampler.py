@@ -308,7 +308,7 @@ def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64
             for j, i in enumerate(members):
                 targets.append((c0 + i, y[j]))
                 tw.append((c0 + i, torch.from_numpy(iw.astype(np.int64))))
-        if verbose:
+        if verbose and ((c0 // chunk) % 16 == 15 or c1 == n_traj):
             print("training set: %d / %d trajectories" % (c1, n_traj), flush=True)
     targets.sort(key=lambda p: p[0])
     tw.sort(key=lambda p: p[0])

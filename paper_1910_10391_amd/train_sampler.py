@@ -63,7 +63,10 @@ def evaluate(smp, ds, full, precision, rule="learned", reps=1):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--train", type=int, default=782, help="training trajectories (x 64 energies each)")
+    ap.add_argument("--train", type=int, default=782, help="training trajectories")
+    ap.add_argument("--energies", type=int, default=64, help="photon energies per training trajectory")
+    ap.add_argument("--train-first", type=int, default=40000,
+                    help="index of the first training particle (validation: 60000.., test: 70000..)")
     ap.add_argument("--val", type=int, default=32)
     ap.add_argument("--test", type=int, default=64)
     ap.add_argument("--steps", type=int, default=12000)
@@ -86,7 +89,8 @@ def main(argv=None):
     gamma = cfg.energy_eV / channeling.ME_EV
     t_start = time.time()
     report = dict(config=dict(workload="positron_spinhalf_sampler", particles_train=a.train,
-                              particles_val=a.val, particles_test=a.test, n_w=int(pg.hw_eV.size), fine=64,
+                              particles_val=a.val, particles_test=a.test, energies_per_train=a.energies,
+                              n_w=int(pg.hw_eV.size), fine=64,
                               cell=8, coverage=a.coverage, cap=a.cap, steps=a.steps, batch=a.batch))
     if a.load:
         smp = Sampler.load(a.load, pg.hw_eV, gamma)
@@ -95,7 +99,9 @@ def main(argv=None):
     else:
         grids = Grids(pg.hw_eV, gamma, n_fine=64, half_width_over_gamma=5.0)
         t0 = time.time()
-        feat, W, Y = training_set(cfg, a.train, grids, n_w_train=64, first=40000, verbose=True)
+        if a.train_first < 70064 and a.train_first + a.train > 60000:
+            raise SystemExit("training particles overlap the validation/test particles (60000..70063)")
+        feat, W, Y = training_set(cfg, a.train, grids, n_w_train=a.energies, first=a.train_first, verbose=True)
         torch.cuda.synchronize()
         report["training_set_seconds"] = time.time() - t0
         print("training set: %d spectra in %.1f s" % (W.numel(), report["training_set_seconds"]), flush=True)
