@@ -62,6 +62,9 @@ constexpr int kRowCols = C_NCOL + 1;   // + the quadrature weight
 template <int TX, int TY, bool WITHJ, bool ROWS>
 struct AmpSmem {
     double row[ROWS ? kRowCols : 1][ROWS ? kSlots : 1];
+    // mixed form: the block's direction tiles, thx then thy (0 outside), and which exist
+    double th[ROWS ? kWavesPerBlock : 1][TX + TY];
+    unsigned char thok[ROWS ? kWavesPerBlock : 1][TX + TY];
     double2 fxy[kSlots * TX * TY];
     double fq[WITHJ ? kSlots * TX * TY : 1];
     double px[kSlots * TX];
@@ -128,6 +131,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     const int64_t k_end = min(n, k_begin + (int64_t)S.chunk_len);
 
     const int nt = L.nt, wg = L.wg;
+    const int lnt = nt == 4 ? 2 : (nt == 2 ? 1 : 0);   // nt is 1, 2 or 4 (checked at launch)
     const int T = kSlots / nt;
     const int n_tiles = n_tx * S.n_ty;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -146,6 +150,53 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         }
     }
     const double kh = MIXED ? kappa * (0.5 / kPi) : kappa * (1.0 / kPi);
+
+    // mixed form: the angles of the block's nt direction tiles, once per item (the
+    // staging loops then index them instead of dividing by the grid's tile count); the
+    // first barrier of the time loop orders these writes before any read.  The FP64
+    // form measured slower with the table (one more accumulator spilled in the
+    // persistent kernel) and computes the directions in the staging loops.
+    for (int i = threadIdx.x; i < (MIXED ? nt * (TX + TY) : 0); i += kBlock) {
+        const int tile = i / (TX + TY), j = i % (TX + TY);
+        const int gt = grp * nt + tile;
+        double th = 0.0;
+        bool ok = false;
+        if (gt < n_tiles) {
+            if (j < TX) {
+                const int jx = (gt % n_tx) * TX + j;
+                ok = jx < n_x;
+                if (ok) th = g_thx[jx];
+            } else {
+                const int jy = (gt / n_tx) * TY + (j - TX);
+                ok = jy < n_y;
+                if (ok) th = g_thy[jy];
+            }
+        }
+        sm.th[tile][j] = th;
+        sm.thok[tile][j] = ok ? 1 : 0;
+    }
+    // direction j (thx for j < TX, else thy) of tile `tile`: its angle (0 outside the
+    // grid) and whether it exists
+    auto direction = [&](int tile, int j, double &th) -> bool {
+        if constexpr (MIXED) {
+            th = sm.th[tile][j];
+            return sm.thok[tile][j] != 0;
+        } else {
+            const int gt = grp * nt + tile;
+            th = 0.0;
+            if (gt >= n_tiles) return false;
+            if (j < TX) {
+                const int jx = (gt % n_tx) * TX + j;
+                if (jx >= n_x) return false;
+                th = g_thx[jx];
+            } else {
+                const int jy = (gt / n_tx) * TY + (j - TX);
+                if (jy >= n_y) return false;
+                th = g_thy[jy];
+            }
+            return true;
+        }
+    };
 
     double axr[NP], axi[NP], ayr[NP], ayi[NP], jr[WITHJ ? NP : 1], ji[WITHJ ? NP : 1];
 #pragma unroll
@@ -181,14 +232,11 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         // ---- stage: integrand and phase parts for kSlots (t, tile) pairs
         for (int i = threadIdx.x; i < kSlots * NP; i += kBlock) {
             const int slot = i / NP, p = i % NP;
-            const int tloc = slot / nt, tile = slot % nt;
+            const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
             const int64_t k = k0 + tloc;
-            const int gt = grp * nt + tile;
-            const int jx = (gt % n_tx) * TX + p % TX;
-            const int jy = (gt / n_tx) * TY + p / TX;
-            double fx = 0.0, fy = 0.0, fq = 0.0;
-            if (k < k_end && gt < n_tiles && jx < n_x && jy < n_y) {
-                const double thx = g_thx[jx], thy = g_thy[jy];
+            double fx = 0.0, fy = 0.0, fq = 0.0, thx, thy;
+            const bool okx = direction(tile, p % TX, thx), oky = direction(tile, TX + p / TX, thy);
+            if (k < k_end && okx && oky) {
                 const double vx = col(C_VX, tloc, k), vy = col(C_VY, tloc, k), dvz = col(C_DVZ, tloc, k);
                 const double ax = col(C_AX, tloc, k), ay = col(C_AY, tloc, k), az = col(C_AZ, tloc, k);
                 double w;
@@ -201,7 +249,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     // FP32 integrand; D and C are formed in FP64 (they are
                     // small differences) and rounded once.
                     const float Df = (float)D, Cf = (float)C;
-                    const float G = (float)w / (Df * Df);
+                    const float G = (float)w * __builtin_amdgcn_rcpf(Df * Df);   // 1 ulp
                     const float tx = (float)thx, ty = (float)thy;
                     const float vxf = (float)vx, vyf = (float)vy;
                     const float axf = (float)ax, ayf = (float)ay, azf = (float)az;
@@ -220,21 +268,17 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         }
         for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
             const int slot = i / (TX + TY), j = i % (TX + TY);
-            const int tloc = slot / nt, tile = slot % nt;
+            const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
             const int64_t k = k0 + tloc;
-            const int gt = grp * nt + tile;
             double v = 0.0;
-            if (k < k_end && gt < n_tiles) {
+            if (k < k_end && grp * nt + tile < n_tiles) {
                 const double t = col(C_T, tloc, k);
-                if (j < TX) {
-                    const int jx = (gt % n_tx) * TX + j;
-                    const double thx = jx < n_x ? g_thx[jx] : 0.0;
-                    v = (c0 * t - col(C_DZ, tloc, k)) + thx * (0.5 * thx * t - col(C_X, tloc, k));
-                } else {
-                    const int jy = (gt / n_tx) * TY + (j - TX);
-                    const double thy = jy < n_y ? g_thy[jy] : 0.0;
-                    v = thy * (0.5 * thy * t - col(C_Y, tloc, k));
-                }
+                double th;
+                (void)direction(tile, j, th);
+                if (j < TX)
+                    v = (c0 * t - col(C_DZ, tloc, k)) + th * (0.5 * th * t - col(C_X, tloc, k));
+                else
+                    v = th * (0.5 * th * t - col(C_Y, tloc, k));
             }
             if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
         }
@@ -534,6 +578,8 @@ static hipError_t launch_amp_v(const AmpLaunch &L, int variant, int grid_blocks,
 hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, int grid_blocks,
                       hipStream_t st, int *occupancy)
 {
+    // the kernel shifts by log2(nt) (an occupancy query passes no launch)
+    if (!occupancy && L.nt != 1 && L.nt != 2 && L.nt != 4) return hipErrorInvalidValue;
     if (withj)
         return mixed ? launch_amp_v<true, true>(L, variant, grid_blocks, st, occupancy)
                      : launch_amp_v<true, false>(L, variant, grid_blocks, st, occupancy);
