@@ -148,7 +148,8 @@ def test_mixed_precision(rad):
 
 
 def test_variants_agree(rad):
-    """Every kernel variant (direction tile, occupancy) gives the same sums."""
+    """Every kernel variant (direction tile, occupancy), one-block-per-item and persistent,
+    FP64 and mixed, on a 9 x 9 grid that leaves partial direction tiles."""
     cfg, tr = _small_channeling(1, seed=17)
     seg = tr[0][0]
     hw = analytic.log_omega(130, 0.5e6, 200e6)
@@ -161,12 +162,14 @@ def test_variants_agree(rad):
         for v in range(rad.tune_num_variants()):
             for k in keys:
                 rad.tune_set_variant(*k, v)
-            out = _cpu(rad.batch(grid, [seg], [0], 1, 7))[0]
-            plan = rad.Plan(grid, [seg], [0], 1, 7)
-            outp = _cpu(plan.launch())[0]
-            for i, k in enumerate((1, 2, 4)):
-                assert_parity(out[i], ref[k], th, th, FP64_TOL, "variant %d kind %d" % (v, k))
-                assert_parity(outp[i], ref[k], th, th, FP64_TOL, "persistent variant %d kind %d" % (v, k))
+            for prec, tol in ((rad.FP64, FP64_TOL), (rad.MIXED, MIXED_TOL)):
+                out = _cpu(rad.batch(grid, [seg], [0], 1, 7, precision=prec))[0]
+                plan = rad.Plan(grid, [seg], [0], 1, 7, precision=prec)
+                outp = _cpu(plan.launch())[0]
+                for i, k in enumerate((1, 2, 4)):
+                    assert_parity(out[i], ref[k], th, th, tol, "variant %d prec %d kind %d" % (v, prec, k))
+                    assert_parity(outp[i], ref[k], th, th, tol,
+                                  "persistent variant %d prec %d kind %d" % (v, prec, k))
     finally:
         for k in keys:
             rad.tune_set_variant(*k, keep[k])
