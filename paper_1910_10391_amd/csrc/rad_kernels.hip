@@ -394,19 +394,49 @@ __global__ void reset_counters_kernel(unsigned *c, int n)
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
+// Sum of the n chunk partials p[0], p[stride], ..., p[(n-1) stride] in a fixed order:
+// partial c goes to running sum c % 8 and the eight sums are added pairwise, so that
+// eight loads are in flight instead of one (a small problem cut into many short chunks
+// would otherwise wait on one load latency per chunk).
+__device__ __forceinline__ double2 chunk_sum(const double2 *__restrict__ p, int64_t stride, int n)
+{
+    constexpr int K = 8;
+    double2 s[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j] = make_double2(0.0, 0.0);
+    int c = 0;
+    for (; c + K <= n; c += K) {
+        double2 v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = p[(int64_t)(c + j) * stride];
+        // all K loads are issued before the first add waits (the scheduler would
+        // otherwise reuse one register and wait after every load)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            s[j].x += v[j].x;
+            s[j].y += v[j].y;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (c + j < n) {
+            const double2 v = p[(int64_t)(c + j) * stride];
+            s[j].x += v.x;
+            s[j].y += v.y;
+        }
+    return make_double2(((s[0].x + s[1].x) + (s[2].x + s[3].x)) + ((s[4].x + s[5].x) + (s[6].x + s[7].x)),
+                        ((s[0].y + s[1].y) + (s[2].y + s[3].y)) + ((s[4].y + s[5].y) + (s[6].y + s[7].y)));
+}
+
 __device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
                                            int comps, int comp, int64_t n_n, int n_w, int64_t nn,
                                            int iw, double &re, double &im)
 {
-    re = 0.0;
-    im = 0.0;
     const int64_t stride = (int64_t)comps * n_n * n_w;
-    const double2 *p = part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw;
-    for (int c = 0; c < d.n_chunks; ++c) {
-        const double2 v = p[(int64_t)c * stride];
-        re += v.x;
-        im += v.y;
-    }
+    const double2 v = chunk_sum(part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw, stride, d.n_chunks);
+    re = v.x;
+    im = v.y;
 }
 
 __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
@@ -494,12 +524,10 @@ __global__ __launch_bounds__(256) void cells_fin_kernel(CellsFin F)
         const double thx = d.thx[jx], thy = d.thy[jy];
         double re[3] = {0.0, 0.0, 0.0}, im[3] = {0.0, 0.0, 0.0};
         for (int comp = 0; comp < F.comps; ++comp) {
-            const double2 *q = F.part + d.part_off + ((int64_t)comp * n_dir + nn) * F.n_w + w;
-            for (int ch = 0; ch < d.n_chunks; ++ch) {
-                const double2 v = q[(int64_t)ch * stride];
-                re[comp] += v.x;
-                im[comp] += v.y;
-            }
+            const double2 v = chunk_sum(F.part + d.part_off + ((int64_t)comp * n_dir + nn) * F.n_w + w, stride,
+                                        d.n_chunks);
+            re[comp] = v.x;
+            im[comp] = v.y;
         }
         const double zr = -(thx * re[0] + thy * re[1]), zi = -(thx * im[0] + thy * im[1]);
         const double S = re[0] * re[0] + im[0] * im[0] + re[1] * re[1] + im[1] * im[1] + zr * zr + zi * zi;

@@ -132,7 +132,10 @@ Tile plan_tile(const rad_grid *g, int variant)
 }
 
 constexpr int64_t kTargetBlocks = 2048;  // 256 CUs x 2 resident blocks x 4 rounds
-constexpr int64_t kMinChunk = 128;
+// Chunk lengths are multiples of kMinChunk samples.  A small problem (few direction
+// tiles and photon energies) is cut this fine so that its blocks, each a single
+// latency-bound wave per SIMD, stay short: 16 samples is one LDS pass of a 4-tile block.
+constexpr int64_t kMinChunk = 16;
 
 // chunks per segment when the launch has `n_segs` segments
 int64_t chunk_factor(const Tile &t, int64_t n_segs)
@@ -145,8 +148,7 @@ int64_t chunk_factor(const Tile &t, int64_t n_segs)
 void plan_chunks(int64_t n, int64_t c, int32_t &n_chunks, int32_t &chunk_len)
 {
     int64_t len = (n + c - 1) / c;
-    len = (len + 63) / 64 * 64;
-    len = std::max(len, kMinChunk);
+    len = (len + kMinChunk - 1) / kMinChunk * kMinChunk;
     len = std::min(len, n);
     chunk_len = (int32_t)len;
     n_chunks = (int32_t)((n + len - 1) / len);
