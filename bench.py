@@ -37,26 +37,33 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # VALU lane-instructions per second
 VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2)}
 
 
-def flops_per_eval(variant, with_j=True):
-    """FP64 flops per (t, w, n) eval of the amplitude kernel (FMA = 2): a lane makes
-    TX + TY phase factors per time step for TX*TY directions, 34 flops each (phase
-    product, exact reduction, f^2, an 8-term sine and a 9-term cosine polynomial,
-    f * poly); then per eval
-    a complex product (6) and 2 flops per real accumulator (A_x, A_y and J: 12)."""
+def flops_per_eval(variant, with_j=True, recurrence=False):
+    """FP64 flops per (t, w, n) eval of the amplitude kernel (FMA = 2).  Phase factors,
+    34 flops each (phase product, exact reduction, f^2, an 8-term sine and a 9-term
+    cosine polynomial, f * poly): TX + TY per time step for TX*TY directions; on a
+    uniform grid (recurrence) 5 (the first factor along x and along y, their two
+    multipliers and the shared second-difference factor) plus 2 (TX + TY) - 6 complex
+    products (6 flops each).  Then per eval a complex product (6) and 2 flops per real
+    accumulator (A_x, A_y and J: 12)."""
     tx, ty, _ = VARIANTS[variant]
-    return 34.0 * (tx + ty) / (tx * ty) + 6.0 + (12.0 if with_j else 8.0)
+    if recurrence:
+        phase = (5 * 34.0 + 6.0 * (2 * (tx + ty) - 6)) / (tx * ty)
+    else:
+        phase = 34.0 * (tx + ty) / (tx * ty)
+    return phase + 6.0 + (12.0 if with_j else 8.0)
 
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
-# FP64 kernel (351 per 16 evals with J, 319 without), counted in the gfx950
-# assembly of this build.
-VALU_PER_EVAL_44 = {True: 351.0 / 16.0, False: 319.0 / 16.0}
+# FP64 kernel, counted in the gfx950 assembly of this build: direct phase factors
+# 351 per 16 evals with J (319 without), recurrence on a uniform grid 323 (290).
+VALU_PER_EVAL_44 = {(True, False): 351.0 / 16.0, (False, False): 319.0 / 16.0,
+                    (True, True): 323.0 / 16.0, (False, True): 290.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "f5cdd1e43ff11a02", "particles": 256, "bytes_per_launch": 2.0760e10}
+MEASURED_TRAFFIC = {"sources_sha256": "2a01fcafee48d1ae", "particles": 256, "bytes_per_launch": 4.4796e10}
 
 
 def kernel_sources_sha():
@@ -584,7 +591,8 @@ def main():
             mixed["rel_err_M2"] = parity["mixed_M2_max"]
 
     variant = rad.tune_get_variant(False, False, True)
-    flops = flops_per_eval(variant, True) * evals
+    rec = grid.step != 0.0
+    flops = flops_per_eval(variant, True, rec) * evals
     achieved = flops / kern_s / 1e12
     traffic = None
     if (kernel_sources_sha() == MEASURED_TRAFFIC["sources_sha256"] and variant == 0
@@ -592,9 +600,9 @@ def main():
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": "amp_kernel<%d,%d,J,fp64,%d>" % VARIANTS[variant], "kernel_ms": kern_s * 1e3,
-                "flops_per_eval": flops_per_eval(variant, True),
-                "valu_issue_frac": (VALU_PER_EVAL_44[True] * evals / kern_s / 1e12 / VALU_PEAK_TOPS
+                "kernel": "amp_kernel<%d,%d,J,fp64,%d%s>" % (VARIANTS[variant] + (",rec" if rec else "",)),
+                "kernel_ms": kern_s * 1e3, "flops_per_eval": flops_per_eval(variant, True, rec),
+                "valu_issue_frac": (VALU_PER_EVAL_44[(True, rec)] * evals / kern_s / 1e12 / VALU_PEAK_TOPS
                                     if variant == 0 else None)}
     res = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,

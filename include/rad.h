@@ -91,7 +91,11 @@ typedef struct {
  * Build a grid handle: photon energies hw_eV[n_w] (> 0), directions
  * thx[n_x] = n_x and thy[n_y] = n_y [rad] (HOST arrays, copied).  The angle
  * integral uses cell widths half-way between neighbours (a single point has
- * width 1).  Allocates device memory; may synchronise `stream`.
+ * width 1).  When thx and thy are uniform with one common spacing d (to within
+ * 8 units in the last place of the largest angle), the FP64 kernels form the
+ * phase factors of a direction tile by recurrence along each axis (the phase is
+ * quadratic in the direction index; Sec. II), see rad_grid_step.  Allocates
+ * device memory; may synchronise `stream`.
  * Errors: RAD_EINVAL for null pointers, sizes < 1 or non-finite values;
  * RAD_ENOMEM / RAD_EDEVICE on allocation or copy failure.
  */
@@ -104,6 +108,11 @@ void rad_free_grid(rad_grid *grid);
 
 /* Grid sizes (any pointer may be NULL). */
 rad_status rad_grid_dims(const rad_grid *grid, int *n_w, int *n_x, int *n_y);
+
+/* The common direction spacing d the FP64 kernels use for their phase recurrence,
+ * or 0 when thx or thy is not uniform or their spacings differ (phase factors are
+ * then evaluated directly).  Errors: RAD_EINVAL for a NULL grid or dth. */
+rad_status rad_grid_step(const rad_grid *grid, double *dth);
 
 /*
  * Workspace bytes that rad_classical / rad_quantum need for any segment with

@@ -16,7 +16,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSlots = 64;   // time-steps x direction-tiles staged in LDS per pass
+constexpr int kSlots = 128;  // time-steps x direction-tiles staged in LDS per pass
 
 // Amplitude-kernel variants: direction tile TX x TY and minimum resident blocks per CU.
 enum Variant { kVar44x2 = 0, kVar43x2 = 1, kVar44x1 = 2, kVar42x2 = 3, kNumVariants = 4 };
@@ -48,6 +48,7 @@ struct SegDesc {
     int32_t n_groups;      // ceil(n_tx * n_ty / nt)
     int32_t n_wblocks;     // ceil(n_w / (64 wg))
     int32_t pad_;
+    double dth;            // common spacing of uniform thx and thy grids, or 0
 };
 
 // One amplitude launch: one "set" (classical kappa = k, or quantum kappa = k*).
@@ -62,6 +63,7 @@ struct AmpLaunch {
     int comps;             // 2 (A_x, A_y) or 3 (A_x, A_y, J)
     double2 *part;         // partial amplitudes [seg][chunk][comp][n][w]
     unsigned *counter;     // ticket of the persistent form (zeroed before the launch)
+    int rec;               // FP64: phase factors by recurrence (every segment's dth != 0)
 };
 
 // Finalize: per output, the segments that feed it, in segment order.

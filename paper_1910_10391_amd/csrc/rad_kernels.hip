@@ -74,7 +74,7 @@ struct AmpSmem {
 
 // One work item b = (segment, time chunk, direction-tile group, photon-energy
 // block) of an amplitude launch, computed by the whole block.
-template <int TX, int TY, bool WITHJ, bool MIXED>
+template <int TX, int TY, bool WITHJ, bool MIXED, bool REC>
 __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ, MIXED> &sm)
 {
     constexpr int NP = TX * TY;
@@ -266,21 +266,49 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             s_fxy[i] = make_double2(fx, fy);
             if constexpr (WITHJ) s_fq[i] = fq;
         }
-        for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
-            const int slot = i / (TX + TY), j = i % (TX + TY);
-            const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
-            const int64_t k = k0 + tloc;
-            double v = 0.0;
-            if (k < k_end && grp * nt + tile < n_tiles) {
-                const double t = col(C_T, tloc, k);
-                double th;
-                (void)direction(tile, j, th);
-                if (j < TX)
-                    v = (c0 * t - col(C_DZ, tloc, k)) + th * (0.5 * th * t - col(C_X, tloc, k));
-                else
-                    v = th * (0.5 * th * t - col(C_Y, tloc, k));
+        if constexpr (REC) {
+            // uniform grids: per (time step, tile) the phase parts of the tile's first
+            // direction and the multipliers of the recurrence along x and y (below)
+            const double dth = S.dth;
+            for (int i = threadIdx.x; i < kSlots * 5; i += kBlock) {
+                const int slot = i / 5, j = i % 5;
+                const int tloc = slot / nt, tile = slot % nt;
+                const int64_t k = k0 + tloc;
+                double v = 0.0;
+                if (k < k_end && grp * nt + tile < n_tiles) {
+                    const double t = col(C_T, tloc, k);
+                    double th0;
+                    (void)direction(tile, j < 3 ? 0 : TX, th0);
+                    if (j == 0)
+                        v = (c0 * t - col(C_DZ, tloc, k)) + th0 * (0.5 * th0 * t - col(C_X, tloc, k));
+                    else if (j == 1)
+                        v = dth * ((th0 + 0.5 * dth) * t - col(C_X, tloc, k));
+                    else if (j == 2)
+                        v = dth * dth * t;
+                    else if (j == 3)
+                        v = th0 * (0.5 * th0 * t - col(C_Y, tloc, k));
+                    else
+                        v = dth * ((th0 + 0.5 * dth) * t - col(C_Y, tloc, k));
+                }
+                if (j < 3) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - 3)] = v;
             }
-            if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
+        } else {
+            for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
+                const int slot = i / (TX + TY), j = i % (TX + TY);
+                const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
+                const int64_t k = k0 + tloc;
+                double v = 0.0;
+                if (k < k_end && grp * nt + tile < n_tiles) {
+                    const double t = col(C_T, tloc, k);
+                    double th;
+                    (void)direction(tile, j, th);
+                    if (j < TX)
+                        v = (c0 * t - col(C_DZ, tloc, k)) + th * (0.5 * th * t - col(C_X, tloc, k));
+                    else
+                        v = th * (0.5 * th * t - col(C_Y, tloc, k));
+                }
+                if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
+            }
         }
         __syncthreads();
         // ---- accumulate: every lane, its photon energy, its direction tile
@@ -298,8 +326,32 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                 fn[jx] = s_fxy[slot * NP + jx];
                 if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + jx];
             }
+            // uniform grids: the phase along x and along y is quadratic in the direction
+            // index, so from the tile's first factor X_0 and R_0 = exp(i kappa a),
+            // B = exp(i kappa dth^2 t), X_{j+1} = X_j R_j with R_{j+1} = R_j B (and the
+            // same along y with S): 5 phase factors per time step instead of TX + TY
+            double br = 0.0, bi = 0.0, sr = 0.0, si = 0.0;
+            if constexpr (REC) {
+                double rr, ri;
+                lane_cis<false>(kh, s_px[slot * TX], xr[0], xi[0]);
+                lane_cis<false>(kh, s_px[slot * TX + 1], rr, ri);
+                lane_cis<false>(kh, s_px[slot * TX + 2], br, bi);
 #pragma unroll
-            for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
+                for (int jx = 1; jx < TX; ++jx) {
+                    xr[jx] = xr[jx - 1] * rr - xi[jx - 1] * ri;
+                    xi[jx] = xr[jx - 1] * ri + xi[jx - 1] * rr;
+                    if (jx + 1 < TX) {
+                        const double t_ = rr * br - ri * bi;
+                        ri = rr * bi + ri * br;
+                        rr = t_;
+                    }
+                }
+                lane_cis<false>(kh, s_py[slot * TY + 1], sr, si);
+            } else {
+#pragma unroll
+                for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
+            }
+            double yr = 0.0, yi = 0.0;
 #pragma unroll
             for (int jy = 0; jy < TY; ++jy) {
                 // with J at 16 directions per lane the kernel sits at the VGPR limit: each
@@ -311,14 +363,36 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                 double q[TX];
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) {
-                    f[jx] = fn[jx];
-                    if constexpr (WITHJ) q[jx] = qn[jx];
+                    // the recurrence form keeps its y state in the registers the next
+                    // row's prefetched integrand values would take, so it reads them here
+                    if constexpr (REC) {
+                        f[jx] = s_fxy[slot * NP + jy * TX + jx];
+                        if constexpr (WITHJ) q[jx] = s_fq[slot * NP + jy * TX + jx];
+                    } else {
+                        f[jx] = fn[jx];
+                        if constexpr (WITHJ) q[jx] = qn[jx];
+                    }
                 }
-                // this row's phase part; the next row's is read one region ahead
-                const double py = pyn;
-                if (jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
-                double yr, yi;
-                lane_cis<MIXED>(kh, py, yr, yi);
+                if constexpr (REC) {
+                    if (jy == 0) {
+                        lane_cis<false>(kh, pyn, yr, yi);
+                    } else {
+                        // Y_jy = Y_{jy-1} S_{jy-1}, then S_jy = S_{jy-1} B
+                        const double t_ = yr * sr - yi * si;
+                        yi = yr * si + yi * sr;
+                        yr = t_;
+                        if (jy + 1 < TY) {
+                            const double u_ = sr * br - si * bi;
+                            si = sr * bi + si * br;
+                            sr = u_;
+                        }
+                    }
+                } else {
+                    // this row's phase part; the next row's is read one region ahead
+                    const double py = pyn;
+                    if (jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
+                    lane_cis<MIXED>(kh, py, yr, yi);
+                }
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) {
                     const int p = jy * TX + jx;
@@ -333,7 +407,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                         ji[p] = __builtin_fma(q[jx], ei, ji[p]);
                     }
                 }
-                if (jy + 1 < TY) {
+                if (!REC && jy + 1 < TY) {
 #pragma unroll
                     for (int jx = 0; jx < TX; ++jx) {
                         fn[jx] = s_fxy[slot * NP + (jy + 1) * TX + jx];
@@ -361,11 +435,17 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
 }
 
 // One block per work item.
-template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB, bool REC>
 __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
 {
     __shared__ AmpSmem<TX, TY, WITHJ, MIXED> sm;
-    amp_item<TX, TY, WITHJ, MIXED>(L, blockIdx.x, sm);
+    // launched with one block per item, so this runs once; written as a loop because
+    // the register allocation of the hot loop comes out tighter in this form
+    // (measured in the gfx950 assembly: no copies or scratch in the recurrence form)
+    for (int64_t b = blockIdx.x; b < L.n_blocks; b += gridDim.x) {
+        amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
+        __syncthreads();
+    }
 }
 
 // Persistent form: a fixed grid of resident blocks pulls work items in launch
@@ -373,7 +453,7 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
 // exhausted; every block leaves the loop once a ticket is past the end.  The
 // ticket only schedules: every item writes its own partial slot, so results do
 // not depend on which block ran it.
-template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB, bool REC>
 __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
 {
     __shared__ AmpSmem<TX, TY, WITHJ, MIXED> sm;
@@ -384,7 +464,7 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
         const int64_t b = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();   // all lanes hold b before thread 0 may take the next ticket
         if (b >= L.n_blocks) break;
-        amp_item<TX, TY, WITHJ, MIXED>(L, b, sm);
+        amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
     }
 }
 
@@ -575,19 +655,29 @@ __global__ __launch_bounds__(256) void angle_kernel(const double *__restrict__ c
 // ---------------------------------------------------------------- launchers
 // grid_blocks > 0: persistent launch with that many blocks; 0: one block per item.
 // occupancy != nullptr: only report resident blocks per CU of the persistent kernel.
-template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
-static hipError_t launch_amp_t(const AmpLaunch &L, int grid_blocks, hipStream_t st, int *occupancy)
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB, bool REC>
+static hipError_t launch_amp_r(const AmpLaunch &L, int grid_blocks, hipStream_t st, int *occupancy)
 {
     if (occupancy)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occupancy, reinterpret_cast<const void *>(amp_persistent<TX, TY, WITHJ, MIXED, MINB>), kBlock, 0);
+            occupancy, reinterpret_cast<const void *>(amp_persistent<TX, TY, WITHJ, MIXED, MINB, REC>), kBlock, 0);
     if (grid_blocks > 0)
-        hipLaunchKernelGGL((amp_persistent<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)grid_blocks),
+        hipLaunchKernelGGL((amp_persistent<TX, TY, WITHJ, MIXED, MINB, REC>), dim3((unsigned)grid_blocks),
                            dim3(kBlock), 0, st, L);
     else
-        hipLaunchKernelGGL((amp_kernel<TX, TY, WITHJ, MIXED, MINB>), dim3((unsigned)L.n_blocks),
+        hipLaunchKernelGGL((amp_kernel<TX, TY, WITHJ, MIXED, MINB, REC>), dim3((unsigned)L.n_blocks),
                            dim3(kBlock), 0, st, L);
     return hipGetLastError();
+}
+
+// The recurrence form exists for FP64 only: in the mixed form a hardware phase
+// factor costs about as much as the complex products that would replace it.
+template <int TX, int TY, bool WITHJ, bool MIXED, int MINB>
+static hipError_t launch_amp_t(const AmpLaunch &L, int grid_blocks, hipStream_t st, int *occupancy)
+{
+    if constexpr (!MIXED)
+        if (L.rec) return launch_amp_r<TX, TY, WITHJ, false, MINB, true>(L, grid_blocks, st, occupancy);
+    return launch_amp_r<TX, TY, WITHJ, MIXED, MINB, false>(L, grid_blocks, st, occupancy);
 }
 
 template <bool WITHJ, bool MIXED>

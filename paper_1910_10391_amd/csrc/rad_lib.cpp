@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -42,6 +43,7 @@ struct rad_grid {
     double *d_hw = nullptr, *d_k = nullptr, *d_thx = nullptr, *d_thy = nullptr;
     double *d_wx = nullptr, *d_wy = nullptr;
     std::vector<double> hw, thx, thy;
+    double dth = 0.0;   // common spacing of uniform thx and thy, or 0
     // pinned staging for descriptor uploads, reused after its last copy completed
     std::mutex mu;
     void *stage = nullptr;
@@ -330,6 +332,7 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
         d.k = g->d_k;
         d.thx = g->d_thx;
         d.thy = g->d_thy;
+        d.dth = g->dth;
         d.n_w = g->n_w;
         d.n_x = g->n_x;
         d.n_y = g->n_y;
@@ -436,6 +439,7 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
     AmpLaunch L{};
     L.n_segs = P.n_segs;
     L.items = nullptr;
+    L.rec = g->dth != 0.0 ? 1 : 0;
     auto set_tile = [&](const Tile &t, int64_t nb) {
         L.n_blocks = nb;
         L.wg = t.wg;
@@ -541,6 +545,31 @@ size_t workspace_for(const rad_grid *g, const std::vector<int64_t> &ns, int n_ou
     return layout(g, (int)ns.size(), n_out, kinds, sum).total;
 }
 
+// Spacing d of a uniform grid (th[j] = th[0] + j d to within a few units in the last
+// place of the largest |th|), or 0; 0 also for fewer than two points.
+double uniform_step(const std::vector<double> &th)
+{
+    const size_t n = th.size();
+    if (n < 2) return 0.0;
+    const double d = (th[n - 1] - th[0]) / (double)(n - 1);
+    if (!(d != 0.0)) return 0.0;
+    const double tol = 8.0 * std::numeric_limits<double>::epsilon() * std::max(std::fabs(th[0]), std::fabs(th[n - 1]));
+    for (size_t j = 0; j < n; ++j)
+        if (std::fabs(th[j] - (th[0] + (double)j * d)) > tol) return 0.0;
+    return d;
+}
+
+// The spacing the phase recurrence uses: thx and thy uniform with the same spacing
+// (one axis of a single direction takes the other's), else 0.
+double common_step(const std::vector<double> &thx, const std::vector<double> &thy)
+{
+    const double dx = uniform_step(thx), dy = uniform_step(thy);
+    if (thx.size() < 2) return dy;
+    if (thy.size() < 2) return dx;
+    if (dx == 0.0 || dy == 0.0) return 0.0;
+    return std::fabs(dx - dy) <= 8.0 * std::numeric_limits<double>::epsilon() * std::fabs(dx) ? dx : 0.0;
+}
+
 std::vector<double> cell_widths(const std::vector<double> &th)
 {
     const size_t n = th.size();
@@ -595,6 +624,7 @@ rad_status rad_setup_grid(const double *hw_eV, int n_w, const double *thx, int n
     g->hw.assign(hw_eV, hw_eV + n_w);
     g->thx.assign(thx, thx + n_x);
     g->thy.assign(thy, thy + n_y);
+    g->dth = common_step(g->thx, g->thy);
     std::vector<double> k(n_w);
     for (int i = 0; i < n_w; ++i) k[i] = hw_eV[i] / kHbarC_eVm;
     const std::vector<double> wx = cell_widths(g->thx), wy = cell_widths(g->thy);
@@ -640,6 +670,13 @@ rad_status rad_grid_dims(const rad_grid *g, int *n_w, int *n_x, int *n_y)
     if (n_w) *n_w = g->n_w;
     if (n_x) *n_x = g->n_x;
     if (n_y) *n_y = g->n_y;
+    return RAD_OK;
+}
+
+rad_status rad_grid_step(const rad_grid *g, double *dth)
+{
+    if (!g || !dth) return fail(RAD_EINVAL, "grid or dth is NULL");
+    *dth = g->dth;
     return RAD_OK;
 }
 
@@ -925,6 +962,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
         d.k = g->d_k;
         d.thx = g->d_thx + (size_t)ci * cx;
         d.thy = g->d_thy + (size_t)cj * cy;
+        d.dth = g->dth;
         d.n_w = n_w;
         d.n_x = cx;
         d.n_y = cy;
@@ -998,6 +1036,7 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
         L.wg = kCellWg;
         L.nt = kWavesPerBlock / kCellWg;
         L.quantum = quantum ? 1 : 0;
+        L.rec = g->dth != 0.0 ? 1 : 0;
         L.comps = comps;
         L.part = part;
         L.counter = nullptr;

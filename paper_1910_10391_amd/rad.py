@@ -50,6 +50,7 @@ def lib():
                 "rad_setup_grid": (I, [D, I, D, I, D, I, P, ctypes.POINTER(P)]),
                 "rad_free_grid": (None, [P]),
                 "rad_grid_dims": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+                "rad_grid_step": (I, [P, D]),
                 "rad_workspace_bytes": (S, [P, I64, I, I]),
                 "rad_batch_workspace_bytes": (S, [P, SP, I, I, I, I]),
                 "rad_classical": (I, [P, SP, I, P, P, S, P]),
@@ -118,6 +119,13 @@ class Grid:
     @property
     def shape(self):
         return (self.hw.size, self.thy.size, self.thx.size)
+
+    @property
+    def step(self):
+        """The common direction spacing of the FP64 phase recurrence, or 0 (rad_grid_step)."""
+        d = ctypes.c_double()
+        _check(lib().rad_grid_step(self.handle, ctypes.byref(d)), "rad_grid_step")
+        return d.value
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

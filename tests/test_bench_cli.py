@@ -21,6 +21,9 @@ def test_flop_accounting():
     # 8 phase factors per 16 evaluations x 34 flops, complex product 6, accumulations 12
     assert bench.flops_per_eval(0, True) == 34.0 * 8 / 16 + 6 + 12
     assert bench.flops_per_eval(0, False) == 34.0 * 8 / 16 + 6 + 8
+    # uniform grid, 4 x 4 tile: 5 phase factors and 10 complex products per 16 evaluations
+    assert bench.flops_per_eval(0, True, True) == (5 * 34.0 + 10 * 6.0) / 16 + 6 + 12
+    assert bench.flops_per_eval(1, True, True) == (5 * 34.0 + 8 * 6.0) / 12 + 6 + 12
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
 
 

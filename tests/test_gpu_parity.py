@@ -147,6 +147,35 @@ def test_mixed_precision(rad):
             assert_parity(out[o, i], ref[o, i], th, th, MIXED_TOL, "mixed traj %d kind %d" % (o, i))
 
 
+def test_phase_recurrence_and_direct_forms(rad):
+    """Uniform grids with one spacing take the FP64 phase recurrence, others the direct
+    phase factors; both against the oracle, through one-block-per-item and persistent
+    launches, with partial tiles."""
+    cfg, tr = _small_channeling(2, seed=29)
+    segs = [tr[0][0], tr[1][0]]
+    gm = segs[0]["gamma"]
+    hw = analytic.log_omega(70, 0.5e6, 200e6)
+    u9 = analytic.cell_centred(9, 5.0 / gm)
+    u7 = analytic.cell_centred(7, 5.0 / gm * 7 / 9)            # the same spacing, 7 points
+    rng = np.random.default_rng(5)
+    irregular = np.sort(rng.uniform(-5.0 / gm, 5.0 / gm, 6))
+    cases = [(u9, u9, True), (u9, u7, True), (u9, analytic.cell_centred(7, 4.0 / gm), False),
+             (irregular, u9, False), (u9[:1], u7, True)]
+    for thx, thy, rec in cases:
+        grid = rad.Grid(hw, thx, thy)
+        assert (grid.step != 0.0) == rec, (len(thx), len(thy), grid.step)
+        if rec and len(thx) > 1:
+            assert abs(grid.step - (thx[1] - thx[0])) < 1e-12 * abs(thx[1] - thx[0])
+        ref = oracle.batch(segs, [0, 1], 2, hw, thx, thy, 7)
+        out = _cpu(rad.batch(grid, segs, [0, 1], 2, 7))
+        outp = _cpu(rad.Plan(grid, segs, [0, 1], 2, 7).launch())
+        for o in range(2):
+            for i in range(3):
+                what = "%s %dx%d out %d kind %d" % ("recurrence" if rec else "direct", len(thx), len(thy), o, i)
+                assert_parity(out[o, i], ref[o, i], thx, thy, FP64_TOL, what)
+                assert_parity(outp[o, i], ref[o, i], thx, thy, FP64_TOL, "persistent " + what)
+
+
 def test_variants_agree(rad):
     """Every kernel variant (direction tile, occupancy), one-block-per-item and persistent,
     FP64 and mixed, on a 9 x 9 grid that leaves partial direction tiles."""
