@@ -61,3 +61,6 @@ def test_validation_before_device(lib):
     assert lib.rad_batch_workspace_bytes(None, None, 0, 1, 1, 0) == 0
     assert lib.rad_tune_set_variant(0, 0, 0, 99) == 1
     assert lib.rad_tune_num_variants() >= 1
+    d = ctypes.c_double(5.0)
+    assert lib.rad_grid_step(None, ctypes.byref(d)) == 1 and d.value == 5.0
+    assert b"NULL" in lib.rad_last_error()
