@@ -29,9 +29,11 @@
 //     Px = 1/(2g^2) t - dz + thx (thx t/2 - x), Py = thy (thy t/2 - y), so a lane
 //     evaluates TX + TY phase factors per time step and forms the TX*TY
 //     factors exp(i kappa psi) = exp(i kappa Px) exp(i kappa Py) by complex
-//     products;
+//     products; on a uniform grid (REC) Px and Py are quadratic in the direction
+//     index and the FP64 form gets a tile's factors from 5 evaluated ones by
+//     recurrence;
 //   * a long segment is cut into time chunks whose FP64 partial amplitudes are
-//     summed in chunk order by fin_kernel.
+//     summed in a fixed order by fin_kernel.
 #include <hip/hip_runtime.h>
 
 #include "rad_internal.h"
