@@ -463,6 +463,22 @@ def cpu_baseline(segs, grid, traj, iw, ix, iy):
     return ref, evals / dt, dt, threads, evals
 
 
+def cpu_single_core(segs, grid, traj, iw, ix, iy):
+    """The oracle on one host core: the shortest trajectory of the sample at every 4th of
+    its photon energies and its directions (a few seconds); evals/s and what it was."""
+    import oracle
+    p = min(traj, key=lambda i: segs[i]["t"].size)
+    hw, thx, thy = grid.hw_eV[iw[::4]], grid.thx[ix], grid.thy[iy]
+    oracle.spectrum(segs[p], hw[:1], thx[:1], thy[:1], oracle.KIND_SPINHALF, threads=1)   # warm-up
+    t0 = time.perf_counter()
+    oracle.spectrum(segs[p], hw, thx, thy, oracle.KIND_SPINHALF, threads=1)
+    dt = time.perf_counter() - t0
+    evals = segs[p]["t"].size * hw.size * thx.size * thy.size
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1,
+            "sample": "trajectory %d, %d photon energies x %dx%d directions, %.3e evals in %.1f s"
+                      % (p, hw.size, thx.size, thy.size, evals, dt)}
+
+
 def rel_metrics(got, ref):
     d = got - ref
     m1 = float(np.linalg.norm(d) / np.linalg.norm(ref))
@@ -577,7 +593,8 @@ def main():
                          "energies x 8x8 strided directions, spin-1/2, %.3e evals in %.1f s; "
                          "host %s, nproc %d" % (len(traj), n_w, cevals, cpu_dt, cpu_model(),
                                                 os.cpu_count() or 0),
-               "trajectories_per_s_extrapolated": rate / (evals / len(segs))}
+               "trajectories_per_s_extrapolated": rate / (evals / len(segs)),
+               "single_core": cpu_single_core(segs, g, traj, iw, ix, iy)}
         got = out[:, 0].cpu().numpy()
         sel = np.ix_(iw, iy, ix)
         m64 = [rel_metrics(got[p][sel], ref[p]) for p in traj]
