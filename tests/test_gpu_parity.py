@@ -160,7 +160,8 @@ def test_phase_recurrence_and_direct_forms(rad):
     rng = np.random.default_rng(5)
     irregular = np.sort(rng.uniform(-5.0 / gm, 5.0 / gm, 6))
     cases = [(u9, u9, True), (u9, u7, True), (u9, analytic.cell_centred(7, 4.0 / gm), False),
-             (irregular, u9, False), (u9[:1], u7, True)]
+             (irregular, u9, False), (u9[:1], u7, True), (u9[::-1].copy(), u9[::-1].copy(), True),
+             (u9, u9[::-1].copy(), False)]
     for thx, thy, rec in cases:
         grid = rad.Grid(hw, thx, thy)
         assert (grid.step != 0.0) == rec, (len(thx), len(thy), grid.step)
