@@ -60,11 +60,11 @@ VALU_PER_EVAL_44 = {(True, False): 351.0 / 16.0, (False, False): 319.0 / 16.0,
                     (True, True): 323.0 / 16.0, (False, True): 290.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
-# for the kernel sources they were measured on (sha256 prefix below; a change of
-# comments only is carried over after checking that the gfx950 assembly is identical).
+# for the kernel sources they were measured on (sha256 prefix below; a source change
+# that leaves amp_kernel's gfx950 assembly identical is carried over after checking that).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "15a182c00f9de761", "particles": 256, "bytes_per_launch": 4.4796e10}
+MEASURED_TRAFFIC = {"sources_sha256": "ee5476af345c2cef", "particles": 256, "bytes_per_launch": 4.4796e10}
 
 
 def kernel_sources_sha():

@@ -477,12 +477,12 @@ __global__ void reset_counters_kernel(unsigned *c, int n)
 }
 
 // Sum of the n chunk partials p[0], p[stride], ..., p[(n-1) stride] in a fixed order:
-// partial c goes to running sum c % 8 and the eight sums are added pairwise, so that
-// eight loads are in flight instead of one (a small problem cut into many short chunks
+// partial c goes to running sum c % 16 and the sixteen sums are added pairwise, so that
+// sixteen loads are in flight instead of one (a small problem cut into many short chunks
 // would otherwise wait on one load latency per chunk).
 __device__ __forceinline__ double2 chunk_sum(const double2 *__restrict__ p, int64_t stride, int n)
 {
-    constexpr int K = 8;
+    constexpr int K = 16;
     double2 s[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) s[j] = make_double2(0.0, 0.0);
@@ -507,8 +507,15 @@ __device__ __forceinline__ double2 chunk_sum(const double2 *__restrict__ p, int6
             s[j].x += v.x;
             s[j].y += v.y;
         }
-    return make_double2(((s[0].x + s[1].x) + (s[2].x + s[3].x)) + ((s[4].x + s[5].x) + (s[6].x + s[7].x)),
-                        ((s[0].y + s[1].y) + (s[2].y + s[3].y)) + ((s[4].y + s[5].y) + (s[6].y + s[7].y)));
+    // pairwise: 16 -> 8 -> 4 -> 2 -> 1
+#pragma unroll
+    for (int h = K / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            s[j].x += s[j + h].x;
+            s[j].y += s[j + h].y;
+        }
+    return s[0];
 }
 
 __device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
