@@ -137,7 +137,7 @@ constexpr int64_t kTargetBlocks = 2048;  // 256 CUs x 2 resident blocks x 4 roun
 // Chunk lengths are multiples of kMinChunk samples.  A small problem (few direction
 // tiles and photon energies) is cut this fine so that its blocks, each a single
 // latency-bound wave per SIMD, stay short; fin_kernel sums the many partials with
-// eight loads in flight.
+// sixteen loads in flight.
 constexpr int64_t kMinChunk = 16;
 
 // chunks per segment when the launch has `n_segs` segments
