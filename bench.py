@@ -40,31 +40,33 @@ VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2)}
 def flops_per_eval(variant, with_j=True, recurrence=False):
     """FP64 flops per (t, w, n) eval of the amplitude kernel (FMA = 2).  Phase factors,
     34 flops each (phase product, exact reduction, f^2, an 8-term sine and a 9-term
-    cosine polynomial, f * poly): TX + TY per time step for TX*TY directions; on a
-    uniform grid (recurrence) 5 (the first factor along x and along y, their two
-    multipliers and the shared second-difference factor) plus 2 (TX + TY) - 6 complex
-    products (6 flops each).  Then per eval a complex product (6) and 2 flops per real
-    accumulator (A_x, A_y and J: 12)."""
+    cosine polynomial, f * poly); complex products 6 flops each.  The first row of a
+    TX x TY direction tile is folded into the x factors, so per time step the direct
+    form evaluates TX + TY - 1 factors and forms TX (TY - 1) products; on a uniform grid
+    (recurrence) it evaluates 4 (the tile's first factor, the multipliers along x and y
+    and the shared second-difference factor) and forms 2 TX - 3 + 2 TY - 4 more products
+    for the recurrences.  Then 2 flops per real accumulator and eval (A_x, A_y and J: 12)."""
     tx, ty, _ = VARIANTS[variant]
+    rows = tx * (ty - 1)
     if recurrence:
-        phase = (5 * 34.0 + 6.0 * (2 * (tx + ty) - 6)) / (tx * ty)
+        phase = (4 * 34.0 + 6.0 * (rows + 2 * tx - 3 + 2 * ty - 4)) / (tx * ty)
     else:
-        phase = 34.0 * (tx + ty) / (tx * ty)
-    return phase + 6.0 + (12.0 if with_j else 8.0)
+        phase = (34.0 * (tx + ty - 1) + 6.0 * rows) / (tx * ty)
+    return phase + (12.0 if with_j else 8.0)
 
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
 # FP64 kernel, counted in the gfx950 assembly of this build: direct phase factors
-# 351 per 16 evals with J (319 without), recurrence on a uniform grid 323 (290).
-VALU_PER_EVAL_44 = {(True, False): 351.0 / 16.0, (False, False): 319.0 / 16.0,
-                    (True, True): 323.0 / 16.0, (False, True): 290.0 / 16.0}
+# 311 per 16 evals with J (279 without), recurrence on a uniform grid 279 (246).
+VALU_PER_EVAL_44 = {(True, False): 311.0 / 16.0, (False, False): 279.0 / 16.0,
+                    (True, True): 279.0 / 16.0, (False, True): 246.0 / 16.0}
 # HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below; a source change
 # that leaves amp_kernel's gfx950 assembly identical is carried over after checking that).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "ee5476af345c2cef", "particles": 256, "bytes_per_launch": 4.4796e10}
+MEASURED_TRAFFIC = {"sources_sha256": "3501a5dc8285bfc8", "particles": 256, "bytes_per_launch": 4.7665e10}
 
 
 def kernel_sources_sha():

@@ -80,6 +80,7 @@ struct FinLaunch {
     int n_out;
     int kinds;
     int n_kinds;
+    int one_chunk;              // every segment is a single time chunk
     double *out;                // [n_out][n_kinds][n_w][n_y][n_x]
 };
 

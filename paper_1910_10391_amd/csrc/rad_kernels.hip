@@ -26,12 +26,13 @@
 //     the phase are computed once per (time step, direction) by the whole
 //     block into LDS, then read by each wave as a broadcast (one address);
 //   * the phase separates, psi = Px(t, thx) + Py(t, thy) with
-//     Px = 1/(2g^2) t - dz + thx (thx t/2 - x), Py = thy (thy t/2 - y), so a lane
-//     evaluates TX + TY phase factors per time step and forms the TX*TY
-//     factors exp(i kappa psi) = exp(i kappa Px) exp(i kappa Py) by complex
-//     products; on a uniform grid (REC) Px and Py are quadratic in the direction
-//     index and the FP64 form gets a tile's factors from 5 evaluated ones by
-//     recurrence;
+//     Px = 1/(2g^2) t - dz + thx (thx t/2 - x), Py = thy (thy t/2 - y).  The
+//     tile's first row is folded into the x part: with X_jx = exp(i kappa (Px_jx
+//     + Py_0)) and Y_jy = exp(i kappa (Py_jy - Py_0)), exp(i kappa psi) = X_jx Y_jy
+//     and Y_0 = 1, so a lane evaluates TX + TY - 1 phase factors per time step and
+//     forms the other factors with (TY - 1) TX complex products; on a uniform grid
+//     (REC) Px and Py are quadratic in the direction index and the FP64 form gets
+//     a tile's factors from 4 evaluated ones by recurrence;
 //   * a long segment is cut into time chunks whose FP64 partial amplitudes are
 //     summed in a fixed order by fin_kernel.
 #include <hip/hip_runtime.h>
@@ -269,30 +270,30 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             if constexpr (WITHJ) s_fq[i] = fq;
         }
         if constexpr (REC) {
-            // uniform grids: per (time step, tile) the phase parts of the tile's first
+            // uniform grids: per (time step, tile) the phase of the tile's first
             // direction and the multipliers of the recurrence along x and y (below)
             const double dth = S.dth;
-            for (int i = threadIdx.x; i < kSlots * 5; i += kBlock) {
-                const int slot = i / 5, j = i % 5;
+            for (int i = threadIdx.x; i < kSlots * 4; i += kBlock) {
+                const int slot = i >> 2, j = i & 3;
                 const int tloc = slot / nt, tile = slot % nt;
                 const int64_t k = k0 + tloc;
                 double v = 0.0;
                 if (k < k_end && grp * nt + tile < n_tiles) {
                     const double t = col(C_T, tloc, k);
-                    double th0;
-                    (void)direction(tile, j < 3 ? 0 : TX, th0);
+                    double thx0, thy0;
+                    (void)direction(tile, 0, thx0);
+                    (void)direction(tile, TX, thy0);
                     if (j == 0)
-                        v = (c0 * t - col(C_DZ, tloc, k)) + th0 * (0.5 * th0 * t - col(C_X, tloc, k));
+                        v = ((c0 * t - col(C_DZ, tloc, k)) + thx0 * (0.5 * thx0 * t - col(C_X, tloc, k))) +
+                            thy0 * (0.5 * thy0 * t - col(C_Y, tloc, k));
                     else if (j == 1)
-                        v = dth * ((th0 + 0.5 * dth) * t - col(C_X, tloc, k));
+                        v = dth * ((thx0 + 0.5 * dth) * t - col(C_X, tloc, k));
                     else if (j == 2)
                         v = dth * dth * t;
-                    else if (j == 3)
-                        v = th0 * (0.5 * th0 * t - col(C_Y, tloc, k));
                     else
-                        v = dth * ((th0 + 0.5 * dth) * t - col(C_Y, tloc, k));
+                        v = dth * ((thy0 + 0.5 * dth) * t - col(C_Y, tloc, k));
                 }
-                if (j < 3) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - 3)] = v;
+                if (j < 3) s_px[slot * TX + j] = v; else s_py[slot * TY] = v;
             }
         } else {
             for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
@@ -301,13 +302,16 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                 const int64_t k = k0 + tloc;
                 double v = 0.0;
                 if (k < k_end && grp * nt + tile < n_tiles) {
-                    const double t = col(C_T, tloc, k);
-                    double th;
+                    const double t = col(C_T, tloc, k), y = col(C_Y, tloc, k);
+                    double th, thy0;
                     (void)direction(tile, j, th);
+                    (void)direction(tile, TX, thy0);
+                    // Px_jx + Py_0, and Py_jy - Py_0 written as a product (0 for jy = 0)
                     if (j < TX)
-                        v = (c0 * t - col(C_DZ, tloc, k)) + th * (0.5 * th * t - col(C_X, tloc, k));
+                        v = ((c0 * t - col(C_DZ, tloc, k)) + th * (0.5 * th * t - col(C_X, tloc, k))) +
+                            thy0 * (0.5 * thy0 * t - y);
                     else
-                        v = th * (0.5 * th * t - col(C_Y, tloc, k));
+                        v = (th - thy0) * (0.5 * (th + thy0) * t - y);
                 }
                 if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
             }
@@ -322,7 +326,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             // so that their latency is hidden
             double2 fn[TX];
             double qn[TX];
-            double pyn = s_py[slot * TY];
+            double pyn = (MIXED && TY > 1) ? s_py[slot * TY + 1] : 0.0;
 #pragma unroll
             for (int jx = 0; jx < TX; ++jx) {
                 fn[jx] = s_fxy[slot * NP + jx];
@@ -330,8 +334,9 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             }
             // uniform grids: the phase along x and along y is quadratic in the direction
             // index, so from the tile's first factor X_0 and R_0 = exp(i kappa a),
-            // B = exp(i kappa dth^2 t), X_{j+1} = X_j R_j with R_{j+1} = R_j B (and the
-            // same along y with S): 5 phase factors per time step instead of TX + TY
+            // B = exp(i kappa dth^2 t), X_{j+1} = X_j R_j with R_{j+1} = R_j B (and
+            // along y Y_1 = S_0, Y_{j+1} = Y_j S_j, S_{j+1} = S_j B): 4 phase factors per
+            // time step instead of TX + TY - 1
             double br = 0.0, bi = 0.0, sr = 0.0, si = 0.0;
             if constexpr (REC) {
                 double rr, ri;
@@ -348,7 +353,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                         rr = t_;
                     }
                 }
-                lane_cis<false>(kh, s_py[slot * TY + 1], sr, si);
+                lane_cis<false>(kh, s_py[slot * TY], sr, si);
             } else {
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
@@ -375,31 +380,34 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                         if constexpr (WITHJ) q[jx] = qn[jx];
                     }
                 }
+                // row 0: Y_0 = 1
                 if constexpr (REC) {
-                    if (jy == 0) {
-                        lane_cis<false>(kh, pyn, yr, yi);
-                    } else {
-                        // Y_jy = Y_{jy-1} S_{jy-1}, then S_jy = S_{jy-1} B
+                    if (jy == 1) {
+                        yr = sr;
+                        yi = si;
+                    } else if (jy > 1) {
+                        // Y_jy = Y_{jy-1} S_{jy-1}
                         const double t_ = yr * sr - yi * si;
                         yi = yr * si + yi * sr;
                         yr = t_;
-                        if (jy + 1 < TY) {
-                            const double u_ = sr * br - si * bi;
-                            si = sr * bi + si * br;
-                            sr = u_;
-                        }
                     }
-                } else {
+                    if (jy > 0 && jy + 1 < TY) {
+                        // S_jy = S_{jy-1} B
+                        const double u_ = sr * br - si * bi;
+                        si = sr * bi + si * br;
+                        sr = u_;
+                    }
+                } else if (jy > 0) {
                     // this row's phase part; the next row's is read one region ahead
-                    const double py = pyn;
-                    if (jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
+                    const double py = MIXED ? pyn : s_py[slot * TY + jy];
+                    if (MIXED && jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
                     lane_cis<MIXED>(kh, py, yr, yi);
                 }
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) {
                     const int p = jy * TX + jx;
-                    const double er = xr[jx] * yr - xi[jx] * yi;
-                    const double ei = xr[jx] * yi + xi[jx] * yr;
+                    const double er = jy == 0 ? xr[jx] : xr[jx] * yr - xi[jx] * yi;
+                    const double ei = jy == 0 ? xi[jx] : xr[jx] * yi + xi[jx] * yr;
                     axr[p] = __builtin_fma(f[jx].x, er, axr[p]);
                     axi[p] = __builtin_fma(f[jx].x, ei, axi[p]);
                     ayr[p] = __builtin_fma(f[jx].y, er, ayr[p]);
@@ -460,14 +468,14 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
 {
     __shared__ AmpSmem<TX, TY, WITHJ, MIXED> sm;
     __shared__ int s_item;
-    for (;;) {
+    auto ticket = [&]() -> int64_t {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(L.counter, 1u);
         __syncthreads();
-        const int64_t b = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();   // all lanes hold b before thread 0 may take the next ticket
-        if (b >= L.n_blocks) break;
-        amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
-    }
+        const int64_t t = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();   // all lanes hold the ticket before thread 0 may take the next
+        return t;
+    };
+    for (int64_t b = ticket(); b < L.n_blocks; b = ticket()) amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
 }
 
 // Tickets start at zero for every launch (a kernel, so graphs hold no memset node).
@@ -518,16 +526,21 @@ __device__ __forceinline__ double2 chunk_sum(const double2 *__restrict__ p, int6
     return s[0];
 }
 
+// ONE: every segment of the launch is a single chunk, and its partial is the sum (the
+// same value chunk_sum returns for n = 1, without the sixteen running sums' registers)
+template <bool ONE>
 __device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
                                            int comps, int comp, int64_t n_n, int n_w, int64_t nn,
                                            int iw, double &re, double &im)
 {
     const int64_t stride = (int64_t)comps * n_n * n_w;
-    const double2 v = chunk_sum(part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw, stride, d.n_chunks);
+    const double2 *p = part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw;
+    const double2 v = ONE ? *p : chunk_sum(p, stride, d.n_chunks);
     re = v.x;
     im = v.y;
 }
 
+template <bool ONE>
 __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
 {
     const int64_t n_n = (int64_t)F.n_x * F.n_y;
@@ -545,8 +558,8 @@ __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
         if (F.kinds & 1) {
             const SegDesc &d = F.cls[s];
             double xr, xi, yr, yi;
-            sum_chunks(F.part_c, d, 2, 0, n_n, F.n_w, nn, iw, xr, xi);
-            sum_chunks(F.part_c, d, 2, 1, n_n, F.n_w, nn, iw, yr, yi);
+            sum_chunks<ONE>(F.part_c, d, 2, 0, n_n, F.n_w, nn, iw, xr, xi);
+            sum_chunks<ONE>(F.part_c, d, 2, 1, n_n, F.n_w, nn, iw, yr, yi);
             const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
             sc += pref * (xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi);
         }
@@ -555,15 +568,15 @@ __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
             const double E = d.energy;
             if (hw < E) {
                 double xr, xi, yr, yi;
-                sum_chunks(F.part_q, d, F.comps_q, 0, n_n, F.n_w, nn, iw, xr, xi);
-                sum_chunks(F.part_q, d, F.comps_q, 1, n_n, F.n_w, nn, iw, yr, yi);
+                sum_chunks<ONE>(F.part_q, d, F.comps_q, 0, n_n, F.n_w, nn, iw, xr, xi);
+                sum_chunks<ONE>(F.part_q, d, F.comps_q, 1, n_n, F.n_w, nn, iw, yr, yi);
                 const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
                 const double S = xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi;
                 const double Es = E - hw;
                 if (F.kinds & 2) s0 += pref * (Es / E) * S;
                 if (F.kinds & 4) {
                     double jr_, ji_;
-                    sum_chunks(F.part_q, d, F.comps_q, 2, n_n, F.n_w, nn, iw, jr_, ji_);
+                    sum_chunks<ONE>(F.part_q, d, F.comps_q, 2, n_n, F.n_w, nn, iw, jr_, ji_);
                     const double SJ = jr_ * jr_ + ji_ * ji_;
                     sh += pref * ((Es * Es + E * E) / (2.0 * E * E) * S +
                                   hw * hw / (2.0 * E * E * d.gamma * d.gamma) * SJ);
@@ -731,7 +744,10 @@ hipError_t launch_fin(const FinLaunch &F, hipStream_t st)
 {
     const int64_t items = (int64_t)F.n_x * F.n_y * F.n_w;
     const unsigned gx = (unsigned)((items + 255) / 256);
-    hipLaunchKernelGGL(fin_kernel, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
+    if (F.one_chunk)
+        hipLaunchKernelGGL(fin_kernel<true>, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
+    else
+        hipLaunchKernelGGL(fin_kernel<false>, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
     return hipGetLastError();
 }
 

@@ -244,6 +244,7 @@ struct Plan {
     std::vector<char> host;      // descriptor region, uploaded to ws[0, lay.desc_bytes)
     bool persistent = false;
     int pgrid_c = 0, pgrid_q = 0;  // persistent grid sizes
+    bool one_chunk = false;        // every segment is a single time chunk
 };
 
 rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index,
@@ -281,6 +282,7 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
         plan_chunks(segs[s].n, cf, nch[s], clen[s]);
         sum_chunks += nch[s];
     }
+    P.one_chunk = sum_chunks == n_segs;
     P.lay = layout(g, n_segs, n_out, kinds, sum_chunks);
     if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < P.lay.total)
@@ -500,6 +502,7 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
     F.n_out = P.n_out;
     F.kinds = P.kinds;
     F.n_kinds = P.n_kinds;
+    F.one_chunk = P.one_chunk ? 1 : 0;
     F.out = out;
     hipError_t e = launch_fin(F, st);
     if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");

@@ -18,12 +18,14 @@ def test_more_than_one_gpu_is_refused():
 def test_flop_accounting():
     sys.path.insert(0, ROOT)
     import bench
-    # 8 phase factors per 16 evaluations x 34 flops, complex product 6, accumulations 12
-    assert bench.flops_per_eval(0, True) == 34.0 * 8 / 16 + 6 + 12
-    assert bench.flops_per_eval(0, False) == 34.0 * 8 / 16 + 6 + 8
-    # uniform grid, 4 x 4 tile: 5 phase factors and 10 complex products per 16 evaluations
-    assert bench.flops_per_eval(0, True, True) == (5 * 34.0 + 10 * 6.0) / 16 + 6 + 12
-    assert bench.flops_per_eval(1, True, True) == (5 * 34.0 + 8 * 6.0) / 12 + 6 + 12
+    # 4x4 tile: 7 evaluated phase factors and 12 complex products per 16 evals
+    assert bench.flops_per_eval(0, True) == (7 * 34.0 + 12 * 6.0) / 16 + 12
+    assert bench.flops_per_eval(0, False) == (7 * 34.0 + 12 * 6.0) / 16 + 8
+    # recurrence, 4x4: 4 evaluated factors; x: 3 products + 2 multiplier steps, y: 2 + 2,
+    # rows 1..3: 12 (28.375 flops per eval)
+    assert bench.flops_per_eval(0, True, True) == (4 * 34.0 + 21 * 6.0) / 16 + 12 == 28.375
+    # 4x3: x 3 + 2, y 1 + 1, rows 8
+    assert bench.flops_per_eval(1, True, True) == (4 * 34.0 + 15 * 6.0) / 12 + 12
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
 
 

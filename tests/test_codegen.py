@@ -16,10 +16,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # (kernel symbol, VALU instructions in the hot loop per 16 evaluations)
 HOT = {
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 323,   # FP64, J, recurrence
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 351,   # FP64, J, direct
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 228,   # mixed, J
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 323,
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,   # FP64, J, recurrence
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,   # FP64, J, direct
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 204,   # mixed, J
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 204,
 }
 
 
