@@ -322,15 +322,17 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         for (int tloc = 0; tloc < tn; ++tloc) {
             const int slot = tloc * nt + tl;
             double xr[TX], xi[TX];
-            // row 0's integrand values and phase part, read before the X phase factors
-            // so that their latency is hidden
+            // the direct forms read row 0's integrand values (and the mixed form row 1's
+            // phase part) before the X phase factors, so that their latency is hidden
             double2 fn[TX];
             double qn[TX];
             double pyn = (MIXED && TY > 1) ? s_py[slot * TY + 1] : 0.0;
+            if constexpr (!REC) {
 #pragma unroll
-            for (int jx = 0; jx < TX; ++jx) {
-                fn[jx] = s_fxy[slot * NP + jx];
-                if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + jx];
+                for (int jx = 0; jx < TX; ++jx) {
+                    fn[jx] = s_fxy[slot * NP + jx];
+                    if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + jx];
+                }
             }
             // uniform grids: the phase along x and along y is quadratic in the direction
             // index, so from the tile's first factor X_0 and R_0 = exp(i kappa a),
@@ -398,7 +400,9 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                         sr = u_;
                     }
                 } else if (jy > 0) {
-                    // this row's phase part; the next row's is read one region ahead
+                    // this row's phase part: the mixed form reads the next row's one region
+                    // ahead; the FP64 direct form reads it here (with that prefetch the
+                    // allocator spilled two accumulators in this loop)
                     const double py = MIXED ? pyn : s_py[slot * TY + jy];
                     if (MIXED && jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
                     lane_cis<MIXED>(kh, py, yr, yi);
