@@ -34,7 +34,7 @@ METRIC = ("(t·ω·n) integrand evals/s and trajectories/s; "
 FP64_PEAK_TFLOPS = 78.6
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # VALU lane-instructions per second, 1e12
 # Amplitude-kernel variants: direction tile (TX, TY) per lane and resident blocks per CU.
-VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2)}
+VARIANTS = {0: (4, 4, 2), 1: (4, 3, 2), 2: (4, 4, 1), 3: (4, 2, 2), 4: (4, 6, 2)}
 
 
 def flops_per_eval(variant, with_j=True, recurrence=False):
@@ -66,7 +66,7 @@ VALU_PER_EVAL_44 = {(True, False): 311.0 / 16.0, (False, False): 279.0 / 16.0,
 # that leaves amp_kernel's gfx950 assembly identical is carried over after checking that).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "7ff8c923e6c3da80", "particles": 256, "bytes_per_launch": 4.7712e10}
+MEASURED_TRAFFIC = {"sources_sha256": "fb6a58ad8dead3dc", "particles": 256, "bytes_per_launch": 4.7712e10}
 
 
 def kernel_sources_sha():

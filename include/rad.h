@@ -219,13 +219,15 @@ const char *rad_last_error(void);
 
 /*
  * Tuning knobs of the amplitude kernel (process-wide), set by the autotuner.  A
- * variant fixes the direction tile each lane owns (4x4, 4x3, 4x2) and the
- * resident blocks per CU it is compiled for.  It is chosen per form
+ * variant fixes the direction tile each lane owns (0: 4x4, 1: 4x3, 2: 4x4 at one
+ * resident block per CU, 3: 4x2, 4: 4x6) and the resident blocks per CU it is
+ * compiled for (two unless stated).  It is chosen per form
  * (`persistent`: rad_plan_* vs the one-block-per-item calls), per precision
  * (`mixed`) and per integral set (`with_j`: the set that also carries J for
  * spin-1/2).  Every variant computes the same sums; only the speed differs.
  * A plan keeps the variants in force when it was created.
- * rad_tune_set_variant: RAD_EINVAL for an unknown variant.
+ * rad_tune_set_variant: RAD_EINVAL for an unknown variant; RAD_EUNSUPPORTED for
+ * variant 4 with with_j set (its 24 directions leave no registers for J).
  */
 rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant);
 rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *variant);

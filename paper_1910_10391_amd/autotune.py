@@ -130,7 +130,12 @@ def tune(grid, dsegs, kinds, precision=rad.FP64, persistent=False, sample=8, min
             continue
         times = {}
         for v in range(rad.tune_num_variants()):
-            rad.tune_set_variant(persistent, mixed, with_j, v)
+            try:
+                rad.tune_set_variant(persistent, mixed, with_j, v)
+            except rad.RadError as e:
+                if e.status == rad.EUNSUPPORTED:
+                    continue                     # a tile without room for this set's accumulators
+                raise
             times[v] = _time_variant(grid, sub, set_kinds, precision, persistent, reps)
             if verbose:
                 print("autotune %s variant %d: %.3f ms" % (k, v, times[v]), flush=True)

@@ -19,9 +19,12 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 128;  // time-steps x direction-tiles staged in LDS per pass
 
 // Amplitude-kernel variants: direction tile TX x TY and minimum resident blocks per CU.
-enum Variant { kVar44x2 = 0, kVar43x2 = 1, kVar44x1 = 2, kVar42x2 = 3, kNumVariants = 4 };
-constexpr int kVarTX[kNumVariants] = {4, 4, 4, 4};
-constexpr int kVarTY[kNumVariants] = {4, 3, 4, 2};
+enum Variant { kVar44x2 = 0, kVar43x2 = 1, kVar44x1 = 2, kVar42x2 = 3, kVar46x2 = 4, kNumVariants = 5 };
+constexpr int kVarTX[kNumVariants] = {4, 4, 4, 4, 4};
+constexpr int kVarTY[kNumVariants] = {4, 3, 4, 2, 6};
+// whether a variant serves the integral set with J: the 4x6 tile's 24 directions fill the
+// VGPRs with the A_x, A_y accumulators alone, so it serves only sets without J
+constexpr bool kVarJ[kNumVariants] = {true, true, true, true, false};
 
 enum Column { C_T = 0, C_X, C_Y, C_DZ, C_VX, C_VY, C_DVZ, C_AX, C_AY, C_AZ, C_NCOL };
 

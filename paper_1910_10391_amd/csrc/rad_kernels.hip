@@ -715,6 +715,9 @@ static hipError_t launch_amp_v(const AmpLaunch &L, int variant, int grid_blocks,
     case kVar43x2: return launch_amp_t<4, 3, WITHJ, MIXED, 2>(L, grid_blocks, st, occupancy);
     case kVar44x1: return launch_amp_t<4, 4, WITHJ, MIXED, 1>(L, grid_blocks, st, occupancy);
     case kVar42x2: return launch_amp_t<4, 2, WITHJ, MIXED, 2>(L, grid_blocks, st, occupancy);
+    case kVar46x2:
+        if constexpr (WITHJ) return hipErrorInvalidValue;   // rejected on the host first
+        else return launch_amp_t<4, 6, false, MIXED, 2>(L, grid_blocks, st, occupancy);
     default: return hipErrorInvalidValue;
     }
 }

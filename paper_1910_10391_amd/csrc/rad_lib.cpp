@@ -1089,6 +1089,9 @@ extern "C" {
 rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant)
 {
     if (variant < 0 || variant >= kNumVariants) return fail(RAD_EINVAL, "variant %d unknown", variant);
+    if (with_j && !kVarJ[variant])
+        return fail(RAD_EUNSUPPORTED, "variant %d (%dx%d tile) serves only integral sets without J", variant,
+                    kVarTX[variant], kVarTY[variant]);
     std::lock_guard<std::mutex> lk(g_var_mu);
     g_variant[persistent ? 1 : 0][mixed ? 1 : 0][with_j ? 1 : 0] = variant;
     return RAD_OK;

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "librad.so")
 
 CLASSICAL, SPIN0, SPINHALF = 1, 2, 4
 FP64, MIXED = 0, 1
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4     # rad_status
 COLUMNS = ("t", "x", "y", "dz", "vx", "vy", "dvz", "ax", "ay", "az")
 
 _lock = threading.Lock()

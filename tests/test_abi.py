@@ -60,7 +60,14 @@ def test_validation_before_device(lib):
     assert lib.rad_workspace_bytes(None, 100, 1, 0) == 0
     assert lib.rad_batch_workspace_bytes(None, None, 0, 1, 1, 0) == 0
     assert lib.rad_tune_set_variant(0, 0, 0, 99) == 1
-    assert lib.rad_tune_num_variants() >= 1
+    assert lib.rad_tune_num_variants() == 5
+    # the 4x6 tile serves only integral sets without J
+    assert lib.rad_tune_set_variant(0, 0, 1, 4) == 4
+    assert b"without J" in lib.rad_last_error()
+    keep = ctypes.c_int()
+    assert lib.rad_tune_get_variant(1, 1, 0, ctypes.byref(keep)) == 0
+    assert lib.rad_tune_set_variant(1, 1, 0, 4) == 0
+    assert lib.rad_tune_set_variant(1, 1, 0, keep.value) == 0
     d = ctypes.c_double(5.0)
     assert lib.rad_grid_step(None, ctypes.byref(d)) == 1 and d.value == 5.0
     assert b"NULL" in lib.rad_last_error()

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1910_10391_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# (kernel symbol, VALU instructions in the hot loop per 16 evaluations)
+# (kernel symbol, VALU instructions in the hot loop per time step: 16 evaluations for a 4x4
+# tile)
 HOT = {
     "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,   # FP64, J, recurrence
     "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,   # FP64, J, direct
@@ -22,6 +23,10 @@ HOT = {
     "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,
     "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,
     "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 204,
+    # 4x6 tile without J: per 24 evaluations
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 327,   # FP64, recurrence
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 389,   # FP64, direct
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 252,   # mixed
 }
 
 
