@@ -148,11 +148,15 @@ int64_t chunk_factor(const Tile &t, int64_t n_segs)
     return (kTargetBlocks + have - 1) / have;
 }
 
+// Longest chunk: chunk lengths are 32-bit in the descriptors, while a segment may have
+// up to 2^40 samples (a multiple of kMinChunk).
+constexpr int64_t kMaxChunk = (int64_t)1 << 30;
+
 void plan_chunks(int64_t n, int64_t c, int32_t &n_chunks, int32_t &chunk_len)
 {
     int64_t len = (n + c - 1) / c;
     len = (len + kMinChunk - 1) / kMinChunk * kMinChunk;
-    len = std::min(len, n);
+    len = std::min(std::min(len, n), kMaxChunk);
     chunk_len = (int32_t)len;
     n_chunks = (int32_t)((n + len - 1) / len);
 }
