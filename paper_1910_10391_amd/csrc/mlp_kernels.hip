@@ -97,22 +97,33 @@ __global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t *__r
 }
 
 // ---------------------------------------------------------------- reductions
-// Stage 1: part[s][n] = sum over rows m in slice s of w[m] X[m][n] (w null -> 1),
-// X FP32 (xf) or BF16 (xb); rows in order.  Stage 2: out[n] = sum_s part[s][n].
-__global__ __launch_bounds__(256) void colsum_stage1(const float *__restrict__ xf, const uint16_t *__restrict__ xb,
-                                                     const float *__restrict__ w, int M, int N, int rows_per,
-                                                     float *__restrict__ part)
+// Column sums, out[n] = sum over rows m of w[m] X[m][n] (w null -> 1), X FP32 (xf) or BF16
+// (xb), in two passes of one kernel: pass 1 over `slices` row slices writes part[s][n],
+// pass 2 sums the slices.  A block of 256 threads takes nb columns x (256 / nb) row lanes:
+// lane j of a column sums rows m0 + j, m0 + j + lanes, ... of its slice in order, then
+// the lanes are added in a fixed LDS tree, so the result is deterministic.
+__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ xf, const uint16_t *__restrict__ xb,
+                                                     const float *__restrict__ w, int M, int N, int nb,
+                                                     int rows_per, float *__restrict__ out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[256];
+    const int lanes = 256 / nb;
+    const int c = threadIdx.x % nb, j = threadIdx.x / nb;
+    const int n = blockIdx.x * nb + c;   // < N: the grid has N / nb blocks along x
     const int s = blockIdx.y;
-    if (n >= N) return;
     const int m0 = s * rows_per, m1 = min(M, m0 + rows_per);
     float acc = 0.0f;
-    for (int m = m0; m < m1; ++m) {
+    for (int m = m0 + j; m < m1; m += lanes) {
         const float v = xf ? xf[(size_t)m * N + n] : bf2f(xb[(size_t)m * N + n]);
         acc += w ? w[m] * v : v;
     }
-    part[(size_t)s * N + n] = acc;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = lanes / 2; h >= 1; h >>= 1) {
+        if (j < h) red[threadIdx.x] += red[threadIdx.x + h * nb];
+        __syncthreads();
+    }
+    if (j == 0) out[(size_t)s * N + n] = red[c];
 }
 
 __global__ __launch_bounds__(256) void sum_slices(const float *__restrict__ part, int slices, int64_t len,
@@ -453,13 +464,18 @@ hipError_t launch_transpose(const uint16_t *in, int M, int N, uint16_t *out, hip
 hipError_t launch_colsum(const float *xf, const uint16_t *xb, const float *w, int M, int N, float *part,
                          int slices, float *out, hipStream_t st)
 {
+    // columns per block: N itself up to 64 (a power of two), else 64 (then pass 2 takes 16)
+    auto cols = [](int n, int most) { return n <= most ? n : most; };
+    const int nb1 = cols(N, 64), nb2 = cols(N, 16);
+    if (M < 1 || N < 1 || slices < 1 || 256 % nb1 != 0 || N % nb1 != 0 || 256 % nb2 != 0 || N % nb2 != 0)
+        return hipErrorInvalidValue;
     const int rows_per = (M + slices - 1) / slices;
-    hipLaunchKernelGGL(colsum_stage1, dim3((unsigned)((N + 255) / 256), (unsigned)slices), dim3(256), 0, st,
-                       xf, xb, w, M, N, rows_per, part);
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)(N / nb1), (unsigned)slices), dim3(256), 0, st, xf, xb, w, M,
+                       N, nb1, rows_per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_slices, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, slices,
-                       (int64_t)N, out, (int64_t)N, N, N);
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)(N / nb2), 1u), dim3(256), 0, st, part, nullptr, nullptr,
+                       slices, N, nb2, slices, out);
     return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ struct MWs {
 };
 
 constexpr int kSplits = 32;     // split-K slices of the weight-gradient products
-constexpr int kColSlices = 64;  // slices of the column sums
+constexpr int kColSlices = 256; // row slices of the column sums (pass 1 runs N/64 x 256 blocks)
 
 // Inference needs the folded biases, and unless the fused kernel runs (n_point <= 8)
 // also h1..h3 and y (about 1.5 KB per point).
