@@ -184,6 +184,19 @@ rad_status rad_plan_launch_graph(rad_plan *plan, double *out, void *stream);
 void rad_plan_free(rad_plan *plan);
 
 /*
+ * The phase factor e^{i phi} as the integral kernels compute it, on given arguments,
+ * for measuring its accuracy.  RAD_FP64: turns[k] = phi/pi (half turns); cos(pi u) and
+ * sin(pi u) from the exact reduction f = u - rint(u) and Chebyshev fits in f on
+ * [-1/2, 1/2].  RAD_MIXED: turns[k] = phi/(2 pi) (revolutions); the FP64 reduction
+ * r - rint(r), rounded to FP32, then the hardware FP32 sine and cosine of revolutions.
+ * turns, c, s: DEVICE double [n]; c[k] = cos, s[k] = sin.  |turns[k]| must stay below
+ * 2^31.  Errors: RAD_EINVAL for an unknown precision, n outside [0, 2^40] or a buffer
+ * that is not n doubles of device memory; nothing is launched for n = 0.
+ */
+rad_status rad_phase_factors(const double *turns, int64_t n, rad_precision prec, double *c, double *s,
+                             void *stream);
+
+/*
  * Angle integral (Sec. IV): dIdw[c][i] = sum_{jy,jx} cube[c][i][jy][jx] dthx[jx] dthy[jy]
  * for n_cubes consecutive DEVICE cubes; dIdw is DEVICE [n_cubes][n_w].
  */

@@ -678,6 +678,27 @@ __global__ __launch_bounds__(256) void angle_kernel(const double *__restrict__ c
     if (threadIdx.x == 0) out[(int64_t)c * n_w + i] = red[0];
 }
 
+// The phase-factor routines of the two forms on given arguments: half turns u
+// (cos(pi u), sin(pi u), FP64 polynomial) or revolutions r (cos(2 pi r), sin(2 pi r),
+// hardware FP32 sin/cos after the exact FP64 reduction), for measuring their accuracy.
+__global__ __launch_bounds__(256) void phase_kernel(const double *__restrict__ turns, int64_t n, int mixed,
+                                                    double *__restrict__ c, double *__restrict__ s)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double cc, ss;
+        if (mixed) {
+            float cf, sf;
+            cis_revolutions_f32(turns[i], cf, sf);
+            cc = cf;
+            ss = sf;
+        } else {
+            cis_halfturns(turns[i], cc, ss);
+        }
+        c[i] = cc;
+        s[i] = ss;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 // grid_blocks > 0: persistent launch with that many blocks; 0: one block per item.
 // occupancy != nullptr: only report resident blocks per CU of the persistent kernel.
@@ -755,6 +776,13 @@ hipError_t launch_fin(const FinLaunch &F, hipStream_t st)
         hipLaunchKernelGGL(fin_kernel<true>, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
     else
         hipLaunchKernelGGL(fin_kernel<false>, dim3(gx, (unsigned)F.n_out), dim3(256), 0, st, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const double *turns, int64_t n, int mixed, double *c, double *s, hipStream_t st)
+{
+    const int64_t want = (n + 255) / 256, blocks = want < 8192 ? want : 8192;
+    hipLaunchKernelGGL(phase_kernel, dim3((unsigned)blocks), dim3(256), 0, st, turns, n, mixed, c, s);
     return hipGetLastError();
 }
 

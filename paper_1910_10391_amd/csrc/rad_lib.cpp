@@ -29,6 +29,7 @@ hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, i
 hipError_t launch_reset(unsigned *counters, int n, hipStream_t st);
 hipError_t launch_cells_fin(const CellsFin &F, hipStream_t st);
 hipError_t launch_fin(const FinLaunch &F, hipStream_t st);
+hipError_t launch_phase(const double *turns, int64_t n, int mixed, double *c, double *s, hipStream_t st);
 hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
                         int n_w, int n_cubes, double *out, hipStream_t st);
 }  // namespace rad
@@ -732,6 +733,22 @@ rad_status rad_batch(const rad_grid *g, const rad_segment *segs, int n_segs, con
 {
     return run(const_cast<rad_grid *>(g), segs, n_segs, out_index, n_out, kinds, prec, out, ws,
                ws_bytes, (hipStream_t)stream);
+}
+
+rad_status rad_phase_factors(const double *turns, int64_t n, rad_precision prec, double *c, double *s,
+                             void *stream)
+{
+    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(RAD_EINVAL, "n = %lld outside [0, 2^40]", (long long)n);
+    if (n == 0) return RAD_OK;
+    const size_t bytes = (size_t)n * sizeof(double);
+    rad_status rs = check_dev_range(turns, bytes, "turns");
+    if (rs == RAD_OK) rs = check_dev_range(c, bytes, "c");
+    if (rs == RAD_OK) rs = check_dev_range(s, bytes, "s");
+    if (rs != RAD_OK) return rs;
+    hipError_t e = launch_phase(turns, n, prec == RAD_MIXED ? 1 : 0, c, s, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phase kernel launch");
+    return RAD_OK;
 }
 
 rad_status rad_angle_integrate(const rad_grid *g, const double *cube, int n_cubes, double *dIdw,

@@ -58,6 +58,7 @@ def lib():
                 "rad_quantum": (I, [P, SP, I, I, P, P, S, P]),
                 "rad_batch": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, P, S, P]),
                 "rad_angle_integrate": (I, [P, P, I, P, P]),
+                "rad_phase_factors": (I, [P, I64, I, P, P, P]),
                 "rad_status_string": (ctypes.c_char_p, [I]),
                 "rad_last_error": (ctypes.c_char_p, []),
                 "rad_tune_set_variant": (I, [I, I, I, I]),
@@ -260,6 +261,20 @@ def batch(grid, segs, out_index, n_out, kinds, precision=FP64, out=None, workspa
                            int(precision), _dptr(out), _dptr(ws), _nbytes(ws), _stream(stream)),
            "rad_batch")
     return out
+
+
+def phase_factors(turns, precision=FP64, stream=None):
+    """(cos, sin) of a contiguous float64 CUDA tensor of half turns (FP64: cos(pi u)) or
+    revolutions (MIXED: cos(2 pi r)), by the integral kernels' own routine
+    (rad_phase_factors)."""
+    import torch
+    if turns.dtype != torch.float64 or not turns.is_cuda or not turns.is_contiguous():
+        raise ValueError("turns must be a contiguous float64 CUDA tensor")
+    c = torch.empty_like(turns)
+    s = torch.empty_like(turns)
+    _check(lib().rad_phase_factors(_dptr(turns), int(turns.numel()), int(precision), _dptr(c), _dptr(s),
+                                   _stream(stream)), "rad_phase_factors")
+    return c, s
 
 
 def angle_integrate(grid, cubes, out=None, stream=None):

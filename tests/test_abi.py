@@ -68,6 +68,14 @@ def test_validation_before_device(lib):
     assert lib.rad_tune_get_variant(1, 1, 0, ctypes.byref(keep)) == 0
     assert lib.rad_tune_set_variant(1, 1, 0, 4) == 0
     assert lib.rad_tune_set_variant(1, 1, 0, keep.value) == 0
+    # rad_phase_factors: precision, size and NULL checks come before any device call;
+    # nothing is launched for n = 0
+    lib.rad_phase_factors.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.rad_phase_factors(None, 4, 7, None, None, None) == 1
+    assert lib.rad_phase_factors(None, -1, 0, None, None, None) == 1
+    assert lib.rad_phase_factors(None, 0, 1, None, None, None) == 0
+    assert lib.rad_phase_factors(None, 4, 0, None, None, None) == 1 and b"turns is NULL" in lib.rad_last_error()
     d = ctypes.c_double(5.0)
     assert lib.rad_grid_step(None, ctypes.byref(d)) == 1 and d.value == 5.0
     assert b"NULL" in lib.rad_last_error()

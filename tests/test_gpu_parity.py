@@ -215,6 +215,50 @@ def test_variants_agree(rad):
             rad.tune_set_variant(*k, keep[k])
 
 
+def _cis_reference(turns, scale):
+    """cos and sin of scale * pi * turns with the exact reduction f = turns - rint(turns),
+    evaluated by mpmath at 40 digits."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    c = np.empty(turns.size)
+    s = np.empty(turns.size)
+    for i, u in enumerate(turns):
+        f = mp.mpf(float(u)) - mp.mpf(float(np.rint(u)))
+        a = scale * mp.pi * f
+        sign = -1.0 if (scale == 1 and int(np.rint(u)) % 2) else 1.0
+        c[i] = sign * float(mp.cos(a))
+        s[i] = sign * float(mp.sin(a))
+    return c, s
+
+
+def test_phase_factor_routines(rad):
+    """The phase factor as the kernels compute it (rad_phase_factors), against mpmath:
+    the FP64 routine on half turns (exact reduction, Chebyshev fits, sign by parity) for
+    |u| up to 1e6 and at every multiple of 1/4, within 3 ulp of 1 (fit error about 1 ulp,
+    Horner evaluation 1.5, the final product 0.5); the mixed form's hardware FP32 sine and
+    cosine of revolutions, whose error (FP32 rounding of the reduced argument, 2 pi 2^-26
+    = 9.4e-8, plus the instruction's own) must stay far inside the mixed tolerance."""
+    import torch
+    rng = np.random.default_rng(3)
+    u = np.concatenate([rng.uniform(-0.5, 0.5, 6000), rng.uniform(-1e4, 1e4, 6000), rng.uniform(-1e6, 1e6, 3000),
+                        np.arange(-8.0, 8.25, 0.25), [1e-300, -1e-300, 3.0e-9, 2.0 ** 30 + 0.375]])
+    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+    c, s = (t.cpu().numpy() for t in rad.phase_factors(ud, rad.FP64))
+    rc, rs = _cis_reference(u, 1)
+    err64 = max(np.abs(c - rc).max(), np.abs(s - rs).max())
+    r = u / 2.0
+    rd = torch.tensor(r, dtype=torch.float64, device="cuda")
+    cm, sm = (t.cpu().numpy() for t in rad.phase_factors(rd, rad.MIXED))
+    mc, ms = _cis_reference(r, 2)
+    err32 = max(np.abs(cm - mc).max(), np.abs(sm - ms).max())
+    print("phase factor max abs error: FP64 %.2e, mixed (hardware FP32) %.2e" % (err64, err32))
+    assert err64 <= 3 * 2.0 ** -52, err64
+    assert err32 <= 1e-6, err32
+    assert np.all(np.abs(c[np.rint(u) == u]) == 1.0) and np.all(s[np.rint(u) == u] == 0.0)
+    with pytest.raises(rad.RadError):
+        rad.phase_factors(ud, 7)
+
+
 def test_bitwise_reproducible(rad):
     cfg, tr = _small_channeling(2, seed=23)
     segs = [tr[0][0], tr[1][0]]
