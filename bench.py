@@ -55,18 +55,19 @@ def flops_per_eval(variant, with_j=True, recurrence=False):
     return phase + (12.0 if with_j else 8.0)
 
 
-# VALU instructions per eval in the compiled hot loop of the 4x4 one-block-per-item
-# FP64 kernel, counted in the gfx950 assembly of this build: direct phase factors
+# VALU instructions per eval in the compiled hot loop of the 4x4 FP64 kernels (the
+# persistent and the one-block-per-item kernel compile to the same loop), counted in the gfx950 assembly of this build: direct phase factors
 # 311 per 16 evals with J (279 without), recurrence on a uniform grid 279 (246).
 VALU_PER_EVAL_44 = {(True, False): 311.0 / 16.0, (False, False): 279.0 / 16.0,
                     (True, True): 279.0 / 16.0, (False, True): 246.0 / 16.0}
-# HBM bytes per amp_kernel launch on this workload from two rocprofv3 PMC passes
+# HBM bytes per amp_persistent launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below; a source change
-# that leaves amp_kernel's gfx950 assembly identical is carried over after checking that).
+# that leaves amp_persistent's gfx950 assembly identical is carried over after checking that).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "c25404e64c1726d0", "particles": 256, "bytes_per_launch": 4.7712e10}
+MEASURED_TRAFFIC = {"sources_sha256": "c25404e64c1726d0", "particles": 256, "kernel": "amp_persistent",
+                    "bytes_per_launch": 4.0295e10}
 
 
 def kernel_sources_sha():
@@ -534,7 +535,7 @@ def main():
           "inputs generated in %.1f s" % (len(segs), n_samples, grid.shape, evals, ws.numel() / 1e9,
                                           t_gen), file=sys.stderr, flush=True)
 
-    tuned = autotune.tune(grid, ds, kinds, rad.FP64, persistent=False, sample=8)
+    tuned = autotune.tune(grid, ds, kinds, rad.FP64, persistent=True, sample=8)
     print("bench: autotuned variants %s" % {k: v["variant"] for k, v in tuned.items()},
           file=sys.stderr, flush=True)
 
@@ -546,7 +547,12 @@ def main():
         del a, b
 
     def step(prec, o):
-        rad.batch(grid, ds, idx, len(segs), kinds, precision=prec, out=o, workspace=ws)
+        # one pass of the batched form over the batch: plan it (longest-first work list,
+        # descriptors uploaded into the workspace), then the persistent amplitude kernel and
+        # the finalize; planning is inside the step, as it is inside every rad_batch call
+        plan = rad.Plan(grid, ds, idx, len(segs), kinds, precision=prec, workspace=ws)
+        plan.launch(o)
+        plan.close()
 
     # ---- FP64, the headline
     for _ in range(args.warmup):
@@ -610,17 +616,17 @@ def main():
             mixed["rel_err_M1"] = parity["mixed_M1_max"]
             mixed["rel_err_M2"] = parity["mixed_M2_max"]
 
-    variant = rad.tune_get_variant(False, False, True)
+    variant = rad.tune_get_variant(True, False, True)
     rec = grid.step != 0.0
     flops = flops_per_eval(variant, True, rec) * evals
     achieved = flops / kern_s / 1e12
     traffic = None
     if (kernel_sources_sha() == MEASURED_TRAFFIC["sources_sha256"] and variant == 0
-            and len(segs) == MEASURED_TRAFFIC["particles"]):
+            and len(segs) == MEASURED_TRAFFIC["particles"] and MEASURED_TRAFFIC["kernel"] == "amp_persistent"):
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": "amp_kernel<%d,%d,J,fp64,%d%s>" % (VARIANTS[variant] + (",rec" if rec else "",)),
+                "kernel": "amp_persistent<%d,%d,J,fp64,%d%s>" % (VARIANTS[variant] + (",rec" if rec else "",)),
                 "kernel_ms": kern_s * 1e3, "flops_per_eval": flops_per_eval(variant, True, rec),
                 "valu_issue_frac": (VALU_PER_EVAL_44[(True, rec)] * evals / kern_s / 1e12 / VALU_PEAK_TOPS
                                     if variant == 0 else None)}
@@ -633,7 +639,7 @@ def main():
                                "spin-1/2, 512 log hw 0.5-200 MeV x 32x32 within 5/gamma"
                                % (len(segs), min(ds.n), max(ds.n)),
                    "trajectories": len(segs), "samples": n_samples, "grid": list(grid.shape),
-                   "kinds": "spin-1/2", "precision": "fp64",
+                   "kinds": "spin-1/2", "precision": "fp64", "form": "persistent plan (rad_plan_*)",
                    "autotune": {k: v["variant"] for k, v in tuned.items()}},
         "trajectories_per_s": len(segs) / dt,
         "mixed": mixed,
