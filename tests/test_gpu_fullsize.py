@@ -1,6 +1,7 @@
 """Parity at full size: the benchmark's workload, launched exactly as bench.py launches it
-(256 trajectories in one rad_batch call, 512 x 32 x 32 grid, spin-1/2, FP64 and mixed),
-checked on sampled outputs that the oracle computes point by point."""
+(256 trajectories planned into one persistent launch, rad_plan_create + rad_plan_launch,
+512 x 32 x 32 grid, spin-1/2, FP64 and mixed; rad_batch on the same batch gives the same
+bits), checked on sampled outputs that the oracle computes point by point."""
 import numpy as np
 import pytest
 
@@ -20,8 +21,16 @@ def test_positron_spinhalf_full_size_sampled():
     grid = rad.Grid(g.hw_eV, g.thx, g.thy)
     idx = list(range(len(segs)))
     print("full-size: %d trajectories, %d..%d samples" % (len(segs), min(ds.n), max(ds.n)), flush=True)
-    out = rad.batch(grid, ds, idx, len(segs), rad.SPINHALF)[:, 0].cpu().numpy()
-    outm = rad.batch(grid, ds, idx, len(segs), rad.SPINHALF, precision=rad.MIXED)[:, 0].cpu().numpy()
+    def planned(prec):
+        plan = rad.Plan(grid, ds, idx, len(segs), rad.SPINHALF, precision=prec)
+        o = plan.launch()
+        plan.close()
+        return o
+    out_t = planned(rad.FP64)
+    assert torch.equal(out_t, rad.batch(grid, ds, idx, len(segs), rad.SPINHALF))
+    out = out_t[:, 0].cpu().numpy()
+    del out_t
+    outm = planned(rad.MIXED)[:, 0].cpu().numpy()
     assert np.all(np.isfinite(out)) and np.all(out >= 0)
     traj, iw, ix, iy = bench.sample_points(segs, g)
     # a fixed random sample of single points from every trajectory on top of the blocks
