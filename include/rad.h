@@ -190,7 +190,7 @@ void rad_plan_free(rad_plan *plan);
  * [-1/2, 1/2].  RAD_MIXED: turns[k] = phi/(2 pi) (revolutions); the FP64 reduction
  * r - rint(r), rounded to FP32, then the hardware FP32 sine and cosine of revolutions.
  * turns, c, s: DEVICE double [n]; c[k] = cos, s[k] = sin.  |turns[k]| must stay below
- * 2^31.  Errors: RAD_EINVAL for an unknown precision, n outside [0, 2^40] or a buffer
+ * 2^51.  Errors: RAD_EINVAL for an unknown precision, n outside [0, 2^40] or a buffer
  * that is not n doubles of device memory; nothing is launched for n = 0.
  */
 rad_status rad_phase_factors(const double *turns, int64_t n, rad_precision prec, double *c, double *s,

@@ -234,14 +234,19 @@ def _cis_reference(turns, scale):
 def test_phase_factor_routines(rad):
     """The phase factor as the kernels compute it (rad_phase_factors), against mpmath:
     the FP64 routine on half turns (exact reduction, Chebyshev fits, sign by parity) for
-    |u| up to 1e6 and at every multiple of 1/4, within 3 ulp of 1 (fit error about 1 ulp,
+    |u| up to 1e6, at every multiple of 1/4 and past 2^31 up to 2^50 (the sign must stay
+    right where a 32-bit parity would overflow), within 3 ulp of 1 (fit error about 1 ulp,
     Horner evaluation 1.5, the final product 0.5); the mixed form's hardware FP32 sine and
     cosine of revolutions, whose error (FP32 rounding of the reduced argument, 2 pi 2^-26
     = 9.4e-8, plus the instruction's own) must stay far inside the mixed tolerance."""
     import torch
     rng = np.random.default_rng(3)
+    # past 2^31 half turns (photon energies near the particle energy, Sec. II eq.
+    # (Lindhard_substi)): integers of both parities, quarter offsets, random values to 2^50
+    big = np.concatenate([2.0 ** np.arange(31, 51), 2.0 ** np.arange(31, 51) + 1.0])
+    big = np.concatenate([big, big + 0.25, big - 0.5, np.ldexp(rng.uniform(1.0, 2.0, 500), rng.integers(31, 50, 500))])
     u = np.concatenate([rng.uniform(-0.5, 0.5, 6000), rng.uniform(-1e4, 1e4, 6000), rng.uniform(-1e6, 1e6, 3000),
-                        np.arange(-8.0, 8.25, 0.25), [1e-300, -1e-300, 3.0e-9, 2.0 ** 30 + 0.375]])
+                        np.arange(-8.0, 8.25, 0.25), [1e-300, -1e-300, 3.0e-9, 2.0 ** 30 + 0.375], big, -big])
     ud = torch.tensor(u, dtype=torch.float64, device="cuda")
     c, s = (t.cpu().numpy() for t in rad.phase_factors(ud, rad.FP64))
     rc, rs = _cis_reference(u, 1)

@@ -2,7 +2,11 @@
 
 cis_halfturns(u) must equal exp(i pi u) to a few units in the last place for
 the half-turn counts the kernels see (|u| up to ~1e6), checked against mpmath
-at 50 digits on the exact binary value of u.
+at 50 digits on the exact binary value of u -- and stay exact far past that:
+the sign (-1)^q of the nearest integer q is taken in FP64, so half-turn counts
+up to 2^51 (a photon energy close to the particle energy makes k* = kE/(E - hw)
+and so the phase arbitrarily large, Sec. II eq. (Lindhard_substi)) must not
+pick up a wrong sign.
 """
 import ctypes
 import os
@@ -67,3 +71,26 @@ def test_cis_unit_modulus_and_symmetry(shim):
     assert np.max(np.abs(c * c + s * s - 1.0)) < 1e-15
     c2, s2 = _run(shim, -u)
     assert np.array_equal(c2, c) and np.array_equal(s2, -s)
+
+
+def test_cis_past_32_bit_parity(shim):
+    """|u| in [2^31, 2^50]: odd and even integers, their quarter offsets and random
+    values; a parity taken through a 32-bit conversion would flip the sign of about half
+    of them.  At these sizes u - rint(u) is a multiple of the spacing of doubles near u,
+    so the reference is evaluated on the exact binary value of u as before."""
+    mp.mp.dps = 60
+    rng = np.random.default_rng(4)
+    ints = np.concatenate([2.0 ** np.arange(31, 51), 2.0 ** np.arange(31, 51) + 1.0,
+                           2.0 ** np.arange(31, 50) + 3.0, 2.0 ** 31 * np.arange(1, 9) + 1.0])
+    offs = np.concatenate([ints + 0.25, ints - 0.25, ints + 0.5])
+    rnd = np.ldexp(rng.uniform(1.0, 2.0, 600), rng.integers(31, 50, 600))
+    u = np.concatenate([ints, offs, rnd])
+    u = np.concatenate([u, -u])
+    c, s = _run(shim, u)
+    err = 0.0
+    for ui, ci, si in zip(u, c, s):
+        x = mp.pi * mp.mpf(float(ui))
+        err = max(err, abs(float(mp.cos(x)) - ci), abs(float(mp.sin(x)) - si))
+    assert err < 4e-16, err
+    odd = np.abs(np.fmod(u[:ints.size], 2.0)) == 1.0
+    assert np.all(c[:ints.size][odd] == -1.0) and np.all(c[:ints.size][~odd] == 1.0)
