@@ -56,10 +56,11 @@ def flops_per_eval(variant, with_j=True, recurrence=False):
 
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 FP64 kernels (the
-# persistent and the one-block-per-item kernel compile to the same loop), counted in the gfx950 assembly of this build: direct phase factors
-# 311 per 16 evals with J (279 without), recurrence on a uniform grid 279 (246).
-VALU_PER_EVAL_44 = {(True, False): 311.0 / 16.0, (False, False): 279.0 / 16.0,
-                    (True, True): 279.0 / 16.0, (False, True): 246.0 / 16.0}
+# persistent and the one-block-per-item kernel compile to the same loop), counted in the
+# gfx950 assembly of this build (tests/test_codegen.py): direct phase factors 310 per 16
+# evals with J (278 without), recurrence on a uniform grid 278 (245).
+VALU_PER_EVAL_44 = {(True, False): 310.0 / 16.0, (False, False): 278.0 / 16.0,
+                    (True, True): 278.0 / 16.0, (False, True): 245.0 / 16.0}
 # HBM bytes per amp_persistent launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below; a source change
@@ -91,6 +92,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one device copy of known size first (counter scale factor)")
+    p.add_argument("--no-legs", action="store_true",
+                   help="skip the secondary legs of the default line (mixed-precision and sections "
+                        "workloads, learned sampler, issue-rate ceilings)")
     return p.parse_args()
 
 
@@ -500,6 +504,210 @@ def cpu_model():
     return platform.processor()
 
 
+# ---------------------------------------------------------------- legs of the default line
+# Each leg is one further configuration of the same path, measured once or twice (not
+# `--steps` times) so that the default run stays within a few minutes.
+
+PAPER_CONTEXT = {
+    "source": "Sec. V, Fig. 7 (speed-ups of classical FP64 radiation integrals of 3000 time "
+              "points each, GPU saturated; other hardware, quoted as context, not as a target)",
+    "titan_v_vs_i7_7820x": 205.1,
+    "titan_v_vs_one_xeon_gold_6140_node": "about 100 (the Xeon node, 36 hardware threads, runs about 2x "
+                                          "the i7-7820X)",
+}
+
+# gfx950 hot loop of the mixed-precision 4x4 kernel with J, per 16 evaluations (time
+# step x direction tile), counted in the assembly by tests/test_codegen.py: 203 VALU
+# instructions, 14 of them transcendental (7 v_sin_f32 + 7 v_cos_f32).
+MIXED_VALU_PER_16 = 203
+MIXED_TRANS_PER_16 = 14
+VALU_LANE_PEAK_T = 256 * 64 * 2.4e9 / 1e12   # lane-instructions per second at 2.4 GHz, 1e12
+
+
+def leg_peaks():
+    """Issue-rate ceilings measured on this GPU (rad_peak)."""
+    from paper_1910_10391_amd import rad
+    res = {}
+    for name, which, iters in (("fp64_fma", rad.PEAK_FMA64, 4096), ("fp32_fma", rad.PEAK_FMA32, 4096),
+                               ("sincos_f32", rad.PEAK_SINCOS32, 1024), ("phase_fp64", rad.PEAK_PHASE64, 256),
+                               ("phase_mixed", rad.PEAK_PHASE_MIXED, 256)):
+        rate, ops, ms = rad.peak(which, iters)
+        res[name] = {"per_s": rate, "ms": ms}
+    res["fp64_fma"]["tflops"] = res["fp64_fma"]["per_s"] / 1e12
+    res["fp64_fma"]["frac_of_78.6"] = res["fp64_fma"]["tflops"] / FP64_PEAK_TFLOPS
+    res["fp32_fma"]["tflops"] = res["fp32_fma"]["per_s"] / 1e12
+    # lane-instructions per second: an FMA is one instruction (2 flops), a sine one
+    fma_lane = res["fp64_fma"]["per_s"] / 2.0
+    res["sincos_f32"]["cost_in_fma64_slots"] = fma_lane / res["sincos_f32"]["per_s"]
+    res["clock_ghz_implied_by_fp64_fma"] = fma_lane / (256 * 64) / 1e9
+    return res
+
+
+def mixed_roofline(evals_per_s, peaks):
+    """The mixed form's issue roofline: VALU lane-instructions per evaluation of its hot
+    loop, the transcendental ones weighted by their measured cost in FMA issue slots,
+    against the chip's lane-instruction rate at the nominal clock."""
+    w = peaks["sincos_f32"]["cost_in_fma64_slots"] if peaks else 4.0
+    per_eval = ((MIXED_VALU_PER_16 - MIXED_TRANS_PER_16) + w * MIXED_TRANS_PER_16) / 16.0
+    achieved = evals_per_s * per_eval / 1e12
+    measured_ceiling = peaks["fp64_fma"]["per_s"] / 2.0 / 1e12 if peaks else None
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_LANE_PEAK_T,
+            "unit": "T VALU lane-instructions/s (transcendentals weighted by measured cost)",
+            "frac": achieved / VALU_LANE_PEAK_T, "traffic": None,
+            "kernel": "amp_persistent<4,4,J,mixed,2>", "valu_per_eval": per_eval, "sincos_weight": w,
+            "frac_of_measured_fma_issue": achieved / measured_ceiling if measured_ceiling else None}
+
+
+def leg_pm_mixed():
+    """The mixed-precision workload: 1024 e+ + 1024 e- at 10 GeV, classical + spin-0 +
+    spin-1/2 on 256 log hw x 16 x 16; mixed against FP64 on the GPU, and the error of each
+    spectrum against the FP64 oracle on a sample (2 e+ and 2 e-, every 4th energy, 8 x 8
+    strided directions)."""
+    import torch
+    import oracle
+    from paper_1910_10391_amd import rad
+    t0 = time.perf_counter()
+    segs, g = build_pm_workload(1024)
+    ds = rad.DeviceSegments(segs)
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    n = len(segs)
+    evals = 2 * int(sum(ds.n)) * int(np.prod(grid.shape))
+    idx = list(range(n))
+    ws = torch.empty(rad.batch_workspace_bytes(grid, ds, n, 7, rad.FP64), dtype=torch.uint8, device="cuda")
+    out = torch.empty((n, 3) + grid.shape, dtype=torch.float64, device="cuda")
+    t_prep = time.perf_counter() - t0
+    stepm = lambda: rad.batch(grid, ds, idx, n, 7, rad.MIXED, out=out, workspace=ws)  # noqa: E731
+    stepm()
+    dt_mx = timed(stepm, 1, torch.cuda.synchronize)
+    sample = [0, 1, 1024, 1025]
+    iw, ixy = np.arange(0, len(g.hw_eV), 4), np.arange(0, len(g.thx), 2)
+    sel = np.ix_(iw, ixy, ixy)
+    got_mx = {p: out[p].cpu().numpy()[(slice(None),) + sel] for p in sample}
+    step64 = lambda: rad.batch(grid, ds, idx, n, 7, rad.FP64, out=out, workspace=ws)  # noqa: E731
+    dt_64 = timed(step64, 1, torch.cuda.synchronize)
+    got_64 = {p: out[p].cpu().numpy()[(slice(None),) + sel] for p in sample}
+    del ws, out
+    errs = {}
+    for i, (k, name) in enumerate(((1, "classical"), (2, "spin0"), (4, "spinhalf"))):
+        e_mx, e_64 = [], []
+        for p in sample:
+            ref = oracle.spectrum(segs[p], g.hw_eV[iw], g.thx[ixy], g.thy[ixy], k)[k]
+            e_mx.append(rel_metrics(got_mx[p][i], ref))
+            e_64.append(rel_metrics(got_64[p][i], ref))
+        errs[name] = {"mixed_M1": max(e[0] for e in e_mx), "mixed_M2": max(e[1] for e in e_mx),
+                      "fp64_M1": max(e[0] for e in e_64), "fp64_M2": max(e[1] for e in e_64)}
+    print("bench leg pm_mixed: mixed %.3f s, fp64 %.3f s (x%.2f)" % (dt_mx, dt_64, dt_64 / dt_mx),
+          file=sys.stderr, flush=True)
+    return {"workload": "pm_mixed: 1024 e+ + 1024 e- at 10 GeV, 100 um, %d..%d samples; classical + spin-0 + "
+                        "spin-1/2 (two integral sets), 256 log hw 0.5-200 MeV x 16x16 within 5/gamma"
+                        % (min(ds.n), max(ds.n)),
+            "evals": evals, "mixed": {"value": evals / dt_mx, "unit": "evals/s", "ms_per_step": dt_mx * 1e3,
+                                      "trajectories_per_s": n / dt_mx},
+            "fp64": {"value": evals / dt_64, "unit": "evals/s", "ms_per_step": dt_64 * 1e3},
+            "speedup_mixed_vs_fp64": dt_64 / dt_mx,
+            "rel_err_vs_oracle": errs,
+            "oracle_sample": "trajectories %s (2 e+, 2 e-), every 4th of 256 energies, 8x8 strided directions"
+                             % sample, "prep_s": t_prep}
+
+
+def leg_sections():
+    """The 50 GeV sections workload: the persistent, autotuned mixed-precision plan replayed
+    from a hipGraph against the plain FP64 rad_batch on the same GPU; errors against FP64
+    on the GPU (whole cubes) and against the oracle (one trajectory, every 8th energy, 4 x 4
+    strided directions)."""
+    import torch
+    import oracle
+    from paper_1910_10391_amd import autotune, rad
+    n = 512
+    segs, idx, g = build_sections_workload(n)
+    ds = rad.DeviceSegments(segs)
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    evals = int(sum(ds.n)) * int(np.prod(grid.shape))
+    tune = autotune.tune(grid, ds, rad.SPINHALF, rad.MIXED, persistent=True, sample=16)
+    side = torch.cuda.Stream()
+    out = torch.empty((n, 1) + grid.shape, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(side):
+        plan = rad.Plan(grid, ds, idx, n, rad.SPINHALF, precision=rad.MIXED, stream=side)
+        plan.launch_graph(out, stream=side)
+        dt_mx = timed(lambda: plan.launch_graph(out, stream=side), 2, side.synchronize)
+    plan.close()
+    ws = torch.empty(rad.batch_workspace_bytes(grid, ds, n, rad.SPINHALF, rad.FP64), dtype=torch.uint8,
+                     device="cuda")
+    out64 = torch.empty_like(out)
+    step64 = lambda: rad.batch(grid, ds, idx, n, rad.SPINHALF, rad.FP64, out=out64, workspace=ws)  # noqa: E731
+    dt_64 = timed(step64, 1, torch.cuda.synchronize)
+    a, b = out[:, 0].cpu().numpy(), out64[:, 0].cpu().numpy()
+    del ws, out, out64
+    m1 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    iw, ixy = np.arange(0, len(g.hw_eV), 8), np.arange(0, len(g.thx), 4)
+    p = 0
+    mine = [s for s, o in zip(segs, idx) if o == p]
+    ref = oracle.batch(mine, [0] * len(mine), 1, g.hw_eV[iw], g.thx[ixy], g.thy[ixy], 4)[0, 0]
+    sel = np.ix_(iw, ixy, ixy)
+    e_mx, e_64 = rel_metrics(a[p][sel], ref), rel_metrics(b[p][sel], ref)
+    print("bench leg sections: mixed graph %.3f s, fp64 %.3f s (x%.2f)" % (dt_mx, dt_64, dt_64 / dt_mx),
+          file=sys.stderr, flush=True)
+    return {"workload": "electron_50gev_sections: 512 e- at 50 GeV, 1 mm in 10 sections (%d segments, %d..%d "
+                        "samples each); spin-1/2, 256 log hw 1 MeV-20 GeV x 16x16 within 4/gamma"
+                        % (len(segs), min(ds.n), max(ds.n)),
+            "evals": evals,
+            "mixed_graph": {"value": evals / dt_mx, "unit": "evals/s", "ms_per_step": dt_mx * 1e3,
+                            "trajectories_per_s": n / dt_mx, "form": "persistent plan, hipGraph replay",
+                            "autotune": {k: v["variant"] for k, v in tune.items()}},
+            "fp64_plain": {"value": evals / dt_64, "unit": "evals/s", "ms_per_step": dt_64 * 1e3,
+                           "form": "rad_batch"},
+            "speedup_mixed_graph_vs_fp64_plain": dt_64 / dt_mx,
+            "mixed_vs_fp64_gpu_M1": m1,
+            "rel_err_vs_oracle": {"mixed_M1": e_mx[0], "mixed_M2": e_mx[1], "fp64_M1": e_64[0], "fp64_M2": e_64[1],
+                                  "sample": "trajectory 0 (10 sections), every 8th energy, 4x4 strided directions"}}
+
+
+SAMPLER_CKPT = os.path.join(ROOT, "paper_1910_10391_amd", "weights", "positron_spinhalf_sampler.npz")
+
+
+def leg_sampler(n_test=32):
+    """The learned angular sampler (committed network) on held-out positrons: spin-1/2 on
+    512 log hw x 64 x 64 directions within 5/gamma, 8 x 8 cells; against the full grid in
+    mixed precision (the judge of its error) and in plain FP64."""
+    import torch
+    from paper_1910_10391_amd import rad, sampler
+    from paper_1910_10391_amd.synth import channeling, presets
+    from paper_1910_10391_amd.train_sampler import errors
+    cfg, pg = presets.positron_config(), presets.positron_grid()
+    gamma = cfg.energy_eV / channeling.ME_EV
+    smp = sampler.Sampler.load(SAMPLER_CKPT, pg.hw_eV, gamma)
+    trs = channeling.generate(cfg, n_test, first=70000, threads=min(16, os.cpu_count() or 1))
+    ds = rad.DeviceSegments([tr[0] for tr in trs])
+    smp.full_grid(ds, rad.MIXED)
+    full_mx, t_mx = min((smp.full_grid(ds, rad.MIXED) for _ in range(2)), key=lambda r: r[1])
+    full_64, t_64 = smp.full_grid(ds, rad.FP64)
+    smp.estimate(ds, precision=rad.MIXED)
+    est = min((smp.estimate(ds, precision=rad.MIXED) for _ in range(2)), key=lambda r: r["seconds"])
+    full = full_mx.cpu().numpy()
+    rel, _ = errors(est["dIdw"].cpu().numpy(), full)
+    rel64, _ = errors(full_64.cpu().numpy(), full)
+    print("bench leg sampler: %.3f s (full grid mixed %.3f s, fp64 %.3f s), max rel err %.4f"
+          % (est["seconds"], t_mx, t_64, rel.max()), file=sys.stderr, flush=True)
+    return {"workload": "sampler: %d held-out positrons at 10 GeV, 100 um; spin-1/2 on 512 log hw x 64x64 "
+                        "within 5/gamma, 8x8 cells, committed network (%s rule)" % (n_test, smp.select_rule),
+            "seconds": est["seconds"], "full_grid_mixed_s": t_mx, "full_grid_fp64_s": t_64,
+            "speedup_vs_full_grid_mixed": t_mx / est["seconds"],
+            "speedup_vs_full_grid_fp64": t_64 / est["seconds"],
+            "max_rel_err_dIdw": float(rel.max()), "accepted_1pct": bool(rel.max() <= 0.01),
+            "evals_frac": est["evals"] / est["evals_full"],
+            "full_evals_replaced_per_s": est["evals_full"] / est["seconds"],
+            "mixed_full_grid_vs_fp64_max_rel": float(rel64.max()), "phases_s": est["phases"]}
+
+
+def run_leg(name, fn):
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 -- a failed leg is reported in the line, not hidden
+        import traceback
+        traceback.print_exc()
+        return {"error": "%s: %s" % (type(e).__name__, e)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -630,6 +838,28 @@ def main():
                 "kernel_ms": kern_s * 1e3, "flops_per_eval": flops_per_eval(variant, True, rec),
                 "valu_issue_frac": (VALU_PER_EVAL_44[(True, rec)] * evals / kern_s / 1e12 / VALU_PEAK_TOPS
                                     if variant == 0 else None)}
+    # ---- the other configurations, the ceilings and the paper's figures as context; the
+    # headline's own buffers are released first
+    legs = None
+    context = dict(PAPER_CONTEXT)
+    if cpu is not None:
+        context["this_gpu_vs_host_oracle"] = {"all_cores": value / cpu["value"], "cores": cpu["cores"],
+                                              "one_core": value / cpu["single_core"]["value"]}
+    if not args.no_legs:
+        del ws, out
+        if out_mx is not None:
+            del out_mx
+        torch.cuda.empty_cache()
+        legs = {"peaks": run_leg("peaks", leg_peaks)}
+        peaks = legs["peaks"] if "error" not in legs["peaks"] else None
+        if mixed is not None:
+            mixed["roofline"] = mixed_roofline(mixed["value"], peaks)
+        legs["sampler"] = run_leg("sampler", leg_sampler)
+        torch.cuda.empty_cache()
+        legs["pm_mixed"] = run_leg("pm_mixed", leg_pm_mixed)
+        torch.cuda.empty_cache()
+        legs["electron_50gev_sections"] = run_leg("sections", leg_sections)
+        torch.cuda.empty_cache()
     res = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -646,8 +876,10 @@ def main():
         "parity": parity,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_context": context,
+        "legs": legs,
     }
-    print(json.dumps(res), flush=True)
+    print(json.dumps(_finite(res)), flush=True)
 
 
 if __name__ == "__main__":

@@ -32,7 +32,9 @@
  *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
  *     calls are asynchronous on it and make no host synchronisation.
  *   - Workspaces are caller-provided device memory; compute calls allocate no
- *     device memory.
+ *     device memory.  They stage their launch descriptors through the grid's
+ *     pinned host buffer (1 MiB from rad_setup_grid, about 1000 segments' worth);
+ *     only a call whose descriptors need more grows it to that size.
  *   - Errors: every call returns a status and never aborts or throws across the
  *     ABI.  Arguments are validated before any launch; on error nothing is
  *     launched and rad_last_error() holds a message (thread-local).
@@ -95,7 +97,8 @@ typedef struct {
  * 8 units in the last place of the largest angle), the FP64 kernels form the
  * phase factors of a direction tile by recurrence along each axis (the phase is
  * quadratic in the direction index; Sec. II), see rad_grid_step.  Allocates
- * device memory; may synchronise `stream`.
+ * device memory and 1 MiB of pinned host memory through which compute calls upload
+ * their launch descriptors; may synchronise `stream`.
  * Errors: RAD_EINVAL for null pointers, sizes < 1 or non-finite values;
  * RAD_ENOMEM / RAD_EDEVICE on allocation or copy failure.
  */
@@ -245,6 +248,15 @@ const char *rad_last_error(void);
 rad_status rad_tune_set_variant(int persistent, int mixed, int with_j, int variant);
 rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *variant);
 int rad_tune_num_variants(void);
+
+/*
+ * Index checks of the debug build (compiled with -DRAD_DEBUG=1, librad_debug.so): the
+ * kernels check descriptor, time-chunk and partial-amplitude indices against the
+ * launch's bounds, count each violation and skip that access.  Returns the count since
+ * the last reset on the current device (synchronising it; reset != 0 clears the count),
+ * -1 in a release build (no checks compiled), -2 if the device cannot be read.
+ */
+int64_t rad_debug_violations(int reset);
 
 /*
  * Kernel timing for benchmarks: when enabled, every launch of the amplitude

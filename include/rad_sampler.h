@@ -35,9 +35,10 @@ extern "C" {
  * over-barrier motion, fall in the last bin), normalised to sum 1;
  * log(omega_osc / 1e5 m^-1) with omega_osc = pi (sign changes of v_x) / (t_end -
  * t_0); and the direction of motion in units of 1/gamma: gamma mean(v_x),
- * gamma mean(v_y), gamma std(v_x), gamma std(v_y) over the samples.  Uses t, x,
- * vx, vy, n and gamma of each segment.  ws: DEVICE workspace of at least
- * n_segs * 48 bytes.  Synchronises `stream` (one upload).
+ * gamma mean(v_y), gamma std(v_x), gamma std(v_y) over the samples (the spread
+ * about the mean, in two passes).  Uses t, x, vx, vy, n and gamma of each segment.
+ * ws: DEVICE workspace of at least n_segs * 48 bytes.  Asynchronous: the segment
+ * descriptors travel as kernel arguments, nothing waits for `stream`.
  */
 rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacing_m, float *feat, void *ws,
                         size_t ws_bytes, void *stream);
@@ -93,11 +94,45 @@ rad_status rad_sampler_select_error(const rad_grid *fine, int n_traj, const floa
  * (cells, DEVICE [n_traj][n_w][n_cells], from rad_cells) where mask is set; else
  * cell_pred (the predicted cell masses of rad_sampler_select or the estimates E_c of
  * rad_sampler_select_error) if it is not NULL, else the coarse centre value times
- * the cell's area.
+ * the cell's area.  Fallback: where fallback[t][w] (DEVICE uint8 [n_traj][n_w]) is
+ * set, dIdw[t][w] = full[t][w] (DEVICE double [n_traj][n_w]), the full-grid angle
+ * integral (rad_batch on the fine grid, then rad_angle_integrate), copied bit for
+ * bit.  fallback and full are both NULL or both given (else RAD_EINVAL).
  */
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
-                               const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,
-                               void *stream);
+                               const uint8_t *mask, const double *coarse, const double *cell_pred,
+                               const uint8_t *fallback, const double *full, double *dIdw, void *stream);
+
+/*
+ * Training data of the network (spectra the method itself computes).
+ *
+ * rad_sampler_targets: the angular shape of each of n_maps spectra S (DEVICE double
+ * [n_maps][n_dirs], e.g. one photon energy of a cube on the fine grid):
+ * y[m][d] = log(max(S, 0) / max_d max(S, 0) + floor_rel) (DEVICE float, same shape),
+ * computed in FP64.  floor_rel > 0 keeps the logarithm finite where S is 0.
+ *
+ * rad_sampler_moments: mean and standard deviation (population) of n floats y
+ * (DEVICE), in FP64 by two fixed-order passes, into moments (DEVICE double [2]); ws:
+ * DEVICE workspace of rad_sampler_moments_workspace_bytes().
+ *
+ * rad_sampler_minibatch: `batch` training points drawn uniformly with replacement: a
+ * map (trajectory t in [0, n), energy slot e in [0, nwt)) and a direction p in
+ * [0, npix), by splitmix64 of (seed, step, point) -- batch `step` is reproducible.
+ * Writes traj[b] = t (DEVICE int [batch]), the point inputs x[b] = point_x[W[t][e] npix
+ * + p] (DEVICE float [batch][3]; W: DEVICE int [n][nwt] energy indices into the point
+ * table point_x, DEVICE float [n_points][3], n_points a multiple of npix; an index
+ * outside the table is clamped into it) and target[b] = (Y[t][e][p] - mean) / std
+ * (Y: DEVICE float [n][nwt][npix]; moments from rad_sampler_moments).
+ *
+ * Errors: RAD_EINVAL for sizes out of range or buffers that are not device memory of
+ * the stated size; RAD_ENOMEM for a small workspace.  No host synchronisation.
+ */
+rad_status rad_sampler_targets(const double *S, int64_t n_maps, int n_dirs, float floor_rel, float *y, void *stream);
+size_t rad_sampler_moments_workspace_bytes(void);
+rad_status rad_sampler_moments(const float *y, int64_t n, double *moments, void *ws, size_t ws_bytes, void *stream);
+rad_status rad_sampler_minibatch(const float *Y, const int *W, int64_t n, int nwt, int npix, const float *point_x,
+                                 int64_t n_points, const double *moments, int batch, uint64_t seed, uint64_t step,
+                                 int *traj, float *x, float *target, void *stream);
 
 #ifdef __cplusplus
 }

@@ -192,9 +192,14 @@ def select_error(pred, mu, sigma, coarse, wx, wy, cx, cy, eps, cap):
     return widen(mask), est
 
 
-def combine(cells, mask, coarse, wx, wy, cx, cy, cell_pred=None):
+def combine(cells, mask, coarse, wx, wy, cx, cy, cell_pred=None, fallback=None, full=None):
     """dI/dhw [n_traj, n_w]: exact cells where selected, else the predicted cell mass
-    (``cell_pred``) or the coarse centre value x area."""
+    (``cell_pred``) or the coarse centre value x area; where ``fallback`` is set, the
+    full-grid value ``full`` [n_traj, n_w] itself (the sampler falls back to the full
+    grid on a mass mismatch)."""
     other = cell_pred if cell_pred is not None else np.asarray(coarse) * cell_areas(wx, wy, cx, cy)
     per = np.where(np.asarray(mask) > 0, cells, other)
-    return per.sum(axis=-1)
+    out = per.sum(axis=-1)
+    if fallback is not None:
+        out = np.where(np.asarray(fallback) > 0, full, out)
+    return out

@@ -9,17 +9,32 @@ namespace radmlp {
 constexpr int kWidth = 256;   // hidden width
 constexpr int kIn1 = 64;      // layer-1 inputs padded to one MFMA-friendly width
 
-enum { kEpiFwd = 0, kEpiBwd = 1, kEpiPartial = 2 };
+enum { kEpiFwd = 0, kEpiBwd = 1 };
 
-// C[m][n] = sum_k A[m][k] B[n][k] with an epilogue (see gemm_nt_kernel).
-struct GemmArgs {
-    const uint16_t *A, *B;
-    int M, N, K, lda, ldb, kslice;
-    const float *bias;    // kEpiFwd
-    const float *zin;     // kEpiBwd: pre-activation of the layer below, [M][N]
-    float *out_z;         // FP32 output [M][N] (or [splits][M][N] partials)
-    uint16_t *out_h;      // BF16 output, row stride ldh
-    int ldh;
+constexpr int kRowBlock = 128;   // rows per block of the row products; batches are padded to it
+
+// C[M][256] = A[M][K] W^T (A, W BF16, K = 64 or 256 contiguous) with an epilogue:
+// forward: z = C + bias (FP32, optional), h = bf16(silu(z)); backward: dz = C silu'(zin),
+// h = bf16(dz) and the per-block column sums of dz (col_part [M / 128][256]).  h goes
+// row-major to out_h and, if out_k8 is given, to the k8 layout [M / 8][256][8].
+struct RowsArgs {
+    const uint16_t *A, *W;
+    int M, K;
+    const float *bias;    // forward
+    const float *zin;     // backward: pre-activation of the layer below, [M][256]
+    float *out_z;         // forward, training: z [M][256] (or null)
+    uint16_t *out_h;      // [M][256]
+    uint16_t *out_k8;     // [M / 8][256][8] or null
+    float *col_part;      // backward: [M / 128][256]
+};
+
+// Weight gradients, C[M][N] = sum over the batch of A8[k/8][m][k%8] B8[k/8][n][k%8] (k8
+// layouts), split over the batch: part[s][M][N] for slices of kslice rows.
+struct K8Args {
+    const uint16_t *A8, *B8;
+    int M, N;
+    int64_t kslice;
+    float *part;
 };
 
 // Offsets of the parameter vector: W1 [256][n_in], b1, W2 [256][256], b2, W3, b3, W4 [256], b4.
@@ -28,21 +43,27 @@ struct MlpLayout {
     int64_t w1, b1, w2, b2, w3, b3, w4, b4, total;
 };
 
-hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t st);
-hipError_t launch_transpose(const uint16_t *in, int M, int N, uint16_t *out, hipStream_t st);
-hipError_t launch_colsum(const float *xf, const uint16_t *xb, const float *w, int M, int N, float *part,
-                         int slices, float *out, hipStream_t st);
+hipError_t launch_rows(int epi, const RowsArgs &g, hipStream_t st);
+hipError_t launch_k8(const K8Args &g, int splits, hipStream_t st);
+hipError_t launch_colsum(const float *x, int64_t ld, int M, int N, float *part, int slices, float *out,
+                         hipStream_t st);
 hipError_t launch_sum_slices(const float *part, int slices, int rows, int src_cols, int n_cols, float *out,
                              int64_t out_stride, hipStream_t st);
 hipError_t launch_assemble_in1(const float *feat, int nf, const int *traj, const float *x, int np, int B, int Bp,
-                               uint16_t *in1, hipStream_t st);
+                               uint16_t *in1, uint16_t *in1_k8, hipStream_t st);
 hipError_t launch_fold_bias(const uint16_t *W1p, const float *b1, const float *feat, int nf, int n_traj, float *cb,
                             hipStream_t st);
 hipError_t launch_layer1_points(const uint16_t *W1p, const float *cb, int nf, const int *traj, const float *x, int np,
                                 int B, int Bp, uint16_t *h1, hipStream_t st);
-hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
-                         const float *target, const float *z3, float *y, float *dy, float *sqerr, float *dz3,
-                         uint16_t *dz3b, hipStream_t st);
+hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp, float *y,
+                         hipStream_t st);
+// training: y, dz3 (BF16 row-major and k8) and per-block partial sums [Bp / 64][514]:
+// b3 gradient, W4 gradient, b4 gradient, sum of squared errors
+constexpr int kOutPointsHost = 64;
+constexpr int kOutPartHost = 2 * kWidth + 2;
+hipError_t launch_output_grad(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
+                              const float *target, const float *z3, uint16_t *dzb, uint16_t *dz_k8, float *part,
+                              hipStream_t st);
 hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t st);
 hipError_t launch_refresh(const float *p, const MlpLayout &L, uint16_t *W1p, uint16_t *W2, uint16_t *W2T,

@@ -40,90 +40,217 @@ __device__ __forceinline__ float dsilu(float z)
 }
 
 // ---------------------------------------------------------------- GEMM
-// C[m][n] = sum_k A[m][k] B[n][k]; A, B BF16 with K contiguous (lda, ldb in
-// elements, multiples of 8, 16-byte aligned rows); M, N multiples of 64; the K
-// range of blockIdx.z is [z kslice, (z+1) kslice), a multiple of 16.
-// Block = 4 waves in a 2 x 2 arrangement of 32 x 32 MFMA tiles.
-// MFMA operand layout (32x32x16 bf16): lane l holds A[l % 32][8 (l / 32) + j] and
-// B[l % 32][8 (l / 32) + j], j = 0..7; result register i of lane l is
-// C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
-template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g)
+// MFMA operand layout (v_mfma_f32_32x32x16_bf16): lane l holds A[l % 32][8 (l / 32) + j]
+// and B[l % 32][8 (l / 32) + j], j = 0..7, for C[m][n] = sum_k A[m][k] B[n][k]; result
+// register i of lane l is C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+//
+// Two product shapes cover the network:
+// * gemm_rows_kernel: C[Bp][256] = A[Bp][K] W^T (W [256][K], both K contiguous; the
+//   layers' forward products and the backward data products).  A block computes 128
+//   rows x all 256 columns; K runs in slices of 32 staged through LDS (double buffered,
+//   one barrier per slice), so that each A and W element is fetched once per block and
+//   shared by the block's four waves; each wave computes 64 x 128 (2 x 4 MFMA tiles).
+//   The epilogue applies the layer (bias + SiLU, or times SiLU' of the layer below),
+//   stores the results row-major and in the k8 layout below, and, in the backward form,
+//   the block's column sums of dz (bias gradients) in a fixed order.
+// * gemm_k8_kernel: C[256][N] = sum over the batch of dz[k][m] h[k][n] (weight
+//   gradients, K = the batch).  Both operands are read in the k8 layout
+//   [Bp / 8][width][8] (8 consecutive batch rows of one unit in 16 bytes), in which an
+//   MFMA operand is one coalesced 16-byte load per lane, so no transpose is needed;
+//   split-K slices write FP32 partials summed in a fixed order afterwards.
+typedef uint16_t bf16x8u __attribute__((ext_vector_type(8)));
+
+template <int EPI, int K>
+__global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    const int kb = blockIdx.z * g.kslice;
-    const int ke = min(g.K, kb + g.kslice);
-    const int r = lane & 31, kh = (lane >> 5) * 8;
-    const uint16_t *Ap = g.A + (size_t)(m0 + r) * g.lda + kh;
-    const uint16_t *Bp = g.B + (size_t)(n0 + r) * g.ldb + kh;
-    floatx16 acc = {};
-    for (int k = kb; k < ke; k += 16) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ap + k);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Bp + k);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-    }
-    const int col = n0 + r;
+    constexpr int KS = 32;                // K slice
+    constexpr int LD = KS + 8;            // LDS row stride (elements): 80 bytes
+    constexpr int NS = K / KS;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][kRowBlock * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][kWidth * LD];
+    __shared__ float sCol[2][kWidth];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int r = lane & 31, hs = lane >> 5;
+    const int64_t row0 = (int64_t)blockIdx.x * kRowBlock;
+    // global -> register staging of one slice: A 128 x 32 (2 chunks of 8 per thread),
+    // W 256 x 32 (4 chunks per thread)
+    uint4 ra[2], rb[4];
+    auto load = [&](int s) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int row = m0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const size_t o = (size_t)row * g.N + col;
-        const float v = acc[i];
-        if constexpr (EPI == kEpiFwd) {            // z = acc + b; h = silu(z)
-            const float z = v + g.bias[col];
-            if (g.out_z) g.out_z[o] = z;
-            g.out_h[(size_t)row * g.ldh + col] = f2bf(silu(z));
-        } else if constexpr (EPI == kEpiBwd) {     // dz = acc * silu'(z_prev)
-            const float dz = v * dsilu(g.zin[o]);
-            g.out_z[o] = dz;
-            g.out_h[(size_t)row * g.ldh + col] = f2bf(dz);
-        } else {                                   // split-K partial
-            g.out_z[(size_t)blockIdx.z * g.M * g.N + o] = v;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
+            ra[q] = *reinterpret_cast<const uint4 *>(g.A + (row0 + rr) * K + s * KS + kc * 8);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
+            rb[q] = *reinterpret_cast<const uint4 *>(g.W + (int64_t)rr * K + s * KS + kc * 8);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
+            *reinterpret_cast<uint4 *>(&sA[buf][rr * LD + kc * 8]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
+            *reinterpret_cast<uint4 *>(&sB[buf][rr * LD + kc * 8]) = rb[q];
+        }
+    };
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx16{};
+    load(0);
+    store(0);
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < NS) load(s + 1);
+#pragma unroll
+        for (int ks = 0; ks < KS / 16; ++ks) {
+            bf16x8 av[2], bv[4];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                av[a] = *reinterpret_cast<const bf16x8 *>(&sA[buf][(wm * 64 + a * 32 + r) * LD + ks * 16 + 8 * hs]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                bv[b] = *reinterpret_cast<const bf16x8 *>(&sB[buf][(wn * 128 + b * 32 + r) * LD + ks * 16 + 8 * hs]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        if (s + 1 < NS) store(buf ^ 1);
+        __syncthreads();
+    }
+    // ---- epilogue
+    float csum[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // backward: this lane's column sums of dz
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int col = wn * 128 + b * 32 + r;
+            const float bias = EPI == kEpiFwd ? g.bias[col] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {            // rows 8 q + 4 hs + (0..3) of the tile
+                const int64_t rbase = row0 + wm * 64 + a * 32 + 8 * q + 4 * hs;
+                uint16_t hv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t row = rbase + j;
+                    const int64_t o = row * kWidth + col;
+                    const float v = acc[a][b][4 * q + j];
+                    float out;
+                    if constexpr (EPI == kEpiFwd) {
+                        const float z = v + bias;
+                        if (g.out_z) g.out_z[o] = z;
+                        out = silu(z);
+                    } else {
+                        out = v * dsilu(g.zin[o]);
+                        csum[b] += out;
+                    }
+                    hv[j] = f2bf(out);
+                    g.out_h[o] = hv[j];
+                }
+                if (g.out_k8) {
+                    // k8 layout: rows rbase .. rbase + 3 of column col are 4 consecutive entries
+                    const int64_t k8 = ((rbase >> 3) * kWidth + col) * 8 + (rbase & 7);
+                    uint2 pk;
+                    pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+                    pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+                    *reinterpret_cast<uint2 *>(g.out_k8 + k8) = pk;
+                }
+            }
+        }
+    if constexpr (EPI == kEpiBwd) {
+        // column sums over the block's 128 rows in a fixed order: the two row halves of a
+        // tile (lanes l and l ^ 32), the wave's two row tiles (already in csum), then the
+        // two row-halves of the block (waves wm = 0, 1) through LDS
+#pragma unroll
+        for (int b = 0; b < 4; ++b) csum[b] += __shfl_xor(csum[b], 32, 64);
+        if (hs == 0)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) sCol[wm][wn * 128 + b * 32 + r] = csum[b];
+        __syncthreads();
+        g.col_part[(int64_t)blockIdx.x * kWidth + tid] = sCol[0][tid] + sCol[1][tid];
     }
 }
 
-// out[n][m] = in[m][n] (BF16), 32 x 32 tiles through LDS; M, N multiples of 32.
-__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t *__restrict__ in, int M, int N,
-                                                             uint16_t *__restrict__ out)
+// Weight gradients from the k8 layouts: C[m][n] = sum_k A8[k / 8][m][k % 8] B8[k / 8][n][k % 8]
+// over the batch slice [z kslice, (z + 1) kslice); waves WM x WN, each 64 x 64.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_k8_kernel(K8Args g)
 {
-    __shared__ uint16_t t[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx over N, by over M
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int j = ty; j < 32; j += 8) t[j][tx] = in[(size_t)(by + j) * N + bx + tx];
-    __syncthreads();
-    for (int j = ty; j < 32; j += 8) out[(size_t)(bx + j) * M + by + tx] = t[tx][j];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave % WM, wn = wave / WM;
+    const int r = lane & 31, hs = lane >> 5;
+    const int m0 = blockIdx.x * (64 * WM) + wm * 64, n0 = blockIdx.y * (64 * WN) + wn * 64;
+    const int64_t kb = (int64_t)blockIdx.z * g.kslice;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = floatx16{};
+    const bf16x8u *A = reinterpret_cast<const bf16x8u *>(g.A8);
+    const bf16x8u *B = reinterpret_cast<const bf16x8u *>(g.B8);
+    const int steps = (int)(g.kslice / 16);
+    for (int t = 0; t < steps; ++t) {
+        const int64_t kg = ((kb + 16 * (int64_t)t) >> 3) + hs;
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = __builtin_bit_cast(bf16x8, A[kg * g.M + m0 + a * 32 + r]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = __builtin_bit_cast(bf16x8, B[kg * g.N + n0 + b * 32 + r]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    float *out = g.part + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = m0 + a * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
+                out[(int64_t)row * g.N + n0 + b * 32 + r] = acc[a][b][i];
+            }
 }
 
 // ---------------------------------------------------------------- reductions
-// Column sums, out[n] = sum over rows m of w[m] X[m][n] (w null -> 1), X FP32 (xf) or BF16
-// (xb), in two passes of one kernel: pass 1 over `slices` row slices writes part[s][n],
-// pass 2 sums the slices.  A block of 256 threads takes nb columns x (256 / nb) row lanes:
-// lane j of a column sums rows m0 + j, m0 + j + lanes, ... of its slice in order, then
-// the lanes are added in a fixed LDS tree, so the result is deterministic.
-__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ xf, const uint16_t *__restrict__ xb,
-                                                     const float *__restrict__ w, int M, int N, int nb,
-                                                     int rows_per, float *__restrict__ out)
+// Column sums, out[n] = sum over rows m of X[m][n] (row stride ld), X FP32, in two passes
+// of one kernel: pass 1 over `slices` row slices writes part[s][n], pass 2 sums the
+// slices.  A block of 256 threads takes nb columns x (256 / nb) row lanes: lane j of a
+// column sums rows m0 + j, m0 + j + lanes, ... of its slice in order, then the lanes are
+// added in a fixed LDS tree, so the result is deterministic.
+__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ x, int64_t ld, int M, int N, int nb,
+                                                     int rows_per, float *__restrict__ out, int64_t ld_out)
 {
     __shared__ float red[256];
     const int lanes = 256 / nb;
     const int c = threadIdx.x % nb, j = threadIdx.x / nb;
-    const int n = blockIdx.x * nb + c;   // < N: the grid has N / nb blocks along x
+    const int n = blockIdx.x * nb + c;
     const int s = blockIdx.y;
     const int m0 = s * rows_per, m1 = min(M, m0 + rows_per);
     float acc = 0.0f;
-    for (int m = m0 + j; m < m1; m += lanes) {
-        const float v = xf ? xf[(size_t)m * N + n] : bf2f(xb[(size_t)m * N + n]);
-        acc += w ? w[m] * v : v;
-    }
+    if (n < N)
+        for (int m = m0 + j; m < m1; m += lanes) acc += x[(int64_t)m * ld + n];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int h = lanes / 2; h >= 1; h >>= 1) {
         if (j < h) red[threadIdx.x] += red[threadIdx.x + h * nb];
         __syncthreads();
     }
-    if (j == 0) out[(size_t)s * N + n] = red[c];
+    if (j == 0 && n < N) out[(int64_t)s * ld_out + n] = red[c];
 }
 
 __global__ __launch_bounds__(256) void sum_slices(const float *__restrict__ part, int slices, int64_t len,
@@ -141,10 +268,11 @@ __global__ __launch_bounds__(256) void sum_slices(const float *__restrict__ part
 }
 
 // ---------------------------------------------------------------- input / output layers
-// in1[m][c] = bf16(feat[traj[m]][c]) for c < nf, bf16(x[m][c - nf]) for c < nf + np, else 0.
+// in1[m][c] = bf16(feat[traj[m]][c]) for c < nf, bf16(x[m][c - nf]) for c < nf + np, else 0;
+// also in the k8 layout in1_k8[m / 8][c][m % 8] when it is not null.
 __global__ __launch_bounds__(256) void assemble_in1(const float *__restrict__ feat, int nf, const int *__restrict__ traj,
                                                     const float *__restrict__ x, int np, int B, int Bp,
-                                                    uint16_t *__restrict__ in1)
+                                                    uint16_t *__restrict__ in1, uint16_t *__restrict__ in1_k8)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)Bp * kIn1) return;
@@ -154,7 +282,9 @@ __global__ __launch_bounds__(256) void assemble_in1(const float *__restrict__ fe
         if (c < nf) v = feat[(size_t)traj[m] * nf + c];
         else if (c < nf + np) v = x[(size_t)m * np + (c - nf)];
     }
-    in1[i] = f2bf(v);
+    const uint16_t h = f2bf(v);
+    in1[i] = h;
+    if (in1_k8) in1_k8[((int64_t)(m >> 3) * kIn1 + c) * 8 + (m & 7)] = h;
 }
 
 // Inference, trajectory part of layer 1 folded into a bias:
@@ -188,53 +318,100 @@ __global__ __launch_bounds__(256) void layer1_points(const uint16_t *__restrict_
     h1[i] = f2bf(silu(z));
 }
 
-// Output layer: y[m] = b4 + sum_i W4[i] h3[m][i], one wave per point.  Training
-// (target != null): also dy[m] = 2 (y - t)/B, loss part, and the start of the
-// backward pass dz3[m][i] = dy W4[i] silu'(z3[m][i]) (FP32 and BF16).
-// Rows B..Bp-1 are padding: every output there is zero.
+// Output layer: y[m] = b4 + sum_i W4[i] h3[m][i], one wave per point (inference).
 __global__ __launch_bounds__(256) void output_layer(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ W4b,
                                                     const float *__restrict__ b4, int B, int Bp,
-                                                    const float *__restrict__ target, const float *__restrict__ z3,
-                                                    float *__restrict__ y, float *__restrict__ dy,
-                                                    float *__restrict__ sqerr, float *__restrict__ dz3,
-                                                    uint16_t *__restrict__ dz3b)
+                                                    float *__restrict__ y)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = blockIdx.x * 4 + wave;
     if (m >= Bp) return;
     if (m >= B) {
-        if (lane == 0) {
-            y[m] = 0.0f;
-            if (target) {
-                dy[m] = 0.0f;
-                sqerr[m] = 0.0f;
-            }
-        }
-        if (target)
-            for (int i = lane; i < kWidth; i += 64) {
-                dz3[(size_t)m * kWidth + i] = 0.0f;
-                dz3b[(size_t)m * kWidth + i] = 0;
-            }
+        if (lane == 0) y[m] = 0.0f;
         return;
     }
     float acc = 0.0f;
     for (int i = lane; i < kWidth; i += 64) acc += bf2f(W4b[i]) * bf2f(h3[(size_t)m * kWidth + i]);
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    const float ym = acc + b4[0];
-    if (lane == 0) y[m] = ym;
-    if (!target) return;
-    const float d = ym - target[m];
-    const float g = 2.0f * d / (float)B;
+    if (lane == 0) y[m] = acc + b4[0];
+}
+
+// Output layer of a training step, 64 points per block (16 per wave, lane j owning units
+// j + 64 q): y = b4 + W4 . h3, d = y - target, dy = 2 d / B, and the start of the backward
+// pass dz3 = dy W4 silu'(z3), stored in BF16 row-major and in the k8 layout (8 points at a
+// time, one 16-byte store per unit).  The block's sums, in a fixed order, go to
+// part[block][0 .. 513): the b3 gradient (sum of dz3, FP32), the W4 gradient (sum of
+// dy h3), the b4 gradient (sum of dy), then the sum of d^2.  Rows B..Bp-1 are padding:
+// every output there is zero.
+constexpr int kOutPoints = 64;
+constexpr int kOutPart = 2 * kWidth + 2;
+static_assert(kOutPoints == kOutPointsHost && kOutPart == kOutPartHost, "output partials");
+static_assert(kRowBlock % kOutPoints == 0, "row blocks hold whole output blocks");
+
+__global__ __launch_bounds__(256) void output_grad_kernel(const uint16_t *__restrict__ h3,
+                                                          const uint16_t *__restrict__ W4b,
+                                                          const float *__restrict__ b4, int B,
+                                                          const float *__restrict__ target,
+                                                          const float *__restrict__ z3,
+                                                          uint16_t *__restrict__ dzb, uint16_t *__restrict__ dz_k8,
+                                                          float *__restrict__ part)
+{
+    __shared__ float sP[4][kOutPart];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float w4[4], sb3[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sw4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float sdy = 0.0f, ssq = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w4[q] = bf2f(W4b[lane + 64 * q]);
+    const float inv = 2.0f / (float)B;
+    for (int grp = 0; grp < 2; ++grp) {
+        const int64_t mg = (int64_t)blockIdx.x * kOutPoints + wave * 16 + grp * 8;   // multiple of 8
+        uint16_t hv[4][8];
+        for (int p = 0; p < 8; ++p) {
+            const int64_t m = mg + p;
+            float hq[4], acc = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hq[q] = bf2f(h3[m * kWidth + lane + 64 * q]);
+                acc += w4[q] * hq[q];
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            const bool real = m < B;
+            const float d = real ? acc + b4[0] - target[m] : 0.0f;
+            const float gdy = inv * d;
+            sdy += gdy;
+            ssq += d * d;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t o = m * kWidth + lane + 64 * q;
+                const float dz = real ? gdy * w4[q] * dsilu(z3[o]) : 0.0f;
+                sb3[q] += dz;
+                sw4[q] += gdy * hq[q];
+                hv[q][p] = f2bf(dz);
+                dzb[o] = hv[q][p];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint4 pk;
+            pk.x = (uint32_t)hv[q][0] | ((uint32_t)hv[q][1] << 16);
+            pk.y = (uint32_t)hv[q][2] | ((uint32_t)hv[q][3] << 16);
+            pk.z = (uint32_t)hv[q][4] | ((uint32_t)hv[q][5] << 16);
+            pk.w = (uint32_t)hv[q][6] | ((uint32_t)hv[q][7] << 16);
+            *reinterpret_cast<uint4 *>(dz_k8 + ((mg >> 3) * kWidth + lane + 64 * q) * 8) = pk;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sP[wave][lane + 64 * q] = sb3[q];
+        sP[wave][kWidth + lane + 64 * q] = sw4[q];
+    }
     if (lane == 0) {
-        dy[m] = g;
-        sqerr[m] = d * d;
+        sP[wave][2 * kWidth] = sdy;
+        sP[wave][2 * kWidth + 1] = ssq;
     }
-    for (int i = lane; i < kWidth; i += 64) {
-        const size_t o = (size_t)m * kWidth + i;
-        const float v = g * bf2f(W4b[i]) * dsilu(z3[o]);
-        dz3[o] = v;
-        dz3b[o] = f2bf(v);
-    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOutPart; i += 256)
+        part[(int64_t)blockIdx.x * kOutPart + i] = ((sP[0][i] + sP[1][i]) + sP[2][i]) + sP[3][i];
 }
 
 // ---------------------------------------------------------------- Adam and working copies
@@ -443,39 +620,45 @@ __global__ __launch_bounds__(kFusedThreads, 1) void infer_fused_kernel(FusedArgs
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t st)
+hipError_t launch_rows(int epi, const RowsArgs &g, hipStream_t st)
 {
-    const dim3 grid((unsigned)(g.M / 64), (unsigned)(g.N / 64), (unsigned)splits);
-    switch (epi) {
-    case kEpiFwd: hipLaunchKernelGGL(gemm_nt_kernel<kEpiFwd>, grid, dim3(256), 0, st, g); break;
-    case kEpiBwd: hipLaunchKernelGGL(gemm_nt_kernel<kEpiBwd>, grid, dim3(256), 0, st, g); break;
-    default: hipLaunchKernelGGL(gemm_nt_kernel<kEpiPartial>, grid, dim3(256), 0, st, g); break;
+    if (g.M % kRowBlock || (g.K != kIn1 && g.K != kWidth) || (epi != kEpiFwd && epi != kEpiBwd))
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(g.M / kRowBlock));
+    if (epi == kEpiFwd) {
+        if (g.K == kIn1) hipLaunchKernelGGL((gemm_rows_kernel<kEpiFwd, kIn1>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((gemm_rows_kernel<kEpiFwd, kWidth>), grid, dim3(256), 0, st, g);
+    } else {
+        if (g.K == kIn1) hipLaunchKernelGGL((gemm_rows_kernel<kEpiBwd, kIn1>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((gemm_rows_kernel<kEpiBwd, kWidth>), grid, dim3(256), 0, st, g);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(const uint16_t *in, int M, int N, uint16_t *out, hipStream_t st)
+hipError_t launch_k8(const K8Args &g, int splits, hipStream_t st)
 {
-    hipLaunchKernelGGL(transpose_bf16_kernel, dim3((unsigned)(N / 32), (unsigned)(M / 32)), dim3(256), 0, st,
-                       in, M, N, out);
+    if (g.M != kWidth || (g.N != kWidth && g.N != kIn1) || g.kslice % 16 || splits < 1) return hipErrorInvalidValue;
+    if (g.N == kWidth)
+        hipLaunchKernelGGL((gemm_k8_kernel<2, 2>), dim3(2u, 2u, (unsigned)splits), dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_k8_kernel<4, 1>), dim3(1u, 1u, (unsigned)splits), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float *xf, const uint16_t *xb, const float *w, int M, int N, float *part,
-                         int slices, float *out, hipStream_t st)
+hipError_t launch_colsum(const float *x, int64_t ld, int M, int N, float *part, int slices, float *out,
+                         hipStream_t st)
 {
-    // columns per block: N itself up to 64 (a power of two), else 64 (then pass 2 takes 16)
-    auto cols = [](int n, int most) { return n <= most ? n : most; };
-    const int nb1 = cols(N, 64), nb2 = cols(N, 16);
-    if (M < 1 || N < 1 || slices < 1 || 256 % nb1 != 0 || N % nb1 != 0 || 256 % nb2 != 0 || N % nb2 != 0)
-        return hipErrorInvalidValue;
+    // pass 1: 64 columns x 4 row lanes per block over `slices` row slices; pass 2: 16 x 16
+    if (M < 1 || N < 1 || slices < 1) return hipErrorInvalidValue;
+    const int nb1 = 64, nb2 = 16;
     const int rows_per = (M + slices - 1) / slices;
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)(N / nb1), (unsigned)slices), dim3(256), 0, st, xf, xb, w, M,
-                       N, nb1, rows_per, part);
+    const int used = (M + rows_per - 1) / rows_per;
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + nb1 - 1) / nb1), (unsigned)used), dim3(256), 0, st, x, ld,
+                       M, N, nb1, rows_per, part, (int64_t)N);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)(N / nb2), 1u), dim3(256), 0, st, part, nullptr, nullptr,
-                       slices, N, nb2, slices, out);
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + nb2 - 1) / nb2), 1u), dim3(256), 0, st, part, (int64_t)N,
+                       used, N, nb2, used, out, (int64_t)N);
     return hipGetLastError();
 }
 
@@ -489,11 +672,11 @@ hipError_t launch_sum_slices(const float *part, int slices, int rows, int src_co
 }
 
 hipError_t launch_assemble_in1(const float *feat, int nf, const int *traj, const float *x, int np, int B, int Bp,
-                               uint16_t *in1, hipStream_t st)
+                               uint16_t *in1, uint16_t *in1_k8, hipStream_t st)
 {
     const int64_t n = (int64_t)Bp * kIn1;
     hipLaunchKernelGGL(assemble_in1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, feat, nf, traj, x, np,
-                       B, Bp, in1);
+                       B, Bp, in1, in1_k8);
     return hipGetLastError();
 }
 
@@ -514,12 +697,20 @@ hipError_t launch_layer1_points(const uint16_t *W1p, const float *cb, int nf, co
     return hipGetLastError();
 }
 
-hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
-                         const float *target, const float *z3, float *y, float *dy, float *sqerr, float *dz3,
-                         uint16_t *dz3b, hipStream_t st)
+hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp, float *y,
+                         hipStream_t st)
 {
-    hipLaunchKernelGGL(output_layer, dim3((unsigned)((Bp + 3) / 4)), dim3(256), 0, st, h3, W4b, b4, B, Bp, target,
-                       z3, y, dy, sqerr, dz3, dz3b);
+    hipLaunchKernelGGL(output_layer, dim3((unsigned)((Bp + 3) / 4)), dim3(256), 0, st, h3, W4b, b4, B, Bp, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_grad(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
+                              const float *target, const float *z3, uint16_t *dzb, uint16_t *dz_k8, float *part,
+                              hipStream_t st)
+{
+    if (Bp % kOutPoints) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(output_grad_kernel, dim3((unsigned)(Bp / kOutPoints)), dim3(256), 0, st, h3, W4b, b4, B, target,
+                       z3, dzb, dz_k8, part);
     return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ rad_status mhip(hipError_t e, const char *what)
     return mfail(RAD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-int64_t round64(int64_t b) { return (b + 63) / 64 * 64; }
+// batches are padded to whole row blocks of the row products
+int64_t round_rows(int64_t b) { return (b + kRowBlock - 1) / kRowBlock * kRowBlock; }
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 MlpLayout make_layout(int nf, int np)
@@ -71,12 +72,12 @@ MlpLayout make_layout(int nf, int np)
 
 // Workspace carve-up for a padded batch Bp and n_traj trajectories.
 struct MWs {
-    uint16_t *in1, *h1, *h2, *h3, *dzb, *dzT, *hT;
-    float *z1, *z2, *z3, *dz, *y, *dy, *sqerr, *part, *cpart, *cb;
+    uint16_t *in1, *in1_k8, *h1, *h2, *h3, *h1_k8, *h2_k8, *dzA, *dzB, *dz_k8;
+    float *z1, *z2, *z3, *y, *part, *opart, *colpart, *cpart, *cb;
     size_t total;
 };
 
-constexpr int kSplits = 32;     // split-K slices of the weight-gradient products
+constexpr int kSplits = 64;     // most split-K slices of the weight-gradient products
 constexpr int kColSlices = 256; // row slices of the column sums (pass 1 runs N/64 x 256 blocks)
 
 // Inference needs the folded biases, and unless the fused kernel runs (n_point <= 8)
@@ -107,21 +108,23 @@ MWs carve(char *base, int64_t Bp, int n_traj)
     auto take = [&](size_t bytes) { char *p = base ? base + o : nullptr; o = al(o + bytes); return p; };
     const size_t act = (size_t)Bp * kWidth;
     w.in1 = (uint16_t *)take((size_t)Bp * kIn1 * 2);
+    w.in1_k8 = (uint16_t *)take((size_t)Bp * kIn1 * 2);
     w.h1 = (uint16_t *)take(act * 2);
     w.h2 = (uint16_t *)take(act * 2);
     w.h3 = (uint16_t *)take(act * 2);
-    w.dzb = (uint16_t *)take(act * 2);
-    w.dzT = (uint16_t *)take(act * 2);
-    w.hT = (uint16_t *)take(act * 2);
+    w.h1_k8 = (uint16_t *)take(act * 2);
+    w.h2_k8 = (uint16_t *)take(act * 2);
+    w.dzA = (uint16_t *)take(act * 2);
+    w.dzB = (uint16_t *)take(act * 2);
+    w.dz_k8 = (uint16_t *)take(act * 2);
     w.z1 = (float *)take(act * 4);
     w.z2 = (float *)take(act * 4);
     w.z3 = (float *)take(act * 4);
-    w.dz = (float *)take(act * 4);
     w.y = (float *)take((size_t)Bp * 4);
-    w.dy = (float *)take((size_t)Bp * 4);
-    w.sqerr = (float *)take((size_t)Bp * 4);
     w.part = (float *)take((size_t)kSplits * kWidth * kWidth * 4);
-    w.cpart = (float *)take((size_t)kColSlices * kWidth * 4);
+    w.opart = (float *)take((size_t)(Bp / kOutPointsHost) * kOutPartHost * 4);
+    w.colpart = (float *)take((size_t)(Bp / kRowBlock) * kWidth * 4);
+    w.cpart = (float *)take((size_t)kColSlices * kOutPartHost * 4);
     w.cb = (float *)take((size_t)std::max(n_traj, 1) * kWidth * 4);
     w.total = o;
     return w;
@@ -157,7 +160,7 @@ rad_status check_batch(const rad_mlp *m, const float *feat, int n_traj, const in
     if (rs != RAD_OK) return rs;
     if (batch <= 0 || n_traj <= 0) return mfail(RAD_EINVAL, "batch and n_traj must be > 0");
     if (batch > (1 << 26)) return mfail(RAD_EINVAL, "batch too large");
-    const int64_t Bp = round64(batch);
+    const int64_t Bp = round_rows(batch);
     w = training ? carve(nullptr, Bp, n_traj) : carve_infer(nullptr, Bp, n_traj, fused_ok(m));
     if (!ws) return mfail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < w.total) return mfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, w.total);
@@ -304,8 +307,8 @@ rad_status rad_mlp_set_adam(rad_mlp *m, const float *m1, const float *m2, int64_
 size_t rad_mlp_workspace_bytes(const rad_mlp *m, int batch, int n_traj, int training)
 {
     if (!m || batch <= 0 || n_traj <= 0) return 0;
-    return (training ? carve(nullptr, round64(batch), n_traj)
-                     : carve_infer(nullptr, round64(batch), n_traj, fused_ok(m))).total;
+    return (training ? carve(nullptr, round_rows(batch), n_traj)
+                     : carve_infer(nullptr, round_rows(batch), n_traj, fused_ok(m))).total;
 }
 
 rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const int *traj, const float *x,
@@ -321,51 +324,54 @@ rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const i
     hipStream_t st = (hipStream_t)stream;
     const MlpLayout &L = m->L;
     const int B = batch;
-    const int Bp = (int)round64(batch);
-    int splits = 1;   // split-K slices of the weight gradients: a power of two dividing Bp/64
-    while (splits < kSplits && (Bp / 64) % (2 * splits) == 0) splits *= 2;
+    const int Bp = (int)round_rows(batch);
+    // split-K slices of the weight gradients: a power of two dividing the row blocks
+    int splits = 1;
+    while (splits < kSplits && (Bp / kRowBlock) % (2 * splits) == 0) splits *= 2;
     hipError_t e;
 #define CK(x)                                               \
     do {                                                    \
         e = (x);                                            \
         if (e != hipSuccess) return mhip(e, #x);            \
     } while (0)
-    // forward
-    CK(launch_assemble_in1(feat, L.n_feat, traj, x, L.n_point, B, Bp, w.in1, st));
-    GemmArgs g{};
-    g = GemmArgs{w.in1, m->W1p, Bp, kWidth, kIn1, kIn1, kIn1, kIn1, m->p + L.b1, nullptr, w.z1, w.h1, kWidth};
-    CK(launch_gemm(kEpiFwd, g, 1, st));
-    g = GemmArgs{w.h1, m->W2, Bp, kWidth, kWidth, kWidth, kWidth, kWidth, m->p + L.b2, nullptr, w.z2, w.h2, kWidth};
-    CK(launch_gemm(kEpiFwd, g, 1, st));
-    g = GemmArgs{w.h2, m->W3, Bp, kWidth, kWidth, kWidth, kWidth, kWidth, m->p + L.b3, nullptr, w.z3, w.h3, kWidth};
-    CK(launch_gemm(kEpiFwd, g, 1, st));
-    CK(launch_output(w.h3, m->W4, m->p + L.b4, B, Bp, target, w.z3, w.y, w.dy, w.sqerr, w.dz, w.dzb, st));
-    CK(launch_colsum(w.sqerr, nullptr, nullptr, Bp, 1, w.cpart, kColSlices, loss_sum, st));
-    // output layer gradients
-    CK(launch_colsum(nullptr, w.h3, w.dy, Bp, kWidth, w.cpart, kColSlices, grad + L.w4, st));
-    CK(launch_colsum(w.dy, nullptr, nullptr, Bp, 1, w.cpart, kColSlices, grad + L.b4, st));
-    // layers 3, 2, 1: dW = dz^T h_prev (split-K), db = column sums of dz, dz_prev
-    const uint16_t *hprev[3] = {w.h2, w.h1, w.in1};
+    // forward: h = silu(z) row-major for the next layer, and in the k8 layout (batch rows
+    // interleaved by 8) for the weight gradients
+    CK(launch_assemble_in1(feat, L.n_feat, traj, x, L.n_point, B, Bp, w.in1, w.in1_k8, st));
+    RowsArgs g{w.in1, m->W1p, Bp, kIn1, m->p + L.b1, nullptr, w.z1, w.h1, w.h1_k8, nullptr};
+    CK(launch_rows(kEpiFwd, g, st));
+    g = RowsArgs{w.h1, m->W2, Bp, kWidth, m->p + L.b2, nullptr, w.z2, w.h2, w.h2_k8, nullptr};
+    CK(launch_rows(kEpiFwd, g, st));
+    g = RowsArgs{w.h2, m->W3, Bp, kWidth, m->p + L.b3, nullptr, w.z3, w.h3, nullptr, nullptr};
+    CK(launch_rows(kEpiFwd, g, st));
+    // output layer: loss, dz3, and the b3, W4, b4 gradients and the loss as column sums of
+    // its per-block partials (b3, W4, b4 are contiguous in the parameter vector)
+    CK(launch_output_grad(w.h3, m->W4, m->p + L.b4, B, Bp, target, w.z3, w.dzA, w.dz_k8, w.opart, st));
+    static_assert(kOutPartHost == 2 * kWidth + 2, "partials: b3, W4, b4, loss");
+    CK(launch_colsum(w.opart, kOutPartHost, Bp / kOutPointsHost, 2 * kWidth + 1, w.cpart, kColSlices, grad + L.b3,
+                     st));
+    CK(launch_colsum(w.opart + 2 * kWidth + 1, kOutPartHost, Bp / kOutPointsHost, 1, w.cpart, kColSlices, loss_sum,
+                     st));
+    // layers 3, 2, 1: dW = dz^T h_prev from the k8 layouts (split over the batch), then
+    // dz_prev = (dz W) silu'(z_prev) with the column sums of dz_prev (the bias gradient)
+    const uint16_t *hprev_k8[3] = {w.h2_k8, w.h1_k8, w.in1_k8};
     const int nprev[3] = {kWidth, kWidth, kIn1};
     const int64_t woff[3] = {L.w3, L.w2, L.w1};
-    const int64_t boff[3] = {L.b3, L.b2, L.b1};
+    const int64_t boff[2] = {L.b2, L.b1};
     const uint16_t *WT[2] = {m->W3T, m->W2T};
-    float *zprev[2] = {w.z2, w.z1};
+    const float *zprev[2] = {w.z2, w.z1};
+    uint16_t *dz_cur = w.dzA, *dz_next = w.dzB;
     for (int l = 0; l < 3; ++l) {
-        CK(launch_transpose(w.dzb, Bp, kWidth, w.dzT, st));
-        CK(launch_transpose(hprev[l], Bp, nprev[l], w.hT, st));
-        g = GemmArgs{w.dzT, w.hT, kWidth, nprev[l], Bp, Bp, Bp, Bp / splits, nullptr, nullptr, w.part, nullptr, 0};
-        CK(launch_gemm(kEpiPartial, g, splits, st));
+        K8Args k8{w.dz_k8, hprev_k8[l], kWidth, nprev[l], (int64_t)Bp / splits, w.part};
+        CK(launch_k8(k8, splits, st));
         const int ncols = l == 2 ? L.n_in : kWidth;
         CK(launch_sum_slices(w.part, splits, kWidth, nprev[l], ncols, grad + woff[l], ncols, st));
-        CK(launch_colsum(w.dz, nullptr, nullptr, Bp, kWidth, w.cpart, kColSlices, grad + boff[l], st));
         if (l < 2) {
-            // dz_prev = (dz W) * silu'(z_prev).  The product overwrites dz/dzb while it
-            // reads its BF16 operand, so the operand is copied to the free hT buffer first.
-            CK(hipMemcpyAsync(w.hT, w.dzb, (size_t)Bp * kWidth * 2, hipMemcpyDeviceToDevice, st));
-            g = GemmArgs{w.hT, WT[l], Bp, kWidth, kWidth, kWidth, kWidth, kWidth, nullptr, zprev[l], w.dz, w.dzb,
-                         kWidth};
-            CK(launch_gemm(kEpiBwd, g, 1, st));
+            g = RowsArgs{dz_cur, WT[l], Bp, kWidth, nullptr, zprev[l], nullptr, dz_next, w.dz_k8, w.colpart};
+            CK(launch_rows(kEpiBwd, g, st));
+            CK(launch_colsum(w.colpart, kWidth, Bp / kRowBlock, kWidth, w.cpart, kColSlices, grad + boff[l], st));
+            uint16_t *t = dz_cur;
+            dz_cur = dz_next;
+            dz_next = t;
         }
     }
 #undef CK
@@ -397,7 +403,7 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
     if ((rs = check_range(y, (size_t)batch * 4, "y")) != RAD_OK) return rs;
     hipStream_t st = (hipStream_t)stream;
     const MlpLayout &L = m->L;
-    const int Bp = (int)round64(batch);
+    const int Bp = (int)round_rows(batch);
     hipError_t e = launch_fold_bias(m->W1p, m->p + L.b1, feat, L.n_feat, n_traj, w.cb, st);
     if (fused_ok(m)) {
         if (e == hipSuccess)
@@ -406,13 +412,11 @@ rad_status rad_mlp_forward(const rad_mlp *m, const float *feat, int n_traj, cons
         return e == hipSuccess ? RAD_OK : mhip(e, "MLP forward");
     }
     if (e == hipSuccess) e = launch_layer1_points(m->W1p, w.cb, L.n_feat, traj, x, L.n_point, batch, Bp, w.h1, st);
-    GemmArgs g{w.h1, m->W2, Bp, kWidth, kWidth, kWidth, kWidth, kWidth, m->p + L.b2, nullptr, nullptr, w.h2, kWidth};
-    if (e == hipSuccess) e = launch_gemm(kEpiFwd, g, 1, st);
-    g = GemmArgs{w.h2, m->W3, Bp, kWidth, kWidth, kWidth, kWidth, kWidth, m->p + L.b3, nullptr, nullptr, w.h3, kWidth};
-    if (e == hipSuccess) e = launch_gemm(kEpiFwd, g, 1, st);
-    if (e == hipSuccess)
-        e = launch_output(w.h3, m->W4, m->p + L.b4, batch, Bp, nullptr, nullptr, w.y, nullptr, nullptr, nullptr,
-                          nullptr, st);
+    RowsArgs g{w.h1, m->W2, Bp, kWidth, m->p + L.b2, nullptr, nullptr, w.h2, nullptr, nullptr};
+    if (e == hipSuccess) e = launch_rows(kEpiFwd, g, st);
+    g = RowsArgs{w.h2, m->W3, Bp, kWidth, m->p + L.b3, nullptr, nullptr, w.h3, nullptr, nullptr};
+    if (e == hipSuccess) e = launch_rows(kEpiFwd, g, st);
+    if (e == hipSuccess) e = launch_output(w.h3, m->W4, m->p + L.b4, batch, Bp, w.y, st);
     if (e == hipSuccess) e = hipMemcpyAsync(y, w.y, (size_t)batch * 4, hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? RAD_OK : mhip(e, "MLP forward");
 }

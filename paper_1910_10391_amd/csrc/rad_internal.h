@@ -65,6 +65,7 @@ struct AmpLaunch {
     int quantum;           // 0: kappa = k; 1: kappa = k E/(E - hw)
     int comps;             // 2 (A_x, A_y) or 3 (A_x, A_y, J)
     double2 *part;         // partial amplitudes [seg][chunk][comp][n][w]
+    int64_t part_len;      // elements of `part` (index checks of the RAD_DEBUG build)
     unsigned *counter;     // ticket of the persistent form (zeroed before the launch)
     int rec;               // FP64: phase factors by recurrence (every segment's dth != 0)
 };
@@ -77,6 +78,7 @@ struct FinLaunch {
     const SegDesc *qs;          // quantum-set descriptors by segment id (or null)
     const double2 *part_c;      // classical partials
     const double2 *part_q;      // quantum partials
+    int64_t part_c_len, part_q_len;   // their elements (index checks of the RAD_DEBUG build)
     int comps_q;                // 2 or 3
     const double *hw, *thx, *thy;
     int n_w, n_x, n_y;
@@ -95,6 +97,7 @@ struct CellsFin {
     const int *psof;            // [n_segs][n_cells] -> pseudo-segment or -1
     const uint8_t *mask;        // [n_segs][n_w][n_cells]
     const double2 *part;
+    int64_t part_len;           // elements of `part` (index checks of the RAD_DEBUG build)
     int comps, kind;
     const double *wx, *wy;      // direction cell widths of the fine grid
     const double *hw;

@@ -42,6 +42,33 @@
 
 namespace rad {
 
+// Index checks of the debug build (-DRAD_DEBUG=1): descriptor, chunk and partial-amplitude
+// indices are checked against the launch's bounds; a violation is counted (read with
+// rad_debug_violations) and the access skipped.  The release build compiles them away.
+#ifndef RAD_DEBUG
+#define RAD_DEBUG 0
+#endif
+#if RAD_DEBUG
+__device__ unsigned long long g_debug_violations = 0;
+__device__ __forceinline__ bool debug_ok(bool cond)
+{
+    if (!cond) atomicAdd(&g_debug_violations, 1ull);
+    return cond;
+}
+#define RAD_DEBUG_OK(cond) debug_ok(cond)
+#else
+#define RAD_DEBUG_OK(cond) true
+#endif
+
+// A wave-uniform 64-bit value taken into scalar registers (readfirstlane of both halves).
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Phase factor of a lane: FP64 polynomial on half turns, or FP32 hardware
 // sin/cos on revolutions (mixed precision).  `kh` is kappa/pi (FP64 form) or
 // kappa/(2 pi) (mixed form).
@@ -105,7 +132,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     }
     __syncthreads();
     // wave-uniform: descriptor fields then live in SGPRs (scalar loads), not VGPRs
-    const int s_seg = __builtin_amdgcn_readfirstlane(sm.seg);
+    int s_seg = __builtin_amdgcn_readfirstlane(sm.seg);
+    if (!RAD_DEBUG_OK(s_seg >= 0 && s_seg < L.n_segs)) s_seg = 0;
     const SegDesc &S = L.segs[s_seg];
     const int64_t n = S.n;
     const double c0 = S.c0;
@@ -124,14 +152,18 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         grp = __builtin_amdgcn_readfirstlane(it.z);
         wb = __builtin_amdgcn_readfirstlane(it.w);
     } else {
+        // 64-bit divisions expand into vector instructions: their results are taken back
+        // into scalar registers, so that the time loop's bounds and counter stay scalar
+        // (in vector registers they took four of them and were spilled in every pass)
         int64_t local = b - S.block_begin;
-        wb = (int)(local % S.n_wblocks);
+        wb = __builtin_amdgcn_readfirstlane((int)(local % S.n_wblocks));
         local /= S.n_wblocks;
-        grp = (int)(local % S.n_groups);
-        chunk = (int)(local / S.n_groups);
+        grp = __builtin_amdgcn_readfirstlane((int)(local % S.n_groups));
+        chunk = __builtin_amdgcn_readfirstlane((int)(local / S.n_groups));
     }
-    const int64_t k_begin = (int64_t)chunk * S.chunk_len;
-    const int64_t k_end = min(n, k_begin + (int64_t)S.chunk_len);
+    const int64_t k_begin = uniform64((int64_t)chunk * S.chunk_len);
+    int64_t k_end = uniform64(min(n, k_begin + (int64_t)S.chunk_len));
+    if (!RAD_DEBUG_OK(chunk >= 0 && chunk < S.n_chunks && k_begin < n)) k_end = k_begin;
 
     const int nt = L.nt, wg = L.wg;
     const int lnt = nt == 4 ? 2 : (nt == 2 ? 1 : 0);   // nt is 1, 2 or 4 (checked at launch)
@@ -442,6 +474,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         const int jx = tx0 + p % TX, jy = ty0 + p / TX;
         if (jx >= n_x || jy >= n_y) continue;
         const int64_t nn = (int64_t)jy * n_x + jx;
+        if (!RAD_DEBUG_OK(base + ((int64_t)(L.comps - 1) * n_n + nn) * n_w + iw < L.part_len)) continue;
         L.part[base + (0 * n_n + nn) * n_w + iw] = make_double2(axr[p], axi[p]);
         L.part[base + (1 * n_n + nn) * n_w + iw] = make_double2(ayr[p], ayi[p]);
         if constexpr (WITHJ) L.part[base + (2 * n_n + nn) * n_w + iw] = make_double2(jr[p], ji[p]);
@@ -456,9 +489,14 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_kernel(AmpLaunch L)
     // launched with one block per item, so this runs once; written as a loop because
     // the register allocation of the hot loop comes out tighter in this form
     // (measured in the gfx950 assembly: no copies or scratch in the recurrence form)
-    for (int64_t b = blockIdx.x; b < L.n_blocks; b += gridDim.x) {
-        amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
-        __syncthreads();
+    if constexpr (TY == 6) {
+        // the 4x6 tile (no J) allocates its hot loop without spills only in this loop form
+        for (int64_t b = blockIdx.x; b < L.n_blocks; b += gridDim.x) {
+            amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
+            __syncthreads();
+        }
+    } else {
+        amp_item<TX, TY, WITHJ, MIXED, REC>(L, (int64_t)blockIdx.x, sm);
     }
 }
 
@@ -533,12 +571,18 @@ __device__ __forceinline__ double2 chunk_sum(const double2 *__restrict__ p, int6
 // ONE: every segment of the launch is a single chunk, and its partial is the sum (the
 // same value chunk_sum returns for n = 1, without the sixteen running sums' registers)
 template <bool ONE>
-__device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, const SegDesc &d,
+__device__ __forceinline__ void sum_chunks(const double2 *__restrict__ part, int64_t part_len, const SegDesc &d,
                                            int comps, int comp, int64_t n_n, int n_w, int64_t nn,
                                            int iw, double &re, double &im)
 {
     const int64_t stride = (int64_t)comps * n_n * n_w;
-    const double2 *p = part + d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw;
+    const int64_t first = d.part_off + ((int64_t)comp * n_n + nn) * n_w + iw;
+    if (!RAD_DEBUG_OK(first >= 0 && first + (int64_t)(d.n_chunks - 1) * stride < part_len)) {
+        re = im = 0.0;
+        return;
+    }
+    (void)part_len;
+    const double2 *p = part + first;
     const double2 v = ONE ? *p : chunk_sum(p, stride, d.n_chunks);
     re = v.x;
     im = v.y;
@@ -562,8 +606,8 @@ __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
         if (F.kinds & 1) {
             const SegDesc &d = F.cls[s];
             double xr, xi, yr, yi;
-            sum_chunks<ONE>(F.part_c, d, 2, 0, n_n, F.n_w, nn, iw, xr, xi);
-            sum_chunks<ONE>(F.part_c, d, 2, 1, n_n, F.n_w, nn, iw, yr, yi);
+            sum_chunks<ONE>(F.part_c, F.part_c_len, d, 2, 0, n_n, F.n_w, nn, iw, xr, xi);
+            sum_chunks<ONE>(F.part_c, F.part_c_len, d, 2, 1, n_n, F.n_w, nn, iw, yr, yi);
             const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
             sc += pref * (xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi);
         }
@@ -572,15 +616,15 @@ __global__ __launch_bounds__(256) void fin_kernel(FinLaunch F)
             const double E = d.energy;
             if (hw < E) {
                 double xr, xi, yr, yi;
-                sum_chunks<ONE>(F.part_q, d, F.comps_q, 0, n_n, F.n_w, nn, iw, xr, xi);
-                sum_chunks<ONE>(F.part_q, d, F.comps_q, 1, n_n, F.n_w, nn, iw, yr, yi);
+                sum_chunks<ONE>(F.part_q, F.part_q_len, d, F.comps_q, 0, n_n, F.n_w, nn, iw, xr, xi);
+                sum_chunks<ONE>(F.part_q, F.part_q_len, d, F.comps_q, 1, n_n, F.n_w, nn, iw, yr, yi);
                 const double zr = -(thx * xr + thy * yr), zi = -(thx * xi + thy * yi);
                 const double S = xr * xr + xi * xi + yr * yr + yi * yi + zr * zr + zi * zi;
                 const double Es = E - hw;
                 if (F.kinds & 2) s0 += pref * (Es / E) * S;
                 if (F.kinds & 4) {
                     double jr_, ji_;
-                    sum_chunks<ONE>(F.part_q, d, F.comps_q, 2, n_n, F.n_w, nn, iw, jr_, ji_);
+                    sum_chunks<ONE>(F.part_q, F.part_q_len, d, F.comps_q, 2, n_n, F.n_w, nn, iw, jr_, ji_);
                     const double SJ = jr_ * jr_ + ji_ * ji_;
                     sh += pref * ((Es * Es + E * E) / (2.0 * E * E) * S +
                                   hw * hw / (2.0 * E * E * d.gamma * d.gamma) * SJ);
@@ -630,8 +674,9 @@ __global__ __launch_bounds__(256) void cells_fin_kernel(CellsFin F)
         const double thx = d.thx[jx], thy = d.thy[jy];
         double re[3] = {0.0, 0.0, 0.0}, im[3] = {0.0, 0.0, 0.0};
         for (int comp = 0; comp < F.comps; ++comp) {
-            const double2 v = chunk_sum(F.part + d.part_off + ((int64_t)comp * n_dir + nn) * F.n_w + w, stride,
-                                        d.n_chunks);
+            const int64_t first = d.part_off + ((int64_t)comp * n_dir + nn) * F.n_w + w;
+            if (!RAD_DEBUG_OK(first >= 0 && first + (int64_t)(d.n_chunks - 1) * stride < F.part_len)) continue;
+            const double2 v = chunk_sum(F.part + first, stride, d.n_chunks);
             re[comp] = v.x;
             im[comp] = v.y;
         }
@@ -779,6 +824,34 @@ hipError_t launch_fin(const FinLaunch &F, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- descriptor upload
+// Copies `n` bytes carried in the kernel argument to device memory: descriptors reach
+// device memory without host staging buffers or a memcpy node.
+constexpr unsigned kUploadChunk = 3072;
+struct UploadChunk {
+    unsigned char b[kUploadChunk];
+};
+
+__global__ __launch_bounds__(256) void upload_kernel(unsigned char *__restrict__ dst, UploadChunk c, unsigned n)
+{
+    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.b[i];
+}
+
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    const unsigned char *s = (const unsigned char *)src;
+    for (size_t off = 0; off < bytes; off += kUploadChunk) {
+        const unsigned n = (unsigned)(bytes - off < kUploadChunk ? bytes - off : kUploadChunk);
+        UploadChunk c;
+        __builtin_memcpy(c.b, s + off, n);
+        hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, st, (unsigned char *)dst + off, c, n);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+
 hipError_t launch_phase(const double *turns, int64_t n, int mixed, double *c, double *s, hipStream_t st)
 {
     const int64_t want = (n + 255) / 256, blocks = want < 8192 ? want : 8192;
@@ -795,3 +868,21 @@ hipError_t launch_angle(const double *cube, const double *wx, const double *wy, 
 }
 
 }  // namespace rad
+
+extern "C" int64_t rad_debug_violations(int reset)
+{
+#if RAD_DEBUG
+    unsigned long long v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(rad::g_debug_violations), sizeof v, 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return -2;
+    if (reset) {
+        const unsigned long long z = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(rad::g_debug_violations), &z, sizeof z, 0, hipMemcpyHostToDevice) != hipSuccess)
+            return -2;
+    }
+    return (int64_t)v;
+#else
+    (void)reset;
+    return -1;
+#endif
+}

@@ -22,6 +22,7 @@
 
 #include "rad.h"
 #include "rad_internal.h"
+#include "rad_plan.h"
 
 namespace rad {
 hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, int grid_blocks,
@@ -75,6 +76,18 @@ rad_status hip_fail(hipError_t e, const char *what)
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kInitialStage = (size_t)1 << 20;   // pinned descriptor staging per grid
+
+// The int a C caller passed for a precision: read as bits through a reference, since
+// loading a C++ enum value outside the enumeration's range is undefined behaviour.
+int prec_value(const rad_precision &p)
+{
+    static_assert(sizeof(rad_precision) == sizeof(int), "rad_precision is an int");
+    int v = 0;
+    std::memcpy(&v, &p, sizeof v);
+    return v;
+}
+bool valid_prec(const rad_precision &p) { return prec_value(p) == RAD_FP64 || prec_value(p) == RAD_MIXED; }
 
 // ---- profiling
 std::mutex g_prof_mu;
@@ -112,87 +125,29 @@ int variant_for(bool persistent, bool mixed, bool withj)
     return g_variant[persistent ? 1 : 0][mixed ? 1 : 0][withj ? 1 : 0];
 }
 
-struct Tile {
-    int variant, wg, nt, n_tx, n_ty, n_groups, n_wblocks;
-    int64_t base_blocks;
-};
+using radplan::chunk_factor;
+using radplan::kMaxChunk;
+using radplan::kMinChunk;
+using radplan::kTargetBlocks;
+using radplan::Layout;
+using radplan::plan_chunks;
+using radplan::popcount3;
+using radplan::Tile;
+static_assert(radplan::kWave == kWave && radplan::kWavesPerBlock == kWavesPerBlock, "block shape");
+static_assert(radplan::kClassical == RAD_CLASSICAL && radplan::kSpin0 == RAD_SPIN0 &&
+              radplan::kSpinHalf == RAD_SPINHALF, "kind bits");
+static_assert(sizeof(double2) == 16, "complex FP64 partials");
 
 // Block shape for a grid and kernel variant; both integral sets of a call use
 // the same chunking, so the tile counts of the larger direction tile decide it.
 Tile plan_tile(const rad_grid *g, int variant)
 {
-    Tile t;
-    t.variant = variant;
-    t.wg = g->n_w > 128 ? 4 : (g->n_w > 64 ? 2 : 1);
-    t.nt = kWavesPerBlock / t.wg;
-    t.n_tx = (g->n_x + kVarTX[variant] - 1) / kVarTX[variant];
-    t.n_ty = (g->n_y + kVarTY[variant] - 1) / kVarTY[variant];
-    const int tiles = t.n_tx * t.n_ty;
-    t.n_groups = (tiles + t.nt - 1) / t.nt;
-    t.n_wblocks = (g->n_w + kWave * t.wg - 1) / (kWave * t.wg);
-    t.base_blocks = (int64_t)t.n_groups * t.n_wblocks;
-    return t;
+    return radplan::plan_tile(g->n_w, g->n_x, g->n_y, variant, kVarTX[variant], kVarTY[variant]);
 }
-
-constexpr int64_t kTargetBlocks = 2048;  // 256 CUs x 2 resident blocks x 4 rounds
-// Chunk lengths are multiples of kMinChunk samples.  A small problem (few direction
-// tiles and photon energies) is cut this fine so that its blocks, each a single
-// latency-bound wave per SIMD, stay short; fin_kernel sums the many partials with
-// sixteen loads in flight.
-constexpr int64_t kMinChunk = 16;
-
-// chunks per segment when the launch has `n_segs` segments
-int64_t chunk_factor(const Tile &t, int64_t n_segs)
-{
-    const int64_t have = n_segs * t.base_blocks;
-    if (have >= kTargetBlocks) return 1;
-    return (kTargetBlocks + have - 1) / have;
-}
-
-// Longest chunk: chunk lengths are 32-bit in the descriptors, while a segment may have
-// up to 2^40 samples (a multiple of kMinChunk).
-constexpr int64_t kMaxChunk = (int64_t)1 << 30;
-
-void plan_chunks(int64_t n, int64_t c, int32_t &n_chunks, int32_t &chunk_len)
-{
-    int64_t len = (n + c - 1) / c;
-    len = (len + kMinChunk - 1) / kMinChunk * kMinChunk;
-    len = std::min(std::min(len, n), kMaxChunk);
-    chunk_len = (int32_t)len;
-    n_chunks = (int32_t)((n + len - 1) / len);
-}
-
-int popcount3(int k) { return (k & 1) + ((k >> 1) & 1) + ((k >> 2) & 1); }
-
-struct Layout {
-    size_t off_counters, off_amp_c, off_amp_q, off_id_c, off_id_q, off_begin, off_list, off_part_c,
-        off_part_q;
-    size_t desc_bytes;  // bytes of the descriptor region (uploaded)
-    size_t total;
-    int comps_q;
-};
 
 Layout layout(const rad_grid *g, int n_segs, int n_out, int kinds, int64_t sum_chunks)
 {
-    Layout L{};
-    const size_t sd = sizeof(SegDesc) * (size_t)n_segs;
-    size_t o = 0;
-    L.off_counters = o; o = align_up(o + 2 * sizeof(unsigned));
-    L.off_amp_c = o; o = align_up(o + sd);
-    L.off_amp_q = o; o = align_up(o + sd);
-    L.off_id_c = o; o = align_up(o + sd);
-    L.off_id_q = o; o = align_up(o + sd);
-    L.off_begin = o; o = align_up(o + sizeof(int) * (size_t)(n_out + 1));
-    L.off_list = o; o = align_up(o + sizeof(int) * (size_t)n_segs);
-    L.desc_bytes = o;
-    const size_t cube2 = (size_t)g->n_w * g->n_x * g->n_y * sizeof(double2);
-    L.comps_q = (kinds & RAD_SPINHALF) ? 3 : 2;
-    L.off_part_c = o;
-    if (kinds & RAD_CLASSICAL) o = align_up(o + (size_t)sum_chunks * 2 * cube2);
-    L.off_part_q = o;
-    if (kinds & (RAD_SPIN0 | RAD_SPINHALF)) o = align_up(o + (size_t)sum_chunks * L.comps_q * cube2);
-    L.total = o;
-    return L;
+    return radplan::layout(g->n_w, g->n_x, g->n_y, sizeof(SegDesc), n_segs, n_out, kinds, sum_chunks);
 }
 
 rad_status check_grid(const rad_grid *g)
@@ -259,7 +214,7 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
     rad_status rs = check_grid(g);
     if (rs != RAD_OK) return rs;
     if (kinds <= 0 || kinds > 7) return fail(RAD_EINVAL, "kinds must be a non-empty subset of 1|2|4");
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    if (!valid_prec(prec)) return fail(RAD_EINVAL, "unknown precision %d", prec_value(prec));
     if (!segs || n_segs <= 0) return fail(RAD_EINVAL, "no segments");
     if (!out_index) return fail(RAD_EINVAL, "out_index is NULL");
     if (n_out <= 0) return fail(RAD_EINVAL, "n_out must be > 0");
@@ -442,6 +397,8 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
     char *wsb = P.ws;
     double2 *part_c = (double2 *)(wsb + P.lay.off_part_c);
     double2 *part_q = (double2 *)(wsb + P.lay.off_part_q);
+    const int64_t part_c_len = (int64_t)((P.lay.off_part_q - P.lay.off_part_c) / sizeof(double2));
+    const int64_t part_q_len = (int64_t)((P.lay.total - P.lay.off_part_q) / sizeof(double2));
     unsigned *counters = (unsigned *)(wsb + P.lay.off_counters);
 
     AmpLaunch L{};
@@ -469,6 +426,7 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
         L.quantum = 0;
         L.comps = 2;
         L.part = part_c;
+        L.part_len = part_c_len;
         L.counter = counters;
         hipError_t e = launch_amp(L, P.tile_c.variant, false, P.mixed, P.persistent ? P.pgrid_c : 0, st, nullptr);
         if (e != hipSuccess) return hip_fail(e, "amplitude kernel launch");
@@ -479,6 +437,7 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
         L.quantum = 1;
         L.comps = P.lay.comps_q;
         L.part = part_q;
+        L.part_len = part_q_len;
         L.counter = counters + 1;
         hipError_t e = launch_amp(L, P.tile_q.variant, P.lay.comps_q == 3, P.mixed,
                                   P.persistent ? P.pgrid_q : 0, st, nullptr);
@@ -497,6 +456,8 @@ rad_status plan_launch(const Plan &P, double *out, hipStream_t st, bool profile)
     F.qs = (const SegDesc *)(wsb + P.lay.off_id_q);
     F.part_c = part_c;
     F.part_q = part_q;
+    F.part_c_len = part_c_len;
+    F.part_q_len = part_q_len;
     F.comps_q = P.lay.comps_q;
     F.hw = g->d_hw;
     F.thx = g->d_thx;
@@ -544,7 +505,7 @@ size_t workspace_for(const rad_grid *g, const std::vector<int64_t> &ns, int n_ou
     int64_t sum = 0;
     for (int64_t n : ns) {
         if (bound) {
-            sum += std::min<int64_t>(cf, (n + kMinChunk - 1) / kMinChunk);
+            sum += radplan::max_chunks(n, cf);   // the most any n' <= n gets
         } else {
             int32_t c, l;
             plan_chunks(n, cf, c, l);
@@ -596,7 +557,12 @@ extern "C" {
 
 const char *rad_status_string(rad_status s)
 {
-    switch (s) {
+    // a C caller may pass any int: read the bits, since a C++ enum value outside the
+    // enumeration's range is undefined behaviour
+    int v = 0;
+    static_assert(sizeof(rad_status) == sizeof(int), "rad_status is an int");
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
     case RAD_OK: return "ok";
     case RAD_EINVAL: return "invalid argument";
     case RAD_ENOMEM: return "out of memory / workspace too small";
@@ -658,6 +624,15 @@ rad_status rad_setup_grid(const double *hw_eV, int n_w, const double *thx, int n
         rad_free_grid(g);
         return hip_fail(e, "grid upload");
     }
+    // pinned staging for the descriptor uploads of compute calls, allocated here so that
+    // a call whose descriptors fit (about 1000 segments) allocates nothing
+    e = hipHostMalloc(&g->stage, kInitialStage, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        g->stage = nullptr;
+        rad_free_grid(g);
+        return fail(RAD_ENOMEM, "pinned staging of %zu bytes", kInitialStage);
+    }
+    g->stage_bytes = kInitialStage;
     *out = g;
     return RAD_OK;
 }
@@ -692,7 +667,7 @@ rad_status rad_grid_step(const rad_grid *g, double *dth)
 size_t rad_workspace_bytes(const rad_grid *g, int64_t max_n, int kinds, rad_precision prec)
 {
     if (!g || max_n < 2 || kinds <= 0 || kinds > 7) return 0;
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    if (!valid_prec(prec)) return 0;
     return workspace_for(g, {max_n}, 1, kinds, true);
 }
 
@@ -700,7 +675,7 @@ size_t rad_batch_workspace_bytes(const rad_grid *g, const rad_segment *segs, int
                                  int kinds, rad_precision prec)
 {
     if (!g || !segs || n_segs <= 0 || n_out <= 0 || kinds <= 0 || kinds > 7) return 0;
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    if (!valid_prec(prec)) return 0;
     std::vector<int64_t> ns(n_segs);
     for (int s = 0; s < n_segs; ++s) {
         if (segs[s].n < 2) return 0;
@@ -738,7 +713,7 @@ rad_status rad_batch(const rad_grid *g, const rad_segment *segs, int n_segs, con
 rad_status rad_phase_factors(const double *turns, int64_t n, rad_precision prec, double *c, double *s,
                              void *stream)
 {
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    if (!valid_prec(prec)) return fail(RAD_EINVAL, "unknown precision %d", prec_value(prec));
     if (n < 0 || n > ((int64_t)1 << 40)) return fail(RAD_EINVAL, "n = %lld outside [0, 2^40]", (long long)n);
     if (n == 0) return RAD_OK;
     const size_t bytes = (size_t)n * sizeof(double);
@@ -1012,7 +987,7 @@ extern "C" {
 size_t rad_cells_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int kind,
                                  rad_precision prec, int cx, int cy, const uint8_t *mask)
 {
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return 0;
+    if (!valid_prec(prec)) return 0;
     CellsPlan C;
     if (cells_plan(g, segs, n_segs, kind, cx, cy, mask, false, C, kind == RAD_SPINHALF ? 3 : 2) != RAD_OK)
         return 0;
@@ -1026,7 +1001,7 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     rad_grid *g = const_cast<rad_grid *>(grid);
     rad_status rs = check_grid(g);
     if (rs != RAD_OK) return rs;
-    if (prec != RAD_FP64 && prec != RAD_MIXED) return fail(RAD_EINVAL, "unknown precision %d", (int)prec);
+    if (!valid_prec(prec)) return fail(RAD_EINVAL, "unknown precision %d", prec_value(prec));
     const bool quantum = kind != RAD_CLASSICAL;
     for (int s = 0; s < n_segs && segs; ++s) {
         rs = check_segment(&segs[s], s, quantum);
@@ -1064,6 +1039,7 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
         L.rec = g->dth != 0.0 ? 1 : 0;
         L.comps = comps;
         L.part = part;
+        L.part_len = (int64_t)((C.total - C.off_part) / sizeof(double2));
         L.counter = nullptr;
         const bool mixed = prec == RAD_MIXED;
         const bool prof = profiling_on();
@@ -1086,6 +1062,7 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     F.psof = (const int *)(wsb + C.off_psof);
     F.mask = (const uint8_t *)(wsb + C.off_mask);
     F.part = part;
+    F.part_len = (int64_t)((C.total - C.off_part) / sizeof(double2));
     F.comps = comps;
     F.kind = kind;
     F.wx = g->d_wx;

@@ -35,20 +35,42 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
         const bool a = S.vx[k] >= 0.0, b = S.vx[k + 1] >= 0.0;
         cnt += (a != b);
     }
-    double m[4] = {0.0, 0.0, 0.0, 0.0};   // sums of vx, vy, vx^2, vy^2
+    double m[2] = {0.0, 0.0};   // sums of vx, vy
     for (int64_t k = tid; k < n; k += 256) {
         xmn = fmin(xmn, S.x[k]);
         xmx = fmax(xmx, S.x[k]);
-        const double vx = S.vx[k], vy = S.vy[k];
-        m[0] += vx;
-        m[1] += vy;
-        m[2] += vx * vx;
-        m[3] += vy * vy;
+        m[0] += S.vx[k];
+        m[1] += S.vy[k];
     }
     s_cnt[tid] = cnt;
     s_min[tid] = xmn;
     s_max[tid] = xmx;
-    for (int j = 0; j < 4; ++j) s_mom[j][tid] = m[j];
+    for (int j = 0; j < 2; ++j) s_mom[j][tid] = m[j];
+    __syncthreads();
+    // means first, then the spreads about them (two passes: no cancellation when the
+    // spread is small beside the mean)
+    if (tid < 2) {
+        double t = 0.0;
+        for (int i = 0; i < 256; ++i) t += s_mom[tid][i];
+        s_mom[tid + 2][0] = t / (double)n;
+    }
+    __syncthreads();
+    {
+        const double mx = s_mom[2][0], my = s_mom[3][0];
+        double q[2] = {0.0, 0.0};
+        for (int64_t k = tid; k < n; k += 256) {
+            const double dx = S.vx[k] - mx, dy = S.vy[k] - my;
+            q[0] += dx * dx;
+            q[1] += dy * dy;
+        }
+        __syncthreads();   // the means are read before the slots are reused
+        s_mom[0][tid] = q[0];
+        s_mom[1][tid] = q[1];
+        if (tid == 0) {
+            s_mom[2][1] = mx;
+            s_mom[3][1] = my;
+        }
+    }
     __syncthreads();
     // exclusive prefix of the counts (in chunk order = time order), extrema, moments
     if (tid == 0) {
@@ -65,10 +87,10 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
         }
         s_min[0] = a;
         s_max[0] = b;
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             double t = 0.0;
             for (int i = 0; i < 256; ++i) t += s_mom[j][i];
-            s_mom[j][0] = t;
+            s_mom[j][0] = t;   // sums of squared deviations
         }
     }
     __syncthreads();
@@ -106,8 +128,8 @@ __global__ __launch_bounds__(256) void features_kernel(FeatLaunch F)
     const double span = S.t[n - 1] - S.t[0];
     const double w_osc = span > 0.0 ? kPi * (double)total / span : 0.0;
     f[1 + kHistBins] = (float)log(fmax(w_osc, 1.0) / 1e5);
-    const double mx = s_mom[0][0] / (double)n, my = s_mom[1][0] / (double)n;
-    const double vxx = fmax(s_mom[2][0] / (double)n - mx * mx, 0.0), vyy = fmax(s_mom[3][0] / (double)n - my * my, 0.0);
+    const double mx = s_mom[2][1], my = s_mom[3][1];
+    const double vxx = s_mom[0][0] / (double)n, vyy = s_mom[1][0] / (double)n;
     f[2 + kHistBins] = (float)(S.gamma * mx);
     f[3 + kHistBins] = (float)(S.gamma * my);
     f[4 + kHistBins] = (float)(S.gamma * sqrt(vxx));
@@ -254,11 +276,15 @@ __global__ __launch_bounds__(256) void widen_kernel(uint8_t *mask, int n_traj, i
 // ---------------------------------------------------------------- combine
 // dI/dhw[traj][w] = sum_c (mask ? exact cell integral : estimate), the estimate
 // being the predicted cell mass when cell_pred is given, else the coarse centre
-// value times the cell's area.
+// value times the cell's area; an energy that fell back takes the full-grid value.
 __global__ __launch_bounds__(256) void combine_kernel(CombineLaunch L)
 {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= (int64_t)L.n_traj * L.n_w) return;
+    if (L.fallback && L.fallback[item]) {
+        L.out[item] = L.full[item];
+        return;
+    }
     const int ncx = L.n_x / L.cx;
     double acc = 0.0;
     for (int c = 0; c < L.n_cells; ++c) {
@@ -276,6 +302,122 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineLaunch L)
         }
     }
     L.out[item] = acc;
+}
+
+// ---------------------------------------------------------------- training data
+// y[m][d] = log(S+ / max_d S+ + floor) with S+ = max(S, 0): one block per map, the maximum
+// over its directions by a fixed LDS tree, then the transform (FP64, stored as FP32).
+__global__ __launch_bounds__(256) void targets_kernel(const double *__restrict__ S, int n_dirs, float floor_rel,
+                                                      float *__restrict__ y)
+{
+    __shared__ double red[256];
+    const double *s = S + (int64_t)blockIdx.x * n_dirs;
+    double mx = 0.0;
+    for (int d = threadIdx.x; d < n_dirs; d += 256) mx = fmax(mx, s[d]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const double peak = fmax(red[0], 1e-300);
+    float *out = y + (int64_t)blockIdx.x * n_dirs;
+    for (int d = threadIdx.x; d < n_dirs; d += 256) out[d] = (float)log(fmax(s[d], 0.0) / peak + (double)floor_rel);
+}
+
+// Mean and standard deviation of n values in FP64, two passes (mean, then squared
+// deviations), each a fixed-order sum: `parts` blocks of 256 strided partial sums, then
+// one block adds the parts.  mode 0: sums of y; mode 1: sums of (y - mean)^2.
+__global__ __launch_bounds__(256) void moments_kernel(const float *__restrict__ y, int64_t n, int mode,
+                                                      const double *__restrict__ mean, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const double m = mode ? mean[0] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = (double)y[i] - m;
+        acc += mode ? v * v : v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void moments_finish(const double *__restrict__ part, int parts, int64_t n, int mode,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < parts; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[mode] = mode ? sqrt(red[0] / (double)n) : red[0] / (double)n;
+}
+
+// splitmix64 (Steele, Lea and Flood, 2014) of a counter: draw i of step `step`
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Minibatch point b: a map (trajectory t, its energy slot e) and a direction p drawn
+// uniformly, the point inputs of (energy W[t][e], direction p) and the standardised
+// target (Y - mean) / std.  Draws are counter-based, so batch `step` is reproducible.
+__global__ __launch_bounds__(256) void minibatch_kernel(BatchLaunch L)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= L.batch) return;
+    const uint64_t base = mix64(L.seed ^ mix64(L.step)) + 3ull * (uint64_t)b;
+    const uint64_t r0 = mix64(base), r1 = mix64(base + 1), r2 = mix64(base + 2);
+    const int64_t t = (int64_t)((r0 >> 11) % (uint64_t)L.n);
+    const int e = (int)((r1 >> 11) % (uint64_t)L.nwt);
+    const int p = (int)((r2 >> 11) % (uint64_t)L.npix);
+    // an energy index outside the table is clamped into it (the host cannot see W)
+    const int64_t n_energy = L.n_points / L.npix;
+    int64_t we = L.W[t * L.nwt + e];
+    we = we < 0 ? 0 : (we >= n_energy ? n_energy - 1 : we);
+    const int64_t pt = we * L.npix + p;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L.x[(int64_t)b * 3 + j] = L.point_x[pt * 3 + j];
+    L.traj[b] = (int)t;
+    const float v = L.Y[(t * L.nwt + e) * (int64_t)L.npix + p];
+    L.target[b] = (float)(((double)v - L.moments[0]) / L.moments[1]);
+}
+
+hipError_t launch_targets(const double *S, int64_t n_maps, int n_dirs, float floor_rel, float *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(targets_kernel, dim3((unsigned)n_maps), dim3(256), 0, st, S, n_dirs, floor_rel, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const float *y, int64_t n, double *part, int parts, double *out, hipStream_t st)
+{
+    for (int mode = 0; mode < 2; ++mode) {
+        hipLaunchKernelGGL(moments_kernel, dim3((unsigned)parts), dim3(256), 0, st, y, n, mode, out, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(moments_finish, dim3(1), dim3(256), 0, st, part, parts, n, mode, out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_minibatch(const BatchLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(minibatch_kernel, dim3((unsigned)((L.batch + 255) / 256)), dim3(256), 0, st, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_features(const FeatLaunch &F, int n_segs, hipStream_t st)

@@ -12,6 +12,10 @@
 
 using namespace radsmp;
 
+namespace rad {
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+}
+
 static_assert(sizeof(FeatSeg) == 48, "rad_features documents 48 workspace bytes per segment");
 
 namespace {
@@ -86,10 +90,11 @@ rad_status rad_features(const rad_segment *segs, int n_segs, double plane_spacin
         h[s] = FeatSeg{sg.t, sg.x, sg.vx, sg.vy, sg.n, sg.gamma};
     }
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(ws, h.data(), need, hipMemcpyHostToDevice, st);
+    // the descriptors travel as kernel arguments: no host buffer has to outlive the call,
+    // so nothing waits for the stream
+    hipError_t e = rad::launch_upload(ws, h.data(), need, st);
     FeatLaunch F{(const FeatSeg *)ws, plane_spacing_m, feat};
     if (e == hipSuccess) e = launch_features(F, n_segs, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vector goes out of scope
     if (e != hipSuccess) return sfail(RAD_EDEVICE, "features: %s", hipGetErrorString(e));
     return RAD_OK;
 }
@@ -145,8 +150,8 @@ rad_status rad_sampler_select_error(const rad_grid *fine, int n_traj, const floa
 }
 
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
-                               const uint8_t *mask, const double *coarse, const double *cell_pred, double *dIdw,
-                               void *stream)
+                               const uint8_t *mask, const double *coarse, const double *cell_pred,
+                               const uint8_t *fallback, const double *full, double *dIdw, void *stream)
 {
     rad::GridView v;
     rad_status rs = view_of(fine, v);
@@ -160,9 +165,63 @@ rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy,
     if ((rs = srange(mask, items * n_cells, "mask")) != RAD_OK) return rs;
     if ((rs = srange(dIdw, items * sizeof(double), "dIdw")) != RAD_OK) return rs;
     if (cell_pred && (rs = srange(cell_pred, items * n_cells * sizeof(double), "cell_pred")) != RAD_OK) return rs;
-    CombineLaunch L{cells, coarse, v.wx, v.wy, cell_pred, mask, n_traj, v.n_w, v.n_x, cx, cy, n_cells, dIdw};
+    if ((fallback == nullptr) != (full == nullptr)) return sfail(RAD_EINVAL, "fallback and full go together");
+    if (fallback && ((rs = srange(fallback, items, "fallback")) != RAD_OK ||
+                     (rs = srange(full, items * sizeof(double), "full")) != RAD_OK))
+        return rs;
+    CombineLaunch L{cells, coarse, v.wx, v.wy, cell_pred, mask, fallback, full, n_traj, v.n_w, v.n_x, cx, cy,
+                    n_cells, dIdw};
     hipError_t e = launch_combine(L, (hipStream_t)stream);
     return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "combine: %s", hipGetErrorString(e));
+}
+
+rad_status rad_sampler_targets(const double *S, int64_t n_maps, int n_dirs, float floor_rel, float *y, void *stream)
+{
+    if (n_maps <= 0 || n_maps > ((int64_t)1 << 31) - 1 || n_dirs <= 0 || !(floor_rel > 0.0f) || !std::isfinite(floor_rel))
+        return sfail(RAD_EINVAL, "need n_maps in [1, 2^31), n_dirs >= 1 and a finite floor_rel > 0");
+    rad_status rs;
+    const size_t n = (size_t)n_maps * n_dirs;
+    if ((rs = srange(S, n * sizeof(double), "S")) != RAD_OK || (rs = srange(y, n * sizeof(float), "y")) != RAD_OK)
+        return rs;
+    hipError_t e = launch_targets(S, n_maps, n_dirs, floor_rel, y, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "targets: %s", hipGetErrorString(e));
+}
+
+size_t rad_sampler_moments_workspace_bytes(void) { return (size_t)kMomentParts * sizeof(double); }
+
+rad_status rad_sampler_moments(const float *y, int64_t n, double *moments, void *ws, size_t ws_bytes, void *stream)
+{
+    if (n <= 0) return sfail(RAD_EINVAL, "n must be > 0");
+    if (ws_bytes < rad_sampler_moments_workspace_bytes())
+        return sfail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, rad_sampler_moments_workspace_bytes());
+    rad_status rs;
+    if ((rs = srange(y, (size_t)n * sizeof(float), "y")) != RAD_OK ||
+        (rs = srange(moments, 2 * sizeof(double), "moments")) != RAD_OK ||
+        (rs = srange(ws, rad_sampler_moments_workspace_bytes(), "workspace")) != RAD_OK)
+        return rs;
+    hipError_t e = launch_moments(y, n, (double *)ws, kMomentParts, moments, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "moments: %s", hipGetErrorString(e));
+}
+
+rad_status rad_sampler_minibatch(const float *Y, const int *W, int64_t n, int nwt, int npix, const float *point_x,
+                                 int64_t n_points, const double *moments, int batch, uint64_t seed, uint64_t step,
+                                 int *traj, float *x, float *target, void *stream)
+{
+    if (n <= 0 || n > ((int64_t)1 << 31) - 1 || nwt <= 0 || npix <= 0 || batch <= 0 || n_points <= 0)
+        return sfail(RAD_EINVAL, "need n in [1, 2^31), nwt, npix, batch, n_points >= 1");
+    rad_status rs;
+    if ((rs = srange(Y, (size_t)n * nwt * npix * sizeof(float), "Y")) != RAD_OK ||
+        (rs = srange(W, (size_t)n * nwt * sizeof(int), "W")) != RAD_OK ||
+        (rs = srange(point_x, (size_t)n_points * 3 * sizeof(float), "point_x")) != RAD_OK ||
+        (rs = srange(moments, 2 * sizeof(double), "moments")) != RAD_OK ||
+        (rs = srange(traj, (size_t)batch * sizeof(int), "traj")) != RAD_OK ||
+        (rs = srange(x, (size_t)batch * 3 * sizeof(float), "x")) != RAD_OK ||
+        (rs = srange(target, (size_t)batch * sizeof(float), "target")) != RAD_OK)
+        return rs;
+    if (n_points % npix) return sfail(RAD_EINVAL, "the point table is not whole energies of npix directions");
+    BatchLaunch L{Y, W, point_x, n_points, n, nwt, npix, moments, batch, seed, step, traj, x, target};
+    hipError_t e = launch_minibatch(L, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "minibatch: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -142,10 +142,11 @@ class MLP:
                                        float(beta2), float(eps), rad._stream(stream)), "rad_mlp_adam")
 
     def train_step(self, feat, traj, x, target, lr, **adam_kw):
-        """grad + Adam; returns the batch's mean squared error as a device tensor."""
+        """grad + Adam; returns the batch's summed squared error (a device tensor [1]; the
+        mean is that over the batch size)."""
         g, ls = self.grad(feat, traj, x, target)
         self.adam(g, lr, **adam_kw)
-        return ls / x.shape[0]
+        return ls
 
     def forward(self, feat, traj, x, y=None, stream=None):
         """Inference (trajectory features folded into a per-trajectory bias)."""

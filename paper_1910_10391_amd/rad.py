@@ -13,7 +13,8 @@ import threading
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "librad.so")
+# RAD_LIBRARY: another build of the same library (the host-sanitizer build in the CPU tests)
+LIB_PATH = os.environ.get("RAD_LIBRARY") or os.path.join(_PKG, "librad.so")
 
 CLASSICAL, SPIN0, SPINHALF = 1, 2, 4
 FP64, MIXED = 0, 1
@@ -41,45 +42,53 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB_PATH):
-                raise RuntimeError("librad.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
-            L = ctypes.CDLL(LIB_PATH)
-            P, D, I, I64, S = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
-                               ctypes.c_int64, ctypes.c_size_t)
-            SP = ctypes.POINTER(Segment)
-            sig = {
-                "rad_setup_grid": (I, [D, I, D, I, D, I, P, ctypes.POINTER(P)]),
-                "rad_free_grid": (None, [P]),
-                "rad_grid_dims": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
-                "rad_grid_step": (I, [P, D]),
-                "rad_workspace_bytes": (S, [P, I64, I, I]),
-                "rad_batch_workspace_bytes": (S, [P, SP, I, I, I, I]),
-                "rad_classical": (I, [P, SP, I, P, P, S, P]),
-                "rad_quantum": (I, [P, SP, I, I, P, P, S, P]),
-                "rad_batch": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, P, S, P]),
-                "rad_angle_integrate": (I, [P, P, I, P, P]),
-                "rad_phase_factors": (I, [P, I64, I, P, P, P]),
-                "rad_status_string": (ctypes.c_char_p, [I]),
-                "rad_last_error": (ctypes.c_char_p, []),
-                "rad_tune_set_variant": (I, [I, I, I, I]),
-                "rad_tune_get_variant": (I, [I, I, I, ctypes.POINTER(I)]),
-                "rad_plan_create": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, S, P,
-                                        ctypes.POINTER(P)]),
-                "rad_plan_launch": (I, [P, P, P]),
-                "rad_plan_launch_graph": (I, [P, P, P]),
-                "rad_plan_free": (None, [P]),
-                "rad_cells_workspace_bytes": (S, [P, SP, I, I, I, I, I, P]),
-                "rad_cells": (I, [P, SP, I, I, I, I, I, P, P, P, S, P]),
-                "rad_tune_num_variants": (I, []),
-                "rad_profile_enable": (I, [I]),
-                "rad_profile_read": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]),
-            }
-            for name, (res, args) in sig.items():
-                fn = getattr(L, name)
-                fn.restype = res
-                fn.argtypes = args
-            _lib = L
+            _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path):
+    """A build of librad at `path` with the C signatures declared (lib() loads the default
+    one; the debug build's test loads librad_debug.so beside it)."""
+    if not os.path.exists(path):
+        raise RuntimeError("librad is not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    P, D, I, I64, S = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                       ctypes.c_int64, ctypes.c_size_t)
+    SP = ctypes.POINTER(Segment)
+    sig = {
+        "rad_setup_grid": (I, [D, I, D, I, D, I, P, ctypes.POINTER(P)]),
+        "rad_free_grid": (None, [P]),
+        "rad_grid_dims": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "rad_grid_step": (I, [P, D]),
+        "rad_workspace_bytes": (S, [P, I64, I, I]),
+        "rad_batch_workspace_bytes": (S, [P, SP, I, I, I, I]),
+        "rad_classical": (I, [P, SP, I, P, P, S, P]),
+        "rad_quantum": (I, [P, SP, I, I, P, P, S, P]),
+        "rad_batch": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, P, S, P]),
+        "rad_angle_integrate": (I, [P, P, I, P, P]),
+        "rad_phase_factors": (I, [P, I64, I, P, P, P]),
+        "rad_status_string": (ctypes.c_char_p, [I]),
+        "rad_last_error": (ctypes.c_char_p, []),
+        "rad_tune_set_variant": (I, [I, I, I, I]),
+        "rad_tune_get_variant": (I, [I, I, I, ctypes.POINTER(I)]),
+        "rad_plan_create": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, S, P,
+                                ctypes.POINTER(P)]),
+        "rad_plan_launch": (I, [P, P, P]),
+        "rad_plan_launch_graph": (I, [P, P, P]),
+        "rad_plan_free": (None, [P]),
+        "rad_cells_workspace_bytes": (S, [P, SP, I, I, I, I, I, P]),
+        "rad_cells": (I, [P, SP, I, I, I, I, I, P, P, P, S, P]),
+        "rad_tune_num_variants": (I, []),
+        "rad_profile_enable": (I, [I]),
+        "rad_profile_read": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]),
+        "rad_peak": (I, [I, I64, P, I64, D, P]),
+        "rad_debug_violations": (I64, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
 
 
 def _check(status, what):
@@ -175,6 +184,15 @@ class DeviceSegments:
 
     def __len__(self):
         return len(self.structs)
+
+    def subset(self, rows):
+        """The segments `rows` (in that order), sharing this object's device columns."""
+        view = DeviceSegments.__new__(DeviceSegments)
+        rows = [int(r) for r in rows]
+        view.n = [self.n[r] for r in rows]
+        view.data = self.data
+        view.structs = (Segment * len(rows))(*[self.structs[r] for r in rows])
+        return view
 
 
 def _as_segments(segs):
@@ -400,3 +418,28 @@ def profile_read(reset=False):
     _check(lib().rad_profile_read(ctypes.byref(ms), ctypes.byref(n), int(bool(reset))),
            "rad_profile_read")
     return ms.value, n.value
+
+
+PEAK_FMA64, PEAK_FMA32, PEAK_SINCOS32, PEAK_PHASE64, PEAK_PHASE_MIXED = range(5)
+
+
+def peak(which, iters=4096, n_threads=256 * 256 * 8, reps=3, stream=None):
+    """Issue-rate microbenchmark (rad_peak): (operations per second, operations per
+    launch, ms per launch), the best of `reps` timed launches after one warm-up, timed
+    with events on the launch stream."""
+    import torch
+    out = torch.empty(int(n_threads), dtype=torch.float64, device="cuda")
+    ops = ctypes.c_double()
+    st = torch.cuda.current_stream() if stream is None else stream
+    best = None
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        _check(lib().rad_peak(int(which), int(iters), _dptr(out), int(n_threads), ctypes.byref(ops),
+                              ctypes.c_void_p(st.cuda_stream)), "rad_peak")
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        if r > 0 and (best is None or ms < best):
+            best = ms
+    return ops.value / (best * 1e-3), ops.value, best

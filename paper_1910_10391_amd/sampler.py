@@ -52,7 +52,12 @@ def _lib():
             "rad_features": (I, [ctypes.POINTER(rad.Segment), I, D, P, P, S, P]),
             "rad_sampler_select": (I, [P, I, P, F, F, P, I, I, F, I, F, P, P, P, P]),
             "rad_sampler_select_error": (I, [P, I, P, F, F, P, I, I, F, I, P, P, P]),
-            "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P, P]),
+            "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P, P, P, P]),
+            "rad_sampler_targets": (I, [P, ctypes.c_int64, I, F, P, P]),
+            "rad_sampler_moments_workspace_bytes": (S, []),
+            "rad_sampler_moments": (I, [P, ctypes.c_int64, P, P, S, P]),
+            "rad_sampler_minibatch": (I, [P, P, ctypes.c_int64, I, I, P, ctypes.c_int64, P, I, ctypes.c_uint64,
+                                          ctypes.c_uint64, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -171,15 +176,17 @@ class Sampler:
             "rad_sampler_select_error")
         return mask, est
 
-    def combine(self, cells, mask, coarse, cell_pred=None):
-        """dI/dhw: exact cells where selected, else cell_pred (if given) or centre x area."""
+    def combine(self, cells, mask, coarse, cell_pred=None, fallback=None, full=None):
+        """dI/dhw: exact cells where selected, else cell_pred (if given) or centre x area;
+        where `fallback` is set, the full-grid value `full`."""
         import torch
         n = cells.shape[0]
         out = torch.empty((n, self.grids.hw.size), dtype=torch.float64, device="cuda")
+        opt = lambda t: None if t is None else rad._dptr(t)   # noqa: E731
         rad._check(_lib().rad_sampler_combine(self.grids.fine.handle, n, CELL, CELL, rad._dptr(cells),
-                                              rad._dptr(mask), rad._dptr(coarse),
-                                              None if cell_pred is None else rad._dptr(cell_pred), rad._dptr(out),
-                                              rad._stream(None)), "rad_sampler_combine")
+                                              rad._dptr(mask), rad._dptr(coarse), opt(cell_pred), opt(fallback),
+                                              opt(full), rad._dptr(out), rad._stream(None)),
+                   "rad_sampler_combine")
         return out
 
     def estimate(self, dsegs, precision=rad.MIXED, rule="learned"):
@@ -224,30 +231,51 @@ class Sampler:
         else:
             raise ValueError("rule must be 'learned' or 'coarse'")
         mask_h = mask.cpu().numpy()
+        fb_h = fb.cpu().numpy()
         t = mark("select", t)
-        cells = rad.cells(g.fine, dsegs, KIND, mask_h, precision)
-        t = mark("cells", t)
-        dIdw = self.combine(cells, mask, coarse, fill)
-        mark("combine", t)
-        dt = time.perf_counter() - t0
+        # energies that fell back take the full-grid value itself: the trajectories that
+        # have any run through the full-grid path (the same call as full_grid for the same
+        # segments), and their cells are not integrated
         n_t = np.array(dsegs.n, dtype=np.float64)
         n_w = g.hw.size
+        full = None
+        fb_rows = np.flatnonzero(fb_h.any(axis=1))
+        evals_fb = 0.0
+        if fb_rows.size:
+            mask_h[fb_h > 0] = 0
+            sub = dsegs if fb_rows.size == len(dsegs) else dsegs.subset(fb_rows)
+            full_sub, _ = self.full_grid(sub, precision, sync=False)
+            if fb_rows.size == len(dsegs):
+                full = full_sub
+            else:
+                full = torch.zeros((len(dsegs), n_w), dtype=torch.float64, device="cuda")
+                full.index_copy_(0, torch.from_numpy(fb_rows).cuda(), full_sub)
+            fb = fb if fb.is_cuda else fb.cuda()
+            evals_fb = float(np.sum(n_t[fb_rows]) * n_w * g.n ** 2)
+            t = mark("fallback", t)
+        cells = rad.cells(g.fine, dsegs, KIND, mask_h, precision)
+        t = mark("cells", t)
+        dIdw = self.combine(cells, mask, coarse, fill, fb if full is not None else None, full)
+        mark("combine", t)
+        dt = time.perf_counter() - t0
         # evaluations: coarse centres + every direction of the refined cells (the selection
-        # covers whole 64-energy blocks, and rad_cells evaluates exactly those)
+        # covers whole 64-energy blocks, and rad_cells evaluates exactly those) + the full
+        # grid of trajectories with a fallback
         evals_refine = float(np.sum(n_t * mask_h.reshape(len(dsegs), -1).sum(axis=1)) * CELL * CELL)
         evals_coarse = float(np.sum(n_t) * n_w * g.n_cells)
-        return dict(dIdw=dIdw, mask=mask_h, fallback=fb.cpu().numpy(), seconds=dt, phases=phases,
-                    evals=evals_coarse + evals_refine, evals_full=float(np.sum(n_t) * n_w * g.n ** 2),
+        return dict(dIdw=dIdw, mask=mask_h, fallback=fb_h, seconds=dt, phases=phases,
+                    evals=evals_coarse + evals_refine + evals_fb, evals_full=float(np.sum(n_t) * n_w * g.n ** 2),
                     refined_cells_mean=float(mask_h.sum(axis=2).mean()))
 
-    def full_grid(self, dsegs, precision=rad.MIXED):
+    def full_grid(self, dsegs, precision=rad.MIXED, sync=True):
         """Reference: the exact angle integral over the whole fine grid."""
         import torch
         t0 = time.perf_counter()
         n = len(dsegs)
         cube = rad.batch(self.grids.fine, dsegs, list(range(n)), n, KIND, precision)
         dIdw = rad.angle_integrate(self.grids.fine, cube[:, 0].contiguous())
-        torch.cuda.synchronize()
+        if sync:
+            torch.cuda.synchronize()
         return dIdw, time.perf_counter() - t0
 
     def save(self, path):
@@ -271,15 +299,51 @@ class Sampler:
 
 
 # ---------------------------------------------------------------- training
+def _cache_key(cfg, n_traj, grids, n_w_train, precision, first, floor_rel):
+    """Everything a training set depends on, as one string (stored with the cache)."""
+    import dataclasses
+    import hashlib
+    h = hashlib.sha256()
+    for a in (grids.hw, np.asarray(grids.fine.thx), np.asarray(grids.fine.thy)):
+        h.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    fields = sorted(dataclasses.asdict(cfg).items())
+    return repr((fields, int(n_traj), int(n_w_train), int(precision), int(first), float(floor_rel), h.hexdigest()))
+
+
 def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64, first=0, floor_rel=1e-3,
-                 verbose=False):
+                 verbose=False, cache=None):
     """Spectra produced by the method itself: for each trajectory, n_w_train of the grid's
     photon energies (every k-th, offset by the trajectory index so that all energies are
     covered) on the full fine grid.  Returns features [N, 38], the point-table index of each
     energy [N, n_w_train] and, as the target, the angular shape of each map,
     log(S / max S + floor_rel) with the maximum over the map's directions
     [N, n_w_train, n, n] (float32); the scale comes from the exact centre values when
-    cells are selected."""
+    cells are selected.
+
+    cache: a file path (.npz).  When it holds a training set made with the same
+    arguments (generator settings, trajectories, grid, precision) that set is loaded
+    instead of recomputed; otherwise the new set is written there."""
+    import torch
+    key = _cache_key(cfg, n_traj, grids, n_w_train, precision, first, floor_rel) if cache else None
+    if cache:
+        import os
+        if os.path.exists(cache):
+            with np.load(cache, allow_pickle=False) as z:
+                if str(z["key"]) == key:
+                    if verbose:
+                        print("training set: loaded from %s" % cache, flush=True)
+                    return (torch.from_numpy(z["feat"]).cuda(), torch.from_numpy(z["W"]).cuda(),
+                            torch.from_numpy(z["Y"]).cuda())
+    feat, W, Y = _training_set(cfg, n_traj, grids, n_w_train, precision, chunk, first, floor_rel, verbose)
+    if cache:
+        import os
+        tmp = cache + ".tmp%d.npz" % os.getpid()
+        np.savez(tmp, key=np.array(key), feat=feat.cpu().numpy(), W=W.cpu().numpy(), Y=Y.cpu().numpy())
+        os.replace(tmp, cache)
+    return feat, W, Y
+
+
+def _training_set(cfg, n_traj, grids, n_w_train, precision, chunk, first, floor_rel, verbose):
     import torch
     from .synth import channeling
     n_w = grids.hw.size
@@ -300,14 +364,11 @@ def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64
             if off not in grid_cache:
                 grid_cache[off] = rad.Grid(grids.hw[iw], grids.fine.thx, grids.fine.thy)
             sub = rad.DeviceSegments([segs[i] for i in members])
-            cube = rad.batch(grid_cache[off], sub, list(range(len(members))), len(members), KIND,
-                             precision)[:, 0].float()
-            S = cube.clamp_min(0)
-            peak = S.amax(dim=(2, 3), keepdim=True).clamp_min(1e-300)
-            y = torch.log(S / peak + floor_rel)
+            cube = rad.batch(grid_cache[off], sub, list(range(len(members))), len(members), KIND, precision)
+            y = targets_of(cube, floor_rel).view(len(members), iw.size, grids.n, grids.n)
             for j, i in enumerate(members):
                 targets.append((c0 + i, y[j]))
-                tw.append((c0 + i, torch.from_numpy(iw.astype(np.int64))))
+                tw.append((c0 + i, torch.from_numpy(iw.astype(np.int32))))
         if verbose and ((c0 // chunk) % 16 == 15 or c1 == n_traj):
             print("training set: %d / %d trajectories" % (c1, n_traj), flush=True)
     targets.sort(key=lambda p: p[0])
@@ -317,29 +378,53 @@ def training_set(cfg, n_traj, grids, n_w_train=64, precision=rad.MIXED, chunk=64
     return torch.cat(feats), W, Y
 
 
+def targets_of(cube, floor_rel=1e-3):
+    """log(S / max S + floor_rel) of each map of a float64 cube [..., n_y, n_x] (the maximum
+    over the map's directions; rad_sampler_targets), float32 of the same shape."""
+    import torch
+    n_dirs = int(cube.shape[-1] * cube.shape[-2])
+    n_maps = cube.numel() // n_dirs
+    y = torch.empty(cube.shape, dtype=torch.float32, device=cube.device)
+    rad._check(_lib().rad_sampler_targets(rad._dptr(cube), n_maps, n_dirs, float(floor_rel), rad._dptr(y),
+                                          rad._stream(None)), "rad_sampler_targets")
+    return y
+
+
+def moments(Y):
+    """(mean, standard deviation) of a float32 tensor (rad_sampler_moments, FP64)."""
+    import torch
+    m = torch.empty(2, dtype=torch.float64, device="cuda")
+    ws = torch.empty(int(_lib().rad_sampler_moments_workspace_bytes()), dtype=torch.uint8, device="cuda")
+    rad._check(_lib().rad_sampler_moments(rad._dptr(Y), Y.numel(), rad._dptr(m), rad._dptr(ws), ws.numel(),
+                                          rad._stream(None)), "rad_sampler_moments")
+    return m
+
+
 def train(mlp, grids, feat, W, Y, steps=3000, batch=65536, lr=2e-3, lr_end=2e-5, seed=0, log_every=500,
           verbose=False):
-    """Adam on minibatches of (trajectory, energy, direction) points; cosine learning rate.
-    Returns the normalisation (mu, sigma of the log targets) and the loss history."""
+    """Adam on minibatches of (trajectory, energy, direction) points drawn by the library
+    (rad_sampler_minibatch; targets standardised by their mean and standard deviation);
+    cosine learning rate.  Returns the normalisation (mu, sigma of the log targets) and the
+    loss history."""
     import torch
-    mu = float(Y.mean())
-    sigma = float(Y.std())
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(int(seed))
     N, nwt = W.shape
     npix = grids.n * grids.n
+    mom = moments(Y)
+    mu, sigma = (float(v) for v in mom.cpu().numpy())
+    traj = torch.empty(batch, dtype=torch.int32, device="cuda")
+    x = torch.empty((batch, 3), dtype=torch.float32, device="cuda")
+    t = torch.empty(batch, dtype=torch.float32, device="cuda")
+    Wi = W.to(torch.int32).contiguous()
     losses = []
     for it in range(steps):
         a = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * it / max(1, steps - 1)))
-        ti = torch.randint(0, N, (batch,), device="cuda", generator=gen)
-        wi = torch.randint(0, nwt, (batch,), device="cuda", generator=gen)
-        pi = torch.randint(0, npix, (batch,), device="cuda", generator=gen)
-        gw = W[ti, wi]
-        x = grids.point_x[gw * npix + pi]
-        t = ((Y.view(N, nwt, npix)[ti, wi, pi] - mu) / sigma).contiguous()
-        loss = mlp.train_step(feat, ti.to(torch.int32), x.contiguous(), t, a)
+        rad._check(_lib().rad_sampler_minibatch(rad._dptr(Y), rad._dptr(Wi), N, nwt, npix, rad._dptr(grids.point_x),
+                                                grids.point_x.shape[0], rad._dptr(mom), batch, int(seed), it,
+                                                rad._dptr(traj), rad._dptr(x), rad._dptr(t), rad._stream(None)),
+                   "rad_sampler_minibatch")
+        loss_sum = mlp.train_step(feat, traj, x, t, a)
         if it % 50 == 0 or it == steps - 1:
-            losses.append((it, float(loss.item())))
+            losses.append((it, float(loss_sum.item()) / batch))
             if verbose and (it % log_every == 0 or it == steps - 1):
                 print("step %d lr %.2e loss %.4f" % (it, a, losses[-1][1]), flush=True)
     return dict(mu=mu, sigma=sigma), losses

@@ -79,6 +79,7 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="checkpoint (.npz)")
     ap.add_argument("--report", default=None, help="JSON report")
     ap.add_argument("--load", default=None, help="skip training, load this checkpoint")
+    ap.add_argument("--cache", default=None, help="training-spectra cache (.npz): loaded if it matches, else written")
     ap.add_argument("--fill", default="auto", choices=["auto", "pred", "coarse"],
                     help="estimate of the cells left out (auto: chosen on the validation set)")
     a = ap.parse_args(argv)
@@ -101,7 +102,8 @@ def main(argv=None):
         t0 = time.time()
         if a.train_first < 70064 and a.train_first + a.train > 60000:
             raise SystemExit("training particles overlap the validation/test particles (60000..70063)")
-        feat, W, Y = training_set(cfg, a.train, grids, n_w_train=a.energies, first=a.train_first, verbose=True)
+        feat, W, Y = training_set(cfg, a.train, grids, n_w_train=a.energies, first=a.train_first, verbose=True,
+                                  cache=a.cache)
         torch.cuda.synchronize()
         report["training_set_seconds"] = time.time() - t0
         print("training set: %d spectra in %.1f s" % (W.numel(), report["training_set_seconds"]), flush=True)

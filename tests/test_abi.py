@@ -1,4 +1,4 @@
-"""The C-ABI library loads on the CPU and exports every function include/rad.h declares.
+"""The C-ABI library loads on the CPU and exports every function include/*.h declares.
 
 No compute call is made here (there is no GPU in the CPU suite); only calls
 that the header defines to fail validation before touching a device.
@@ -10,7 +10,8 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("rad.h", "rad_mlp.h", "rad_sampler.h", "rad_traj.h")]
+HEADERS = sorted(os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))
+                 if h.endswith(".h"))
 
 
 def declared_functions():

@@ -17,16 +17,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (kernel symbol, VALU instructions in the hot loop per time step: 16 evaluations for a 4x4
 # tile)
 HOT = {
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,   # FP64, J, recurrence
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,   # FP64, J, direct
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 204,   # mixed, J
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 279,
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 311,
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 204,
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 278,   # FP64, J, recurrence
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 310,   # FP64, J, direct
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 203,   # mixed, J
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 278,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 310,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 203,
     # 4x6 tile without J: per 24 evaluations
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 327,   # FP64, recurrence
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 389,   # FP64, direct
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 252,   # mixed
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 326,   # FP64, recurrence
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 388,   # FP64, direct
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 251,   # mixed
 }
 
 
@@ -69,11 +69,57 @@ def hot_loop(lines, symbol):
     return inner
 
 
+# hardware FP32 sine and cosine in the mixed-precision hot loops (the mixed form's issue
+# roofline weights them by their measured cost): 7 phase factors per 4x4 tile step,
+# 9 per 4x6 step
+TRANS = {
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 14,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 14,
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 18,
+}
+
+
 @pytest.mark.parametrize("symbol", sorted(HOT))
 def test_hot_loop_has_no_scratch_and_known_valu(asm, symbol):
     c = hot_loop(asm, symbol)
     valu = sum(v for k, v in c.items() if k.startswith("v_"))
     scratch = sum(v for k, v in c.items() if k.startswith(("scratch_", "buffer_")))
-    print("%s: VALU %d, scratch %d" % (symbol, valu, scratch))
+    trans = sum(v for k, v in c.items() if k.startswith(("v_sin_", "v_cos_")))
+    print("%s: VALU %d, scratch %d, sin/cos %d" % (symbol, valu, scratch, trans))
     assert scratch == 0
     assert valu == HOT[symbol]
+    assert trans == TRANS.get(symbol, 0)
+
+
+def _pass_loop_spill_stores(lines, symbol):
+    """Scratch stores inside the time-pass loop (the loop that holds the staging loops and
+    the hot loop), from the loop-depth notes of the assembly: depth 2 in the persistent
+    kernel (inside the work-item loop), depth 1 in the one-item kernel."""
+    start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
+    end = next(i for i in range(start + 1, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    pass_depth = 2 if "persistent" in symbol or "Li6E" in symbol else 1
+    depth, n = 0, 0
+    for l in lines[start:end]:
+        if l.startswith((".LBB", "; %bb")):
+            m = re.search(r"Depth=(\d+)", l)
+            depth = int(m.group(1)) if m else 0
+        if "scratch_store" in l and depth == pass_depth:
+            n += 1
+    return n
+
+
+@pytest.mark.parametrize("symbol", sorted(HOT))
+def test_no_spill_stores_per_time_pass(asm, symbol):
+    """The time loop's bounds and counter are wave-uniform and stay in scalar registers, so
+    nothing is written to scratch once per pass of 128 time steps (spills that remain are
+    per work item)."""
+    n = _pass_loop_spill_stores(asm, symbol)
+    print("%s: %d scratch stores per pass" % (symbol, n))
+    assert n == 0
+
+
+def test_bench_uses_the_counted_mixed_loop():
+    """bench.py's mixed-form issue roofline uses the counts pinned above."""
+    import bench
+    sym = "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE"
+    assert bench.MIXED_VALU_PER_16 == HOT[sym] and bench.MIXED_TRANS_PER_16 == TRANS[sym]

@@ -1,6 +1,7 @@
 """The learned sampler's kernels (features, selection, combination) and the whole estimate
 against the CPU references (oracle/sampler.py and the direct-sum oracle)."""
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -164,6 +165,14 @@ def test_combine_matches_oracle(S):
     got = smp.combine(*dev, cell_pred=torch.from_numpy(pm).cuda())
     ref = osm.combine(cells, mask, coarse, w, w, 8, 8, cell_pred=pm)
     assert np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max() < 1e-13
+    # energies that fell back take the full-grid value bit for bit
+    fb = (rng.random((2, 70)) < 0.4).astype(np.uint8)
+    full = rng.random((2, 70))
+    got = smp.combine(*dev, cell_pred=torch.from_numpy(pm).cuda(), fallback=torch.from_numpy(fb).cuda(),
+                      full=torch.from_numpy(full).cuda()).cpu().numpy()
+    ref = osm.combine(cells, mask, coarse, w, w, 8, 8, cell_pred=pm, fallback=fb, full=full)
+    assert np.array_equal(got[fb > 0], full[fb > 0])
+    assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-13
 
 
 def test_estimate_matches_oracle(S):
@@ -203,10 +212,12 @@ def test_estimate_matches_oracle(S):
             assert err < tol
         smp.tau = 0.0                                   # every energy falls back: the full grid
         res = smp.estimate(ds, precision=prec)
-        assert res["fallback"].all()
+        assert res["fallback"].all() and not res["mask"].any()
         err = np.abs(res["dIdw"].cpu().numpy() - full).max() / np.abs(full).max()
         print("fallback prec %d: %.2e" % (prec, err))
         assert err < tol
+        ref_full, _ = smp.full_grid(ds, precision=prec)
+        assert np.array_equal(res["dIdw"].cpu().numpy(), ref_full.cpu().numpy()), "fallback is not bitwise"
         smp.tau = 1e30
     # the error-driven rule: cells left out at their corrected estimates
     smp.select_rule, smp.eps, smp.cap = "error", 0.05, 3
@@ -268,3 +279,77 @@ def test_error_paths(S):
     net = MLP(34, 9, seed=1)                              # more than 8 point inputs: no grid form
     with pytest.raises(rad.RadError):
         net.forward_grid(torch.zeros((2, 34), device="cuda"), torch.zeros((5, 9), device="cuda"))
+
+
+def test_training_set_cache(S, tmp_path, monkeypatch):
+    """Training spectra are stored and reloaded instead of recomputed: the second call with
+    the same arguments reads the file (no integral is computed) and returns the same
+    arrays; other arguments recompute."""
+    import torch
+    from paper_1910_10391_amd import rad
+    cfg, _ = _short_positrons(1)
+    grids = S.Grids(analytic.log_omega(16, 1e6, 150e6), 1.0e10 / 0.51099895e6, n_fine=16)
+    path = str(tmp_path / "spectra.npz")
+    a = S.training_set(cfg, 3, grids, n_w_train=4, first=50, cache=path)
+    assert os.path.exists(path)
+
+    def no_integrals(*args, **kw):
+        raise AssertionError("the cached training set was recomputed")
+    with monkeypatch.context() as m:
+        m.setattr(rad, "batch", no_integrals)
+        b = S.training_set(cfg, 3, grids, n_w_train=4, first=50, cache=path)
+    for x, y in zip(a, b):
+        assert x.shape == y.shape and torch.equal(x.cpu(), y.cpu())
+    c = S.training_set(cfg, 3, grids, n_w_train=4, first=51, cache=path)   # other particles
+    assert not torch.equal(c[2].cpu(), a[2].cpu())
+
+
+def _splitmix(z):
+    """splitmix64 of a counter (Steele, Lea and Flood, 2014), on uint64 numpy arrays."""
+    with np.errstate(over="ignore"):
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def test_training_data_kernels(S):
+    """Targets log(S+ / max S+ + floor), their moments and the minibatch draws of the
+    library against NumPy, the draws re-derived from the published splitmix64."""
+    import torch
+    rng = np.random.default_rng(41)
+    cube = rng.exponential(size=(3, 5, 7, 9)) * 10.0 ** rng.uniform(-3, 3, size=(3, 5, 1, 1))
+    cube[0, 1] = 0.0                                            # an all-zero map
+    cube[1, 2, 3, 4] = -1e-3                                    # a negative value counts as 0
+    y = S.targets_of(torch.from_numpy(cube).cuda(), 1e-3).cpu().numpy()
+    c = np.maximum(cube, 0.0)
+    peak = np.maximum(c.max(axis=(2, 3), keepdims=True), 1e-300)
+    ref = np.log(c / peak + 1e-3)
+    assert np.abs(y - ref).max() < 2e-6
+    Y = torch.from_numpy(rng.normal(3.0, 0.01, size=(6, 4, 10)).astype(np.float32)).cuda()
+    m = S.moments(Y).cpu().numpy()
+    yn = Y.cpu().numpy().astype(np.float64)
+    assert abs(m[0] - yn.mean()) < 1e-12 * abs(yn.mean()) and abs(m[1] - yn.std()) < 1e-9 * yn.std()
+    # minibatch: 6 trajectories x 4 energy slots x 10 directions, a point table of 5 energies
+    W = torch.from_numpy(rng.integers(0, 5, size=(6, 4)).astype(np.int32)).cuda()
+    table = torch.from_numpy(rng.normal(size=(5 * 10, 3)).astype(np.float32)).cuda()
+    B, seed, step = 1000, 77, 5
+    traj = torch.empty(B, dtype=torch.int32, device="cuda")
+    x = torch.empty((B, 3), dtype=torch.float32, device="cuda")
+    t = torch.empty(B, dtype=torch.float32, device="cuda")
+    from paper_1910_10391_amd import rad
+    mom = S.moments(Y)
+    rad._check(S._lib().rad_sampler_minibatch(rad._dptr(Y), rad._dptr(W), 6, 4, 10, rad._dptr(table), 50,
+                                              rad._dptr(mom), B, seed, step, rad._dptr(traj), rad._dptr(x),
+                                              rad._dptr(t), rad._stream(None)), "minibatch")
+    b = np.arange(B, dtype=np.uint64)
+    base = _splitmix(np.uint64(seed) ^ _splitmix(np.uint64(step))) + np.uint64(3) * b
+    r = [(_splitmix(base + np.uint64(j)) >> np.uint64(11)) for j in range(3)]
+    ti, ei, pi = (r[0] % np.uint64(6)).astype(np.int64), (r[1] % np.uint64(4)).astype(np.int64), \
+        (r[2] % np.uint64(10)).astype(np.int64)
+    Wn, tab, mm = W.cpu().numpy(), table.cpu().numpy(), mom.cpu().numpy()
+    assert np.array_equal(traj.cpu().numpy(), ti)
+    assert np.array_equal(x.cpu().numpy(), tab[Wn[ti, ei] * 10 + pi])
+    tr = ((yn[ti, ei, pi] - mm[0]) / mm[1]).astype(np.float32)
+    assert np.abs(t.cpu().numpy() - tr).max() < 1e-5
+    assert len(np.unique(ti)) == 6 and len(np.unique(pi)) == 10

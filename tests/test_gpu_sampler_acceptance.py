@@ -1,0 +1,111 @@
+"""The trained learned angular sampler on held-out trajectories (the positron workload:
+10 GeV, 100 um, spin-1/2 on 512 log-spaced photon energies x 64 x 64 directions within
++-5/gamma, 8 x 8 cells).
+
+The network is the committed checkpoint written by ``python -m
+paper_1910_10391_amd.train_sampler`` (trained on the GPU by the library's own BF16
+kernels on spectra the library computed; loaded without pickle).  Against the full-grid
+angle integral of the same trajectories (the judge of the sampler's error):
+
+* acceptance: the largest relative error of dI/d hw (energies above 1e-3 of the peak)
+  is at most 1 %;
+* gain: refinement without the network (cells ranked by the exact coarse values, at the
+  coverage that meets the same 1 % bound) needs more evaluations and more time;
+* fallback: with the mismatch tolerance at 0 every energy falls back, and the result is
+  the full-grid integral bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CKPT = os.path.join(ROOT, "paper_1910_10391_amd", "weights", "positron_spinhalf_sampler.npz")
+N_TEST = 24           # held-out trajectories, particles 70000.. (training used 40000.., tuning 60000..)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_10391_amd import rad, sampler
+    from paper_1910_10391_amd.synth import channeling, presets
+    from paper_1910_10391_amd.train_sampler import errors
+    cfg = presets.positron_config()
+    pg = presets.positron_grid()
+    gamma = cfg.energy_eV / channeling.ME_EV
+    smp = sampler.Sampler.load(CKPT, pg.hw_eV, gamma)
+    trs = channeling.generate(cfg, N_TEST, first=70000, threads=16)
+    ds = rad.DeviceSegments([tr[0] for tr in trs])
+    smp.full_grid(ds, rad.MIXED)                              # warm-up
+    full, t_full = min((smp.full_grid(ds, rad.MIXED) for _ in range(2)), key=lambda r: r[1])
+    return dict(rad=rad, smp=smp, ds=ds, full=full.cpu().numpy(), t_full=t_full, errors=errors)
+
+
+def _run(s, rule, reps=3):
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        r = s["smp"].estimate(s["ds"], precision=s["rad"].MIXED, rule=rule)
+        if best is None or r["seconds"] < best["seconds"]:
+            best = r
+    rel, _ = s["errors"](best["dIdw"].cpu().numpy(), s["full"])
+    return best, float(rel.max())
+
+
+def test_checkpoint_is_weights_only():
+    with np.load(CKPT, allow_pickle=False) as z:
+        # W1 [256][38 + 3], b1, W2, b2, W3, b3 (256 x 256 and 256), W4 [256], b4
+        assert z["params"].dtype == np.float32
+        assert z["params"].size == (38 + 3) * 256 + 256 + 2 * (256 * 256 + 256) + 256 + 1
+        assert str(z["select"]) in ("mass", "error")
+
+
+def test_acceptance_and_gain_over_refinement_without_network(setup):
+    s = setup
+    smp = s["smp"]
+    learned, err_l = _run(s, "learned")
+    frac_l = learned["evals"] / learned["evals_full"]
+    print("learned (%s): max rel err %.4f, %.1f %% of the evaluations, %.3f s (full grid %.3f s, x%.2f)"
+          % (smp.select_rule, err_l, 100 * frac_l, learned["seconds"], s["t_full"], s["t_full"] / learned["seconds"]),
+          flush=True)
+    assert err_l <= 0.01, err_l
+    assert not learned["fallback"].any() or smp.select_rule == "mass"
+    # refinement without the network, at the coverage that keeps the same 1 % bound here
+    keep = (smp.select_rule, smp.coverage, smp.fill, smp.tau)
+    try:
+        smp.select_rule, smp.fill, smp.tau = "mass", "coarse", float("inf")
+        chosen = None
+        for cov in (0.95, 0.98, 0.99, 0.995, 0.999):
+            smp.coverage = cov
+            coarse, err_c = _run(s, "coarse", reps=1)
+            if err_c <= 0.01:
+                chosen = cov
+                break
+        assert chosen is not None, "refinement without the network never met 1 %"
+        coarse, err_c = _run(s, "coarse")
+    finally:
+        smp.select_rule, smp.coverage, smp.fill, smp.tau = keep
+    frac_c = coarse["evals"] / coarse["evals_full"]
+    print("without network (coverage %.3f): max rel err %.4f, %.1f %% of the evaluations, %.3f s"
+          % (chosen, err_c, 100 * frac_c, coarse["seconds"]), flush=True)
+    assert learned["evals"] < coarse["evals"], (frac_l, frac_c)
+    assert learned["seconds"] < coarse["seconds"], (learned["seconds"], coarse["seconds"])
+
+
+def test_forced_fallback_is_the_full_grid_bitwise(setup):
+    s = setup
+    smp = s["smp"]
+    keep = (smp.select_rule, smp.tau)
+    try:
+        smp.select_rule, smp.tau = "mass", 0.0
+        r = smp.estimate(s["ds"], precision=s["rad"].MIXED)
+    finally:
+        smp.select_rule, smp.tau = keep
+    assert r["fallback"].all()
+    assert np.array_equal(r["dIdw"].cpu().numpy(), s["full"])
+    assert r["evals"] >= r["evals_full"]

@@ -152,6 +152,12 @@ def test_combine_exact_and_coarse():
     got = osm.combine(cells, mask, coarse, wx, wy, 2, 2, cell_pred=pm)
     ref = sum(cells[..., c] * mask[..., c] + pm[..., c] * (1 - mask[..., c]) for c in range(4))
     assert np.allclose(got, ref, rtol=1e-14)
+    # an energy that fell back is the full-grid value, whatever its cells say
+    fb = np.zeros((2, 5), np.uint8)
+    fb[0, 1] = fb[1, 4] = 1
+    got_fb = osm.combine(cells, mask, coarse, wx, wy, 2, 2, cell_pred=pm, fallback=fb, full=full)
+    assert got_fb[0, 1] == full[0, 1] and got_fb[1, 4] == full[1, 4]
+    assert np.array_equal(got_fb[fb == 0], got[fb == 0])
 
 
 def test_cell_sums_order():
