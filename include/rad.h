@@ -35,6 +35,7 @@
  *     device memory.  They stage their launch descriptors through the grid's
  *     pinned host buffer (1 MiB from rad_setup_grid, about 1000 segments' worth);
  *     only a call whose descriptors need more grows it to that size.
+ *     rad_batch_static allocates nothing at all.
  *   - Errors: every call returns a status and never aborts or throws across the
  *     ABI.  Arguments are validated before any launch; on error nothing is
  *     launched and rad_last_error() holds a message (thread-local).
@@ -161,6 +162,26 @@ rad_status rad_quantum(const rad_grid *grid, const rad_segment *seg, int kinds, 
 rad_status rad_batch(const rad_grid *grid, const rad_segment *segs, int n_segs,
                      const int *out_index, int n_out, int kinds, rad_precision prec, double *out,
                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * rad_batch for callers that cannot allocate: code under hipGraph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * errors as rad_batch, without the workspace: the segment descriptors and partial
+ * amplitudes live in a fixed device array of rad_static_scratch_bytes() (64 MiB)
+ * that the library holds on every GPU it runs on until the process ends; the
+ * descriptors are written into it by kernels (no host staging buffer), and the
+ * call allocates no device or pinned host memory.  The time chunks are coarsened
+ * (down to one per segment) until the work fits, so results equal rad_batch's to
+ * rounding (bitwise where the chunking is the same).  Errors: as rad_batch, and
+ * RAD_ENOMEM when even one chunk per segment needs more than the fixed scratch
+ * (then nothing is launched).  All calls on one GPU share its array and it keeps
+ * the last call's contents: calls that overlap in time on one GPU (two streams,
+ * two threads) race and give wrong results; serialise them.
+ */
+size_t rad_static_scratch_bytes(void);
+rad_status rad_batch_static(const rad_grid *grid, const rad_segment *segs, int n_segs,
+                            const int *out_index, int n_out, int kinds, rad_precision prec,
+                            double *out, void *stream);
 
 /*
  * Persistent, replayable batches.  A plan fixes one rad_batch call's segments,

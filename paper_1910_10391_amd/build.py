@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "librad.so")
 OBJ = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["rad_kernels.hip", "rad_lib.cpp", "mlp_kernels.hip", "mlp_lib.cpp",
+SOURCES = ["rad_kernels.hip", "rad_lib.cpp", "rad_static.hip", "mlp_kernels.hip", "mlp_lib.cpp",
            "sampler_kernels.hip", "sampler_lib.cpp", "traj_kernels.hip", "traj_lib.cpp", "peak_kernels.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -207,9 +207,12 @@ struct Plan {
     bool one_chunk = false;        // every segment is a single time chunk
 };
 
+// fixed_cap > 0: `ws` is the library's own fixed scratch of fixed_cap bytes (no
+// device-allocation check); the time chunks are then made coarser, down to one chunk
+// per segment, until the workspace fits in it.
 rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_index,
                       int n_out, int kinds, rad_precision prec, void *ws, size_t ws_bytes,
-                      bool persistent, Plan &P)
+                      bool persistent, Plan &P, size_t fixed_cap = 0)
 {
     rad_status rs = check_grid(g);
     if (rs != RAD_OK) return rs;
@@ -235,20 +238,40 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
     P.withj = (kinds & RAD_SPINHALF) != 0;
     P.tile_c = plan_tile(g, variant_for(persistent, P.mixed, false));
     P.tile_q = plan_tile(g, variant_for(persistent, P.mixed, P.withj));
-    const int64_t cf = chunk_factor(plan_tile(g, kVar44x2), n_segs);   // variant-independent chunking
+    int64_t cf = chunk_factor(plan_tile(g, kVar44x2), n_segs);   // variant-independent chunking
     std::vector<int32_t> nch(n_segs), clen(n_segs);
-    int64_t sum_chunks = 0;
-    for (int s = 0; s < n_segs; ++s) {
-        plan_chunks(segs[s].n, cf, nch[s], clen[s]);
-        sum_chunks += nch[s];
+    auto chunk_all = [&](int64_t c) {
+        int64_t sum = 0;
+        for (int s = 0; s < n_segs; ++s) {
+            plan_chunks(segs[s].n, c, nch[s], clen[s]);
+            sum += nch[s];
+        }
+        return sum;
+    };
+    int64_t sum_chunks = chunk_all(cf);
+    P.lay = layout(g, n_segs, n_out, kinds, sum_chunks);
+    if (fixed_cap > 0 && P.lay.total > fixed_cap) {
+        // the largest chunk factor whose workspace fits (the size grows with the factor)
+        int64_t lo = 1, hi = cf - 1;
+        if (layout(g, n_segs, n_out, kinds, chunk_all(1)).total > fixed_cap)
+            return fail(RAD_ENOMEM, "the call needs %zu bytes of scratch even in one time chunk per segment; "
+                        "the fixed scratch holds %zu", layout(g, n_segs, n_out, kinds, chunk_all(1)).total, fixed_cap);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (layout(g, n_segs, n_out, kinds, chunk_all(mid)).total <= fixed_cap) lo = mid; else hi = mid - 1;
+        }
+        cf = lo;
+        sum_chunks = chunk_all(cf);
+        P.lay = layout(g, n_segs, n_out, kinds, sum_chunks);
     }
     P.one_chunk = sum_chunks == n_segs;
-    P.lay = layout(g, n_segs, n_out, kinds, sum_chunks);
     if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < P.lay.total)
         return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, P.lay.total);
-    rs = check_dev_range(ws, P.lay.total, "workspace");
-    if (rs != RAD_OK) return rs;
+    if (fixed_cap == 0) {
+        rs = check_dev_range(ws, P.lay.total, "workspace");
+        if (rs != RAD_OK) return rs;
+    }
     P.ws = (char *)ws;
     P.ws_bytes = ws_bytes;
     const size_t cube = (size_t)g->n_w * g->n_x * g->n_y;
@@ -495,6 +518,33 @@ rad_status run(rad_grid *g, const rad_segment *segs, int n_segs, const int *out_
     if (rs != RAD_OK) return rs;
     return plan_launch(P, out, st, profiling_on());
 }
+
+}  // namespace
+
+namespace rad {
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+// rad_batch on `cap` bytes of the library's fixed device scratch at `scratch`: the time
+// chunks are coarsened until the workspace fits, and the descriptors reach the scratch
+// as kernel arguments, so nothing is allocated (no pinned staging, no device memory).
+rad_status run_in_scratch(const rad_grid *grid, const rad_segment *segs, int n_segs, const int *out_index,
+                          int n_out, int kinds, rad_precision prec, double *out, char *scratch, size_t cap,
+                          hipStream_t st)
+{
+    rad_grid *g = const_cast<rad_grid *>(grid);
+    if (!scratch) return fail(RAD_EDEVICE, "no fixed scratch on this device");
+    Plan P;
+    rad_status rs = plan_build(g, segs, n_segs, out_index, n_out, kinds, prec, scratch, cap, false, P, cap);
+    if (rs != RAD_OK) return rs;
+    rs = check_out(P, out);
+    if (rs != RAD_OK) return rs;
+    hipError_t e = launch_upload(P.ws, P.host.data(), P.lay.desc_bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    return plan_launch(P, out, st, false);
+}
+}  // namespace rad
+
+namespace {
 
 // The chunking (and so the size) must not depend on which form or variant runs:
 // it is planned with the 4x4 tile count whatever the variant.
