@@ -432,6 +432,8 @@ def bench_mlp(args):
     print("bench mlp: inference %.1f ms for %d points (%.3e points/s); training step %.2f ms" % (
         dt * 1e3, pts, pts / dt, dt_tr * 1e3), file=sys.stderr, flush=True)
     tf = pts * mfma_flops / dt / 1e12
+    tr_bytes = mlp_training_bytes(B, 41)
+    tr_flops = mlp_training_flops(B, 41)
     return {
         "metric": "network evaluations (points) per second", "value": pts / dt, "unit": "points/s", "n_gpus": 1,
         "steps": max(1, args.steps), "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -442,7 +444,39 @@ def bench_mlp(args):
                      "traffic": None},
         "all_flops_tflops": pts * all_flops / dt / 1e12,
         "training_step_ms": dt_tr * 1e3, "training_points_per_s": B / dt_tr,
+        "training_roofline": {"bound": "hbm", "achieved": tr_bytes / dt_tr / 1e9, "peak": 8000.0, "unit": "GB/s",
+                              "frac": tr_bytes / dt_tr / 8e12, "bytes": tr_bytes,
+                              "mfma_tflops": tr_flops / dt_tr / 1e12},
     }
+
+
+def mlp_training_bytes(B, n_in):
+    """Algorithmic HBM bytes of one training step of B points (B a multiple of 128): every
+    activation, SiLU derivative, dz and k8 copy written once and read by its consumers,
+    the split-K and per-block partials, Adam's four parameter-sized arrays."""
+    a = B * 256 * 2                           # one BF16 activation-sized array
+    i1 = B * 64 * 2                           # the padded layer-1 input
+    P = 256 * n_in + 256 + 2 * (256 * 256 + 256) + 256 + 1
+    wp = 64 * 256 * 4                         # split-K partial rows per output row
+    total = B * 16 + 2 * i1                   # assemble: traj + x in, in1 + in1_k8 out
+    total += i1 + 3 * a                       # layer 1: in1 in; h1, ds1, h1_k8 out
+    total += a + 3 * a                        # layer 2
+    total += a + 2 * a                        # layer 3 (no k8 copy)
+    total += 2 * a + B * 4 + 2 * a + (B // 64) * 514 * 4      # output layer and dz3
+    total += 2 * (2 * a + wp * 256)           # dW3, dW2 partials
+    total += 2 * (2 * a + 2 * a + (B // 128) * 256 * 4)       # dz2, dz1 (with their k8 copies)
+    total += a + i1 + wp * 64                 # dW1 partials
+    total += 2 * wp * 256 + wp * 64 + (B // 64) * 514 * 4 + 2 * (B // 128) * 256 * 4   # final reductions
+    total += 7 * P * 4                        # Adam: p, m1, m2, g in; p, m1, m2 out
+    return float(total)
+
+
+def mlp_training_flops(B, n_in):
+    """Dense products of one training step: forward 41(64) -> 256 -> 256 -> 256, the two
+    backward data products and the three weight-gradient products (2 flops per MAC)."""
+    fwd = 2.0 * B * (64 * 256 + 2 * 256 * 256)
+    bwd = 2.0 * B * (2 * 256 * 256) + 2.0 * B * (2 * 256 * 256 + 256 * 64)
+    return fwd + bwd
 
 
 def sample_points(segs, grid):

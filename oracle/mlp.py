@@ -3,7 +3,8 @@
 Plain NumPy in FP64: forward pass, mean-squared-error loss, backward pass by the
 chain rule, and one Adam step -- the definitions written out.  With
 ``bf16=True`` it rounds to BF16 at the points where the GPU kernels store BF16
-(inputs, weights, activations, the backward operands), so that GPU gradients
+(inputs, weights, activations, the SiLU derivatives kept from the forward pass for
+the backward pass, the backward operands), so that GPU gradients
 can be compared closely; with ``bf16=False`` it is the exact FP64 network,
 pinned by finite differences in the CPU tests.
 
@@ -95,13 +96,13 @@ def loss_and_grad(theta, feat, traj, x, target, bf=False):
     g = {}
     g["W4"] = c["h3"].T @ dy
     g["b4"] = np.array([dy.sum()])
-    dz3 = (dy[:, None] * W4[None, :]) * dsilu(c["z3"])
+    dz3 = (dy[:, None] * W4[None, :]) * r(dsilu(c["z3"]))
     g["W3"] = r(dz3).T @ c["h2"]
     g["b3"] = dz3.sum(0)
-    dz2 = (r(dz3) @ W3) * dsilu(c["z2"])
+    dz2 = (r(dz3) @ W3) * r(dsilu(c["z2"]))
     g["W2"] = r(dz2).T @ c["h1"]
     g["b2"] = dz2.sum(0)
-    dz1 = (r(dz2) @ W2) * dsilu(c["z1"])
+    dz1 = (r(dz2) @ W2) * r(dsilu(c["z1"]))
     g["W1"] = r(dz1).T @ c["a0"]
     g["b1"] = dz1.sum(0)
     return loss, pack(g, c["n_in"])

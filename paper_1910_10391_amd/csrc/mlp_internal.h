@@ -14,15 +14,17 @@ enum { kEpiFwd = 0, kEpiBwd = 1 };
 constexpr int kRowBlock = 128;   // rows per block of the row products; batches are padded to it
 
 // C[M][256] = A[M][K] W^T (A, W BF16, K = 64 or 256 contiguous) with an epilogue:
-// forward: z = C + bias (FP32, optional), h = bf16(silu(z)); backward: dz = C silu'(zin),
-// h = bf16(dz) and the per-block column sums of dz (col_part [M / 128][256]).  h goes
-// row-major to out_h and, if out_k8 is given, to the k8 layout [M / 8][256][8].
+// forward: z = C + bias, h = bf16(silu(z)) and, in training, ds = bf16(silu'(z)) (the
+// factor the backward pass needs, computed here from the FP32 z); backward: dz = C dsin
+// (dsin the ds of the layer below), h = bf16(dz) and the per-block column sums of dz
+// (col_part [M / 128][256]).  h goes row-major to out_h and, if out_k8 is given, to the k8
+// layout [M / 8][256][8].
 struct RowsArgs {
     const uint16_t *A, *W;
     int M, K;
     const float *bias;    // forward
-    const float *zin;     // backward: pre-activation of the layer below, [M][256]
-    float *out_z;         // forward, training: z [M][256] (or null)
+    const uint16_t *dsin; // backward: silu' of the layer below (BF16), [M][256]
+    uint16_t *out_ds;     // forward, training: silu'(z) (BF16) [M][256] (or null)
     uint16_t *out_h;      // [M][256]
     uint16_t *out_k8;     // [M / 8][256][8] or null
     float *col_part;      // backward: [M / 128][256]
@@ -35,6 +37,7 @@ struct K8Args {
     int M, N;
     int64_t kslice;
     float *part;
+    int splits;      // slices of the batch (set by launch_k8)
 };
 
 // Offsets of the parameter vector: W1 [256][n_in], b1, W2 [256][256], b2, W3, b3, W4 [256], b4.
@@ -45,10 +48,29 @@ struct MlpLayout {
 
 hipError_t launch_rows(int epi, const RowsArgs &g, hipStream_t st);
 hipError_t launch_k8(const K8Args &g, int splits, hipStream_t st);
-hipError_t launch_colsum(const float *x, int64_t ld, int M, int N, float *part, int slices, float *out,
-                         hipStream_t st);
-hipError_t launch_sum_slices(const float *part, int slices, int rows, int src_cols, int n_cols, float *out,
-                             int64_t out_stride, hipStream_t st);
+// The gradient's final reductions in one launch, each in a fixed order:
+// W tasks: out[r][c] = sum_s part[s][r][c] over the split-K slices (part [slices][256]
+// [src_cols], out [256][n_cols], n_cols <= src_cols); column-sum tasks: the sums over rows
+// of x [M][ld] (first N columns), columns c < split to out[c], the rest to out2[c - split].
+constexpr int kFinishW = 3, kFinishC = 3;
+struct FinishW {
+    const float *part;
+    int slices, src_cols, n_cols;
+    float *out;
+    int blocks;      // set by launch_finish_grad
+};
+struct FinishC {
+    const float *x;
+    int64_t ld;
+    int M, N, split;
+    float *out, *out2;
+    int blocks;      // set by launch_finish_grad
+};
+struct FinishArgs {
+    FinishW w[kFinishW];
+    FinishC c[kFinishC];
+};
+hipError_t launch_finish_grad(FinishArgs f, hipStream_t st);
 hipError_t launch_assemble_in1(const float *feat, int nf, const int *traj, const float *x, int np, int B, int Bp,
                                uint16_t *in1, uint16_t *in1_k8, hipStream_t st);
 hipError_t launch_fold_bias(const uint16_t *W1p, const float *b1, const float *feat, int nf, int n_traj, float *cb,
@@ -62,7 +84,7 @@ hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b
 constexpr int kOutPointsHost = 64;
 constexpr int kOutPartHost = 2 * kWidth + 2;
 hipError_t launch_output_grad(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
-                              const float *target, const float *z3, uint16_t *dzb, uint16_t *dz_k8, float *part,
+                              const float *target, const uint16_t *ds3, uint16_t *dzb, uint16_t *dz_k8, float *part,
                               hipStream_t st);
 hipError_t launch_adam(float *p, float *m1, float *m2, const float *g, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t st);

@@ -33,11 +33,8 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigmoidf_(z); }
-__device__ __forceinline__ float dsilu(float z)
-{
-    const float s = sigmoidf_(z);
-    return s * (1.0f + z * (1.0f - s));
-}
+// silu'(z) = s (1 + z (1 - s)) with s = sigmoid(z)
+__device__ __forceinline__ float dsilu_s(float z, float s) { return s * (1.0f + z * (1.0f - s)); }
 
 // ---------------------------------------------------------------- GEMM
 // MFMA operand layout (v_mfma_f32_32x32x16_bf16): lane l holds A[l % 32][8 (l / 32) + j]
@@ -75,30 +72,27 @@ __global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
     const int64_t row0 = (int64_t)blockIdx.x * kRowBlock;
     // global -> register staging of one slice: A 128 x 32 (2 chunks of 8 per thread),
     // W 256 x 32 (4 chunks per thread)
-    uint4 ra[2], rb[4];
-    auto load = [&](int s) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
-            ra[q] = *reinterpret_cast<const uint4 *>(g.A + (row0 + rr) * K + s * KS + kc * 8);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
-            rb[q] = *reinterpret_cast<const uint4 *>(g.W + (int64_t)rr * K + s * KS + kc * 8);
-        }
+    uint4 ra0, ra1, rb0, rb1, rb2, rb3;
+    const int srr = tid >> 2, skc = (tid & 3) * 8;   // this thread's row (and row + 64 q) and k chunk
+    auto load = [&](int s) __attribute__((always_inline)) {
+        const uint16_t *a = g.A + (row0 + srr) * K + s * KS + skc;
+        const uint16_t *w = g.W + (int64_t)srr * K + s * KS + skc;
+        ra0 = *reinterpret_cast<const uint4 *>(a);
+        ra1 = *reinterpret_cast<const uint4 *>(a + 64 * K);
+        rb0 = *reinterpret_cast<const uint4 *>(w);
+        rb1 = *reinterpret_cast<const uint4 *>(w + 64 * K);
+        rb2 = *reinterpret_cast<const uint4 *>(w + 128 * K);
+        rb3 = *reinterpret_cast<const uint4 *>(w + 192 * K);
     };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
-            *reinterpret_cast<uint4 *>(&sA[buf][rr * LD + kc * 8]) = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = tid + 256 * q, rr = c >> 2, kc = c & 3;
-            *reinterpret_cast<uint4 *>(&sB[buf][rr * LD + kc * 8]) = rb[q];
-        }
+    auto store = [&](int buf) __attribute__((always_inline)) {
+        uint16_t *a = &sA[buf][srr * LD + skc];
+        uint16_t *w = &sB[buf][srr * LD + skc];
+        *reinterpret_cast<uint4 *>(a) = ra0;
+        *reinterpret_cast<uint4 *>(a + 64 * LD) = ra1;
+        *reinterpret_cast<uint4 *>(w) = rb0;
+        *reinterpret_cast<uint4 *>(w + 64 * LD) = rb1;
+        *reinterpret_cast<uint4 *>(w + 128 * LD) = rb2;
+        *reinterpret_cast<uint4 *>(w + 192 * LD) = rb3;
     };
     floatx16 acc[2][4];
 #pragma unroll
@@ -130,44 +124,74 @@ __global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
         if (s + 1 < NS) store(buf ^ 1);
         __syncthreads();
     }
-    // ---- epilogue
+    // ---- epilogue, one 32 x 32 tile at a time.  A lane holds 4 consecutive rows of one
+    // column (the MFMA result layout); the row-major outputs go through a per-wave LDS
+    // stage (the K loop's buffers, free after its last barrier) so that every global store
+    // is 16 contiguous bytes per lane; the k8 layout takes the 4 rows directly.
+    constexpr int HLD = 40;                      // stage row stride (bf16), 16-byte aligned
+    uint16_t *hst = &sB[0][0] + wave * (2 * 32 * HLD);
+    uint16_t *dst = hst + 32 * HLD;
     float csum[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // backward: this lane's column sums of dz
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int col = wn * 128 + b * 32 + r;
+            const int64_t trow = row0 + wm * 64 + a * 32;   // first row of the tile
             const float bias = EPI == kEpiFwd ? g.bias[col] : 0.0f;
+            float dsin[16];
+            if constexpr (EPI == kEpiBwd) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    dsin[i] = bf2f(g.dsin[(trow + 8 * (i >> 2) + 4 * hs + (i & 3)) * kWidth + col]);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {            // rows 8 q + 4 hs + (0..3) of the tile
-                const int64_t rbase = row0 + wm * 64 + a * 32 + 8 * q + 4 * hs;
+                const int rt = 8 * q + 4 * hs;
                 uint16_t hv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int64_t row = rbase + j;
-                    const int64_t o = row * kWidth + col;
                     const float v = acc[a][b][4 * q + j];
                     float out;
                     if constexpr (EPI == kEpiFwd) {
                         const float z = v + bias;
-                        if (g.out_z) g.out_z[o] = z;
-                        out = silu(z);
+                        const float s = sigmoidf_(z);
+                        out = z * s;
+                        dst[(rt + j) * HLD + r] = f2bf(dsilu_s(z, s));
                     } else {
-                        out = v * dsilu(g.zin[o]);
+                        out = v * dsin[4 * q + j];
                         csum[b] += out;
                     }
                     hv[j] = f2bf(out);
-                    g.out_h[o] = hv[j];
+                    hst[(rt + j) * HLD + r] = hv[j];
                 }
                 if (g.out_k8) {
-                    // k8 layout: rows rbase .. rbase + 3 of column col are 4 consecutive entries
-                    const int64_t k8 = ((rbase >> 3) * kWidth + col) * 8 + (rbase & 7);
+                    // k8 layout: rows rt .. rt + 3 of column col are 4 consecutive entries
+                    const int64_t rb = trow + rt;
+                    const int64_t k8 = ((rb >> 3) * kWidth + col) * 8 + (rb & 7);
                     uint2 pk;
                     pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
                     pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
                     *reinterpret_cast<uint2 *>(g.out_k8 + k8) = pk;
                 }
             }
+            __builtin_amdgcn_wave_barrier();     // the wave's stage writes before its reads
+            const int c0 = wn * 128 + b * 32;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {        // h: 32 rows x 4 chunks of 8
+                const int c = lane + 64 * k, rr = c >> 2, cc = c & 3;
+                *reinterpret_cast<uint4 *>(g.out_h + (trow + rr) * kWidth + c0 + cc * 8) =
+                    *reinterpret_cast<const uint4 *>(&hst[rr * HLD + cc * 8]);
+            }
+            if (EPI == kEpiFwd && g.out_ds) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int c = lane + 64 * k, rr = c >> 2, cc = c & 3;
+                    *reinterpret_cast<uint4 *>(g.out_ds + (trow + rr) * kWidth + c0 + cc * 8) =
+                        *reinterpret_cast<const uint4 *>(&dst[rr * HLD + cc * 8]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();     // reads done before the next tile's writes
         }
     if constexpr (EPI == kEpiBwd) {
         // column sums over the block's 128 rows in a fixed order: the two row halves of a
@@ -184,15 +208,35 @@ __global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
 }
 
 // Weight gradients from the k8 layouts: C[m][n] = sum_k A8[k / 8][m][k % 8] B8[k / 8][n][k % 8]
-// over the batch slice [z kslice, (z + 1) kslice); waves WM x WN, each 64 x 64.
+// over the batch slice [z kslice, (z + 1) kslice); WM x WN tiles of 64 x 64, each computed by
+// two waves over alternate 16-row steps of the slice (operands loaded two steps ahead of
+// their products), their sums added in a fixed order through LDS.  One-dimensional grid of
+// T = 256 / (64 WM) x N / (64 WN) blocks per slice: when the slices come in multiples of 8,
+// the T blocks of a slice are given ids congruent mod 8, which puts them on one XCD (blocks
+// are dealt to the 8 XCDs round-robin), so that the slice's operands are fetched from HBM
+// once into that XCD's L2 and shared by the T blocks.
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_k8_kernel(K8Args g)
+__global__ __launch_bounds__(512) void gemm_k8_kernel(K8Args g)
 {
+    constexpr int NT = WM * WN;
+    constexpr int BM = kWidth / (64 * WM);       // blocks along m
+    __shared__ float sRed[NT][64 * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = wave % WM, wn = wave / WM;
+    const int tile = wave % NT, par = wave / NT;
+    const int wm = tile % WM, wn = tile / WM;
     const int r = lane & 31, hs = lane >> 5;
-    const int m0 = blockIdx.x * (64 * WM) + wm * 64, n0 = blockIdx.y * (64 * WN) + wn * 64;
-    const int64_t kb = (int64_t)blockIdx.z * g.kslice;
+    const int T = BM * (g.N / (64 * WN));
+    const int L = blockIdx.x;
+    int z, t;
+    if (T > 1 && g.splits % 8 == 0) {
+        z = L % 8 + 8 * (L / (8 * T));
+        t = (L / 8) % T;
+    } else {
+        z = L / T;
+        t = L % T;
+    }
+    const int m0 = (t % BM) * (64 * WM) + wm * 64, n0 = (t / BM) * (64 * WN) + wn * 64;
+    const int64_t kb = (int64_t)z * g.kslice;
     floatx16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -200,21 +244,43 @@ __global__ __launch_bounds__(256) void gemm_k8_kernel(K8Args g)
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx16{};
     const bf16x8u *A = reinterpret_cast<const bf16x8u *>(g.A8);
     const bf16x8u *B = reinterpret_cast<const bf16x8u *>(g.B8);
-    const int steps = (int)(g.kslice / 16);
-    for (int t = 0; t < steps; ++t) {
-        const int64_t kg = ((kb + 16 * (int64_t)t) >> 3) + hs;
-        bf16x8 av[2], bv[2];
+    const int steps = (int)(g.kslice / 32);       // pairs of 16-row steps
+    auto load = [&](int st, bf16x8 (&av)[2], bf16x8 (&bv)[2]) __attribute__((always_inline)) {
+        const int64_t kg = ((kb + 32 * (int64_t)st + 16 * par) >> 3) + hs;
 #pragma unroll
         for (int a = 0; a < 2; ++a) av[a] = __builtin_bit_cast(bf16x8, A[kg * g.M + m0 + a * 32 + r]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) bv[b] = __builtin_bit_cast(bf16x8, B[kg * g.N + n0 + b * 32 + r]);
+    };
+    bf16x8 av[2], bv[2], a1[2], b1[2], a2[2], b2[2];
+    load(0, av, bv);
+    if (steps > 1) load(1, a1, b1);
+    for (int st = 0; st < steps; ++st) {
+        if (st + 2 < steps) load(st + 2, a2, b2);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            av[a] = a1[a];
+            bv[a] = b1[a];
+            a1[a] = a2[a];
+            b1[a] = b2[a];
+        }
     }
-    float *out = g.part + (int64_t)blockIdx.z * g.M * g.N;
+    if (par == 1) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sRed[tile][((a * 2 + b) * 16 + i) * 64 + lane] = acc[a][b][i];
+    }
+    __syncthreads();
+    if (par == 1) return;
+    float *out = g.part + (int64_t)z * g.M * g.N;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -222,7 +288,7 @@ __global__ __launch_bounds__(256) void gemm_k8_kernel(K8Args g)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int row = m0 + a * 32 + 8 * (i >> 2) + 4 * hs + (i & 3);
-                out[(int64_t)row * g.N + n0 + b * 32 + r] = acc[a][b][i];
+                out[(int64_t)row * g.N + n0 + b * 32 + r] = acc[a][b][i] + sRed[tile][((a * 2 + b) * 16 + i) * 64 + lane];
             }
 }
 
@@ -232,39 +298,76 @@ __global__ __launch_bounds__(256) void gemm_k8_kernel(K8Args g)
 // slices.  A block of 256 threads takes nb columns x (256 / nb) row lanes: lane j of a
 // column sums rows m0 + j, m0 + j + lanes, ... of its slice in order, then the lanes are
 // added in a fixed LDS tree, so the result is deterministic.
-__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ x, int64_t ld, int M, int N, int nb,
-                                                     int rows_per, float *__restrict__ out, int64_t ld_out)
+// The gradient's reductions, one launch at the end of the backward pass (none of the
+// step's other kernels reads them).  Tasks, by block range:
+// * W tasks: out[r][c] = sum over the split-K slices s of part[s][r][src_cols r + c]
+//   (r < 256, c < n_cols), four columns per thread where the widths allow, the slices in
+//   order;
+// * column-sum tasks: out[c] = sum over rows m of x[m][c] (c < N; columns from `split` on
+//   go to out2), 4 columns per block, 64 row lanes per column each summing rows j, j + 64,
+//   ... in order, then a fixed tree over the lanes.
+__global__ __launch_bounds__(256) void finish_grad_kernel(FinishArgs f)
 {
     __shared__ float red[256];
-    const int lanes = 256 / nb;
-    const int c = threadIdx.x % nb, j = threadIdx.x / nb;
-    const int n = blockIdx.x * nb + c;
-    const int s = blockIdx.y;
-    const int m0 = s * rows_per, m1 = min(M, m0 + rows_per);
-    float acc = 0.0f;
-    if (n < N)
-        for (int m = m0 + j; m < m1; m += lanes) acc += x[(int64_t)m * ld + n];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = lanes / 2; h >= 1; h >>= 1) {
-        if (j < h) red[threadIdx.x] += red[threadIdx.x + h * nb];
-        __syncthreads();
+    int b = blockIdx.x;
+    for (int t = 0; t < kFinishW; ++t) {
+        const FinishW &w = f.w[t];
+        if (b >= w.blocks) {
+            b -= w.blocks;
+            continue;
+        }
+        const int64_t len = (int64_t)kWidth * w.src_cols;
+        const int64_t i = (int64_t)b * 256 + threadIdx.x;
+        if (w.n_cols % 4 == 0) {
+            const int q = w.n_cols / 4;
+            if (i >= (int64_t)kWidth * q) return;
+            const int64_t r = i / q, c = 4 * (i % q);
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll 8
+            for (int s = 0; s < w.slices; ++s) {
+                const float4 v = *reinterpret_cast<const float4 *>(w.part + s * len + r * w.src_cols + c);
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
+            }
+            float *o = w.out + r * w.n_cols + c;
+            o[0] = acc.x;
+            o[1] = acc.y;
+            o[2] = acc.z;
+            o[3] = acc.w;
+        } else {
+            if (i >= (int64_t)kWidth * w.n_cols) return;
+            const int64_t r = i / w.n_cols, c = i % w.n_cols;
+            float acc = 0.0f;
+#pragma unroll 8
+            for (int s = 0; s < w.slices; ++s) acc += w.part[s * len + r * w.src_cols + c];
+            w.out[r * w.n_cols + c] = acc;
+        }
+        return;
     }
-    if (j == 0 && n < N) out[(int64_t)s * ld_out + n] = red[c];
-}
-
-__global__ __launch_bounds__(256) void sum_slices(const float *__restrict__ part, int slices, int64_t len,
-                                                  float *__restrict__ out, int64_t out_stride, int n_cols,
-                                                  int src_cols)
-{
-    // out row r, column c (c < n_cols) = sum_s part[s][r * src_cols + c]
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t rows = len / src_cols;
-    if (i >= rows * n_cols) return;
-    const int64_t r = i / n_cols, c = i % n_cols;
-    float acc = 0.0f;
-    for (int s = 0; s < slices; ++s) acc += part[(size_t)s * len + r * src_cols + c];
-    out[r * out_stride + c] = acc;
+    for (int t = 0; t < kFinishC; ++t) {
+        const FinishC &c = f.c[t];
+        if (b >= c.blocks) {
+            b -= c.blocks;
+            continue;
+        }
+        const int col = 4 * b + (threadIdx.x & 3), j = threadIdx.x >> 2;
+        float acc = 0.0f;
+        if (col < c.N)
+            for (int m = j; m < c.M; m += 64) acc += c.x[(int64_t)m * c.ld + col];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 32; h >= 1; h >>= 1) {
+            if (j < h) red[threadIdx.x] += red[threadIdx.x + 4 * h];
+            __syncthreads();
+        }
+        if (j == 0 && col < c.N) {
+            if (col < c.split) c.out[col] = red[threadIdx.x];
+            else c.out2[col - c.split] = red[threadIdx.x];
+        }
+        return;
+    }
 }
 
 // ---------------------------------------------------------------- input / output layers
@@ -274,17 +377,31 @@ __global__ __launch_bounds__(256) void assemble_in1(const float *__restrict__ fe
                                                     const float *__restrict__ x, int np, int B, int Bp,
                                                     uint16_t *__restrict__ in1, uint16_t *__restrict__ in1_k8)
 {
+    // one thread per (group of 8 rows, column): 8 row-major entries (a wave writes 128
+    // contiguous bytes per row) and one 16-byte chunk of the k8 layout
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)Bp * kIn1) return;
-    const int m = (int)(i / kIn1), c = (int)(i % kIn1);
-    float v = 0.0f;
-    if (m < B) {
-        if (c < nf) v = feat[(size_t)traj[m] * nf + c];
-        else if (c < nf + np) v = x[(size_t)m * np + (c - nf)];
+    if (i >= (int64_t)(Bp / 8) * kIn1) return;
+    const int grp = (int)(i / kIn1), c = (int)(i % kIn1);
+    uint16_t h[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int m = 8 * grp + p;
+        float v = 0.0f;
+        if (m < B) {
+            if (c < nf) v = feat[(size_t)traj[m] * nf + c];
+            else if (c < nf + np) v = x[(size_t)m * np + (c - nf)];
+        }
+        h[p] = f2bf(v);
+        in1[(int64_t)m * kIn1 + c] = h[p];
     }
-    const uint16_t h = f2bf(v);
-    in1[i] = h;
-    if (in1_k8) in1_k8[((int64_t)(m >> 3) * kIn1 + c) * 8 + (m & 7)] = h;
+    if (in1_k8) {
+        uint4 pk;
+        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        pk.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+        pk.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+        *reinterpret_cast<uint4 *>(in1_k8 + i * 8) = pk;
+    }
 }
 
 // Inference, trajectory part of layer 1 folded into a bias:
@@ -338,8 +455,8 @@ __global__ __launch_bounds__(256) void output_layer(const uint16_t *__restrict__
 
 // Output layer of a training step, 64 points per block (16 per wave, lane j owning units
 // j + 64 q): y = b4 + W4 . h3, d = y - target, dy = 2 d / B, and the start of the backward
-// pass dz3 = dy W4 silu'(z3), stored in BF16 row-major and in the k8 layout (8 points at a
-// time, one 16-byte store per unit).  The block's sums, in a fixed order, go to
+// pass dz3 = dy W4 silu'(z3) (silu'(z3) as the forward epilogue stored it, in BF16), stored
+// in BF16 row-major and in the k8 layout (8 points at a time, one 16-byte store per unit).  The block's sums, in a fixed order, go to
 // part[block][0 .. 513): the b3 gradient (sum of dz3, FP32), the W4 gradient (sum of
 // dy h3), the b4 gradient (sum of dy), then the sum of d^2.  Rows B..Bp-1 are padding:
 // every output there is zero.
@@ -352,7 +469,7 @@ __global__ __launch_bounds__(256) void output_grad_kernel(const uint16_t *__rest
                                                           const uint16_t *__restrict__ W4b,
                                                           const float *__restrict__ b4, int B,
                                                           const float *__restrict__ target,
-                                                          const float *__restrict__ z3,
+                                                          const uint16_t *__restrict__ ds3,
                                                           uint16_t *__restrict__ dzb, uint16_t *__restrict__ dz_k8,
                                                           float *__restrict__ part)
 {
@@ -365,27 +482,41 @@ __global__ __launch_bounds__(256) void output_grad_kernel(const uint16_t *__rest
     const float inv = 2.0f / (float)B;
     for (int grp = 0; grp < 2; ++grp) {
         const int64_t mg = (int64_t)blockIdx.x * kOutPoints + wave * 16 + grp * 8;   // multiple of 8
-        uint16_t hv[4][8];
-        for (int p = 0; p < 8; ++p) {
-            const int64_t m = mg + p;
-            float hq[4], acc = 0.0f;
+        // all loads of the 8 points first, then their 8 reductions side by side
+        float hq[8][4], zq[8][4], acc[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                hq[q] = bf2f(h3[m * kWidth + lane + 64 * q]);
-                acc += w4[q] * hq[q];
+                const int64_t o = (mg + p) * kWidth + lane + 64 * q;
+                hq[p][q] = bf2f(h3[o]);
+                zq[p][q] = bf2f(ds3[o]);
             }
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            acc[p] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p] += w4[q] * hq[p][q];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int p = 0; p < 8; ++p) acc[p] += __shfl_xor(acc[p], off, 64);
+        uint16_t hv[4][8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int64_t m = mg + p;
             const bool real = m < B;
-            const float d = real ? acc + b4[0] - target[m] : 0.0f;
+            const float d = real ? acc[p] + b4[0] - target[m] : 0.0f;
             const float gdy = inv * d;
             sdy += gdy;
             ssq += d * d;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t o = m * kWidth + lane + 64 * q;
-                const float dz = real ? gdy * w4[q] * dsilu(z3[o]) : 0.0f;
+                const float dz = real ? gdy * w4[q] * zq[p][q] : 0.0f;
                 sb3[q] += dz;
-                sw4[q] += gdy * hq[q];
+                sw4[q] += gdy * hq[p][q];
                 hv[q][p] = f2bf(dz);
                 dzb[o] = hv[q][p];
             }
@@ -637,44 +768,44 @@ hipError_t launch_rows(int epi, const RowsArgs &g, hipStream_t st)
 
 hipError_t launch_k8(const K8Args &g, int splits, hipStream_t st)
 {
-    if (g.M != kWidth || (g.N != kWidth && g.N != kIn1) || g.kslice % 16 || splits < 1) return hipErrorInvalidValue;
+    if (g.M != kWidth || (g.N != kWidth && g.N != kIn1) || g.kslice < 32 || g.kslice % 32 || splits < 1)
+        return hipErrorInvalidValue;
+    K8Args a = g;
+    a.splits = splits;
     if (g.N == kWidth)
-        hipLaunchKernelGGL((gemm_k8_kernel<2, 2>), dim3(2u, 2u, (unsigned)splits), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_k8_kernel<2, 2>), dim3(4u * (unsigned)splits), dim3(512), 0, st, a);
     else
-        hipLaunchKernelGGL((gemm_k8_kernel<4, 1>), dim3(1u, 1u, (unsigned)splits), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_k8_kernel<4, 1>), dim3((unsigned)splits), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float *x, int64_t ld, int M, int N, float *part, int slices, float *out,
-                         hipStream_t st)
+hipError_t launch_finish_grad(FinishArgs f, hipStream_t st)
 {
-    // pass 1: 64 columns x 4 row lanes per block over `slices` row slices; pass 2: 16 x 16
-    if (M < 1 || N < 1 || slices < 1) return hipErrorInvalidValue;
-    const int nb1 = 64, nb2 = 16;
-    const int rows_per = (M + slices - 1) / slices;
-    const int used = (M + rows_per - 1) / rows_per;
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + nb1 - 1) / nb1), (unsigned)used), dim3(256), 0, st, x, ld,
-                       M, N, nb1, rows_per, part, (int64_t)N);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + nb2 - 1) / nb2), 1u), dim3(256), 0, st, part, (int64_t)N,
-                       used, N, nb2, used, out, (int64_t)N);
-    return hipGetLastError();
-}
-
-hipError_t launch_sum_slices(const float *part, int slices, int rows, int src_cols, int n_cols, float *out,
-                             int64_t out_stride, hipStream_t st)
-{
-    const int64_t items = (int64_t)rows * n_cols;
-    hipLaunchKernelGGL(sum_slices, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, part, slices,
-                       (int64_t)rows * src_cols, out, out_stride, n_cols, src_cols);
+    int blocks = 0;
+    for (FinishW &w : f.w) {
+        if (w.slices < 1 || w.n_cols < 1 || w.n_cols > w.src_cols) return hipErrorInvalidValue;
+        const bool v4 = w.n_cols % 4 == 0 && w.src_cols % 4 == 0 &&
+                        ((uintptr_t)w.part % 16) == 0;
+        if (w.n_cols % 4 == 0 && !v4) return hipErrorInvalidValue;
+        const int64_t items = (int64_t)kWidth * (w.n_cols % 4 == 0 ? w.n_cols / 4 : w.n_cols);
+        w.blocks = (int)((items + 255) / 256);
+        blocks += w.blocks;
+    }
+    for (FinishC &c : f.c) {
+        if (c.M < 1 || c.N < 1 || c.split < 0 || c.split > c.N || (c.split < c.N && !c.out2))
+            return hipErrorInvalidValue;
+        c.blocks = (c.N + 3) / 4;
+        blocks += c.blocks;
+    }
+    hipLaunchKernelGGL(finish_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, f);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble_in1(const float *feat, int nf, const int *traj, const float *x, int np, int B, int Bp,
                                uint16_t *in1, uint16_t *in1_k8, hipStream_t st)
 {
-    const int64_t n = (int64_t)Bp * kIn1;
+    if (Bp % 8) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(Bp / 8) * kIn1;
     hipLaunchKernelGGL(assemble_in1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, feat, nf, traj, x, np,
                        B, Bp, in1, in1_k8);
     return hipGetLastError();
@@ -705,12 +836,12 @@ hipError_t launch_output(const uint16_t *h3, const uint16_t *W4b, const float *b
 }
 
 hipError_t launch_output_grad(const uint16_t *h3, const uint16_t *W4b, const float *b4, int B, int Bp,
-                              const float *target, const float *z3, uint16_t *dzb, uint16_t *dz_k8, float *part,
+                              const float *target, const uint16_t *ds3, uint16_t *dzb, uint16_t *dz_k8, float *part,
                               hipStream_t st)
 {
     if (Bp % kOutPoints) return hipErrorInvalidValue;
     hipLaunchKernelGGL(output_grad_kernel, dim3((unsigned)(Bp / kOutPoints)), dim3(256), 0, st, h3, W4b, b4, B, target,
-                       z3, dzb, dz_k8, part);
+                       ds3, dzb, dz_k8, part);
     return hipGetLastError();
 }
 

@@ -73,12 +73,15 @@ MlpLayout make_layout(int nf, int np)
 // Workspace carve-up for a padded batch Bp and n_traj trajectories.
 struct MWs {
     uint16_t *in1, *in1_k8, *h1, *h2, *h3, *h1_k8, *h2_k8, *dzA, *dzB, *dz_k8;
-    float *z1, *z2, *z3, *y, *part, *opart, *colpart, *cpart, *cb;
+    uint16_t *ds1, *ds2, *ds3;   // silu' of the layers' pre-activations (BF16)
+    float *y, *cb;
+    float *part[3];      // split-K partials of the W3, W2, W1 gradients
+    float *opart;        // output-layer partials [Bp / 64][514]
+    float *colpart[2];   // column partials of dz2, dz1 [Bp / 128][256]
     size_t total;
 };
 
 constexpr int kSplits = 64;     // most split-K slices of the weight-gradient products
-constexpr int kColSlices = 256; // row slices of the column sums (pass 1 runs N/64 x 256 blocks)
 
 // Inference needs the folded biases, and unless the fused kernel runs (n_point <= 8)
 // also h1..h3 and y (about 1.5 KB per point).
@@ -117,14 +120,13 @@ MWs carve(char *base, int64_t Bp, int n_traj)
     w.dzA = (uint16_t *)take(act * 2);
     w.dzB = (uint16_t *)take(act * 2);
     w.dz_k8 = (uint16_t *)take(act * 2);
-    w.z1 = (float *)take(act * 4);
-    w.z2 = (float *)take(act * 4);
-    w.z3 = (float *)take(act * 4);
+    w.ds1 = (uint16_t *)take(act * 2);
+    w.ds2 = (uint16_t *)take(act * 2);
+    w.ds3 = (uint16_t *)take(act * 2);
     w.y = (float *)take((size_t)Bp * 4);
-    w.part = (float *)take((size_t)kSplits * kWidth * kWidth * 4);
+    for (int l = 0; l < 3; ++l) w.part[l] = (float *)take((size_t)kSplits * kWidth * (l == 2 ? kIn1 : kWidth) * 4);
     w.opart = (float *)take((size_t)(Bp / kOutPointsHost) * kOutPartHost * 4);
-    w.colpart = (float *)take((size_t)(Bp / kRowBlock) * kWidth * 4);
-    w.cpart = (float *)take((size_t)kColSlices * kOutPartHost * 4);
+    for (int l = 0; l < 2; ++l) w.colpart[l] = (float *)take((size_t)(Bp / kRowBlock) * kWidth * 4);
     w.cb = (float *)take((size_t)std::max(n_traj, 1) * kWidth * 4);
     w.total = o;
     return w;
@@ -337,43 +339,42 @@ rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const i
     // forward: h = silu(z) row-major for the next layer, and in the k8 layout (batch rows
     // interleaved by 8) for the weight gradients
     CK(launch_assemble_in1(feat, L.n_feat, traj, x, L.n_point, B, Bp, w.in1, w.in1_k8, st));
-    RowsArgs g{w.in1, m->W1p, Bp, kIn1, m->p + L.b1, nullptr, w.z1, w.h1, w.h1_k8, nullptr};
+    RowsArgs g{w.in1, m->W1p, Bp, kIn1, m->p + L.b1, nullptr, w.ds1, w.h1, w.h1_k8, nullptr};
     CK(launch_rows(kEpiFwd, g, st));
-    g = RowsArgs{w.h1, m->W2, Bp, kWidth, m->p + L.b2, nullptr, w.z2, w.h2, w.h2_k8, nullptr};
+    g = RowsArgs{w.h1, m->W2, Bp, kWidth, m->p + L.b2, nullptr, w.ds2, w.h2, w.h2_k8, nullptr};
     CK(launch_rows(kEpiFwd, g, st));
-    g = RowsArgs{w.h2, m->W3, Bp, kWidth, m->p + L.b3, nullptr, w.z3, w.h3, nullptr, nullptr};
+    g = RowsArgs{w.h2, m->W3, Bp, kWidth, m->p + L.b3, nullptr, w.ds3, w.h3, nullptr, nullptr};
     CK(launch_rows(kEpiFwd, g, st));
-    // output layer: loss, dz3, and the b3, W4, b4 gradients and the loss as column sums of
-    // its per-block partials (b3, W4, b4 are contiguous in the parameter vector)
-    CK(launch_output_grad(w.h3, m->W4, m->p + L.b4, B, Bp, target, w.z3, w.dzA, w.dz_k8, w.opart, st));
+    // output layer: loss, dz3, and the per-block partials of the b3, W4, b4 gradients and
+    // the loss (b3, W4, b4 are contiguous in the parameter vector)
+    CK(launch_output_grad(w.h3, m->W4, m->p + L.b4, B, Bp, target, w.ds3, w.dzA, w.dz_k8, w.opart, st));
     static_assert(kOutPartHost == 2 * kWidth + 2, "partials: b3, W4, b4, loss");
-    CK(launch_colsum(w.opart, kOutPartHost, Bp / kOutPointsHost, 2 * kWidth + 1, w.cpart, kColSlices, grad + L.b3,
-                     st));
-    CK(launch_colsum(w.opart + 2 * kWidth + 1, kOutPartHost, Bp / kOutPointsHost, 1, w.cpart, kColSlices, loss_sum,
-                     st));
-    // layers 3, 2, 1: dW = dz^T h_prev from the k8 layouts (split over the batch), then
-    // dz_prev = (dz W) silu'(z_prev) with the column sums of dz_prev (the bias gradient)
+    // layers 3, 2, 1: split-K partials of dW = dz^T h_prev from the k8 layouts, then
+    // dz_prev = (dz W) silu'(z_prev) with the per-block column sums of dz_prev
     const uint16_t *hprev_k8[3] = {w.h2_k8, w.h1_k8, w.in1_k8};
     const int nprev[3] = {kWidth, kWidth, kIn1};
-    const int64_t woff[3] = {L.w3, L.w2, L.w1};
-    const int64_t boff[2] = {L.b2, L.b1};
     const uint16_t *WT[2] = {m->W3T, m->W2T};
-    const float *zprev[2] = {w.z2, w.z1};
+    const uint16_t *dsprev[2] = {w.ds2, w.ds1};
     uint16_t *dz_cur = w.dzA, *dz_next = w.dzB;
     for (int l = 0; l < 3; ++l) {
-        K8Args k8{w.dz_k8, hprev_k8[l], kWidth, nprev[l], (int64_t)Bp / splits, w.part};
+        K8Args k8{w.dz_k8, hprev_k8[l], kWidth, nprev[l], (int64_t)Bp / splits, w.part[l]};
         CK(launch_k8(k8, splits, st));
-        const int ncols = l == 2 ? L.n_in : kWidth;
-        CK(launch_sum_slices(w.part, splits, kWidth, nprev[l], ncols, grad + woff[l], ncols, st));
         if (l < 2) {
-            g = RowsArgs{dz_cur, WT[l], Bp, kWidth, nullptr, zprev[l], nullptr, dz_next, w.dz_k8, w.colpart};
+            g = RowsArgs{dz_cur, WT[l], Bp, kWidth, nullptr, dsprev[l], nullptr, dz_next, w.dz_k8, w.colpart[l]};
             CK(launch_rows(kEpiBwd, g, st));
-            CK(launch_colsum(w.colpart, kWidth, Bp / kRowBlock, kWidth, w.cpart, kColSlices, grad + boff[l], st));
             uint16_t *t = dz_cur;
             dz_cur = dz_next;
             dz_next = t;
         }
     }
+    // every reduction into the gradient vector, in one launch
+    FinishArgs f{};
+    const int64_t woff[3] = {L.w3, L.w2, L.w1};
+    for (int l = 0; l < 3; ++l) f.w[l] = FinishW{w.part[l], splits, nprev[l], l == 2 ? L.n_in : kWidth, grad + woff[l], 0};
+    f.c[0] = FinishC{w.opart, kOutPartHost, Bp / kOutPointsHost, 2 * kWidth + 2, 2 * kWidth + 1, grad + L.b3, loss_sum, 0};
+    f.c[1] = FinishC{w.colpart[0], kWidth, Bp / kRowBlock, kWidth, kWidth, grad + L.b2, nullptr, 0};
+    f.c[2] = FinishC{w.colpart[1], kWidth, Bp / kRowBlock, kWidth, kWidth, grad + L.b1, nullptr, 0};
+    CK(launch_finish_grad(f, st));
 #undef CK
     return RAD_OK;
 }
