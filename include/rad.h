@@ -248,6 +248,25 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
                      rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
                      void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * rad_cells with the mask in DEVICE memory (uint8 [n_segs][n_w][n_cells]), read by the
+ * kernels when they run, so that a mask computed on the device (the sampler's
+ * selection) needs no copy to the host and nothing waits for `stream`.  The launch
+ * covers every (segment, cell, block of 64 photon energies); a block whose energies
+ * have no mask bit set leaves at once, so the work done is that of rad_cells.  The
+ * sums are those of rad_cells, but the time axis is cut into chunks planned for every
+ * cell (rad_cells plans them for the masked cells only, and cuts finer when few are
+ * masked), so the results equal rad_cells' to rounding, bitwise where the two plans
+ * coincide (a full mask).  The workspace holds partial amplitudes for every cell
+ * (ws_bytes >= rad_cells_device_workspace_bytes(...), which needs no mask).  Errors as rad_cells, plus RAD_EINVAL for a mask that is not
+ * n_segs * n_w * n_cells bytes of device memory.
+ */
+size_t rad_cells_device_workspace_bytes(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                                        rad_precision prec, int cx, int cy);
+rad_status rad_cells_device(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                            rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
+                            void *ws, size_t ws_bytes, void *stream);
+
 /* Static text of a status code. */
 const char *rad_status_string(rad_status status);
 

@@ -68,6 +68,23 @@ struct AmpLaunch {
     int64_t part_len;      // elements of `part` (index checks of the RAD_DEBUG build)
     unsigned *counter;     // ticket of the persistent form (zeroed before the launch)
     int rec;               // FP64: phase factors by recurrence (every segment's dth != 0)
+    // cell refinement with a device mask: the items were compacted on the device and
+    // only the first *n_live of them run (the blocks past it return at once); null
+    // otherwise
+    const int *n_live;
+};
+
+// Device-side compaction of the cell refinement's items: items (in launch order) whose
+// photon-energy block has a mask bit set, for pseudo-segment p = (p / n_cells, p % n_cells)
+// = (segment, cell), keep their order in `live`, their number in *n_live.
+struct CellCompact {
+    const int4 *items;
+    int64_t n_items;
+    const uint8_t *mask;     // [n_segs][n_w][n_cells]
+    int n_cells, n_w, wg;
+    int *flags;              // [n_items]
+    int4 *live;              // [n_items]
+    int *n_live;
 };
 
 // Finalize: per output, the segments that feed it, in segment order.

@@ -104,7 +104,9 @@ struct AmpSmem {
 
 // One work item b = (segment, time chunk, direction-tile group, photon-energy
 // block) of an amplitude launch, computed by the whole block.
-template <int TX, int TY, bool WITHJ, bool MIXED, bool REC>
+// CELLS: the one-block-per-item launches, which serve the cell refinement's device
+// mask; the persistent form never does, and leaves the check out of its code.
+template <int TX, int TY, bool WITHJ, bool MIXED, bool REC, bool CELLS = true>
 __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ, MIXED> &sm)
 {
     constexpr int NP = TX * TY;
@@ -113,6 +115,9 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     double *const s_px = sm.px;
     double *const s_py = sm.py;
 
+    // cell refinement with a device mask: the live items were compacted to the front
+    // of the list, and the blocks past them leave at once
+    if (CELLS && L.n_live && b >= (int64_t)__builtin_amdgcn_readfirstlane(*L.n_live)) return;
     // segment and coordinates of this item: from the explicit list, or the
     // last segment s with block_begin <= b
     int chunk = 0, grp = 0, wb = 0;
@@ -517,7 +522,7 @@ __global__ __launch_bounds__(kBlock, MINB) void amp_persistent(AmpLaunch L)
         __syncthreads();   // all lanes hold the ticket before thread 0 may take the next
         return t;
     };
-    for (int64_t b = ticket(); b < L.n_blocks; b = ticket()) amp_item<TX, TY, WITHJ, MIXED, REC>(L, b, sm);
+    for (int64_t b = ticket(); b < L.n_blocks; b = ticket()) amp_item<TX, TY, WITHJ, MIXED, REC, false>(L, b, sm);
 }
 
 // Tickets start at zero for every launch (a kernel, so graphs hold no memset node).
@@ -793,6 +798,8 @@ hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, i
 {
     // the kernel shifts by log2(nt) (an occupancy query passes no launch)
     if (!occupancy && L.nt != 1 && L.nt != 2 && L.nt != 4) return hipErrorInvalidValue;
+    // compacted cell items need the item list and the one-block-per-item form
+    if (L.n_live && (grid_blocks > 0 || !L.items)) return hipErrorInvalidValue;
     if (withj)
         return mixed ? launch_amp_v<true, true>(L, variant, grid_blocks, st, occupancy)
                      : launch_amp_v<true, false>(L, variant, grid_blocks, st, occupancy);
@@ -804,6 +811,65 @@ hipError_t launch_cells_fin(const CellsFin &F, hipStream_t st)
 {
     const int64_t total = (int64_t)F.n_segs * F.n_cells * F.n_w;
     hipLaunchKernelGGL(cells_fin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, F);
+    return hipGetLastError();
+}
+
+// Cell compaction, pass 1: one wave per item, flags[i] = 1 if any photon energy of the
+// item's block has its mask bit set for the item's (segment, cell).
+__global__ __launch_bounds__(256) void cell_flags_kernel(CellCompact C)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (i >= C.n_items) return;
+    const int4 it = C.items[i];
+    const int s = it.x / C.n_cells, c = it.x % C.n_cells;
+    int any = 0;
+    for (int k = lane; k < C.wg * kWave; k += kWave) {
+        const int w = it.w * C.wg * kWave + k;
+        if (w < C.n_w) any |= C.mask[((int64_t)s * C.n_w + w) * C.n_cells + c] != 0;
+    }
+    any = __any(any);
+    if (lane == 0) C.flags[i] = any;
+}
+
+// Pass 2: one block of 1024 threads scans the flags tile by tile in order and writes the
+// flagged items to live[0 .. n), n to *n_live (order kept: the launch order of the plan).
+__global__ __launch_bounds__(1024) void cell_compact_kernel(CellCompact C)
+{
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    if (t == 0) base = 0;
+    __syncthreads();
+    for (int64_t t0 = 0; t0 < C.n_items; t0 += 1024) {
+        const int64_t i = t0 + t;
+        const int f = i < C.n_items ? C.flags[i] : 0;
+        const uint64_t bal = __ballot(f);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));   // flagged lanes below this one
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wave; ++w) off += wsum[w];
+        if (f) C.live[off + before] = C.items[i];
+        __syncthreads();
+        if (t == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (t == 0) *C.n_live = base;
+}
+
+hipError_t launch_cell_compact(const CellCompact &C, hipStream_t st)
+{
+    if (C.n_items < 1 || C.n_cells < 1 || C.wg < 1) return hipErrorInvalidValue;
+    const int64_t threads = C.n_items * kWave;
+    hipLaunchKernelGGL(cell_flags_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cell_compact_kernel, dim3(1), dim3(1024), 0, st, C);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, i
                       hipStream_t st, int *occupancy);
 hipError_t launch_reset(unsigned *counters, int n, hipStream_t st);
 hipError_t launch_cells_fin(const CellsFin &F, hipStream_t st);
+hipError_t launch_cell_compact(const CellCompact &C, hipStream_t st);
 hipError_t launch_fin(const FinLaunch &F, hipStream_t st);
 hipError_t launch_phase(const double *turns, int64_t n, int mixed, double *c, double *s, hipStream_t st);
 hipError_t launch_angle(const double *cube, const double *wx, const double *wy, int n_x, int n_y,
@@ -913,18 +914,25 @@ struct CellsPlan {
     int n_segs = 0, ncx = 0, ncy = 0, n_cells = 0, n_wb = 0;
     int n_ps = 0;                 // active (segment, cell) pseudo-segments
     int64_t n_items = 0;
+    bool dense = false;           // device mask: every (segment, cell) pair, p = s * n_cells + c
     size_t off_ps, off_items, off_psof, off_mask, off_part, desc_bytes, total;
+    size_t off_flags = 0, off_live = 0, off_nlive = 0;   // device-mask compaction (dense plans)
     std::vector<char> host;
 };
 
 constexpr int kCellWg = 1;        // 64 photon energies per block, 4 direction tiles (one 8x8 cell)
 
+// The work of rad_cells for a host mask (only the selected (segment, cell, photon-energy
+// block) items), or, with mask == nullptr and dense set, for a device mask read by the
+// kernels themselves: every (segment, cell) pair and every block, items of unselected
+// blocks leaving at once.
 rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, int kind, int cx, int cy,
-                      const uint8_t *mask, bool fill, CellsPlan &C, int comps)
+                      const uint8_t *mask, bool fill, CellsPlan &C, int comps, bool dense = false)
 {
     if (!g) return fail(RAD_EINVAL, "grid is NULL");
     if (!segs || n_segs <= 0) return fail(RAD_EINVAL, "no segments");
-    if (!mask) return fail(RAD_EINVAL, "mask is NULL");
+    if (!mask && !dense) return fail(RAD_EINVAL, "mask is NULL");
+    C.dense = dense;
     if (kind != RAD_CLASSICAL && kind != RAD_SPIN0 && kind != RAD_SPINHALF)
         return fail(RAD_EINVAL, "kind must be exactly one of RAD_CLASSICAL, RAD_SPIN0, RAD_SPINHALF");
     if (cx != 8 || cy != 8) return fail(RAD_EUNSUPPORTED, "cells of %d x %d directions (8 x 8 supported)", cx, cy);
@@ -943,7 +951,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
         for (int c = 0; c < C.n_cells; ++c) {
             std::vector<int> blocks;
             for (int b = 0; b < C.n_wb; ++b) {
-                bool any = false;
+                bool any = dense;
                 for (int w = b * kWave * kCellWg; w < std::min(n_w, (b + 1) * kWave * kCellWg) && !any; ++w)
                     any = mask[((size_t)s * n_w + w) * C.n_cells + c] != 0;
                 if (any) blocks.push_back(b);
@@ -974,8 +982,13 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     C.off_ps = o; o = align_up(o + sizeof(SegDesc) * (size_t)std::max(C.n_ps, 1));
     C.off_items = o; o = align_up(o + sizeof(int4) * (size_t)std::max<int64_t>(items, 1));
     C.off_psof = o; o = align_up(o + sizeof(int) * psof.size());
-    C.off_mask = o; o = align_up(o + (size_t)n_segs * n_w * C.n_cells);
+    C.off_mask = o; o = align_up(o + (dense ? 0 : (size_t)n_segs * n_w * C.n_cells));
     C.desc_bytes = o;
+    if (dense) {   // written by the compaction kernels, not uploaded
+        C.off_flags = o; o = align_up(o + sizeof(int) * (size_t)std::max<int64_t>(items, 1));
+        C.off_live = o; o = align_up(o + sizeof(int4) * (size_t)std::max<int64_t>(items, 1));
+        C.off_nlive = o; o = align_up(o + sizeof(int));
+    }
     C.off_part = o;
     o = align_up(o + (size_t)sum_chunks * comps * cell_dirs * n_w * sizeof(double2));
     C.total = o;
@@ -985,7 +998,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     SegDesc *D = (SegDesc *)(C.host.data() + C.off_ps);
     int4 *I = (int4 *)(C.host.data() + C.off_items);
     std::memcpy(C.host.data() + C.off_psof, psof.data(), sizeof(int) * psof.size());
-    std::memcpy(C.host.data() + C.off_mask, mask, (size_t)n_segs * n_w * C.n_cells);
+    if (!dense) std::memcpy(C.host.data() + C.off_mask, mask, (size_t)n_segs * n_w * C.n_cells);
     // launch order: longest segment first
     std::vector<int> order(C.n_ps);
     std::iota(order.begin(), order.end(), 0);
@@ -1030,23 +1043,10 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     return RAD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t rad_cells_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int kind,
-                                 rad_precision prec, int cx, int cy, const uint8_t *mask)
-{
-    if (!valid_prec(prec)) return 0;
-    CellsPlan C;
-    if (cells_plan(g, segs, n_segs, kind, cx, cy, mask, false, C, kind == RAD_SPINHALF ? 3 : 2) != RAD_OK)
-        return 0;
-    return C.total;
-}
-
-rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
-                     rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
-                     void *ws, size_t ws_bytes, void *stream)
+// rad_cells (host mask) and rad_cells_device (device mask, dense plan).
+rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind, rad_precision prec,
+                     int cx, int cy, const uint8_t *mask, bool dev_mask, double *cell_out, void *ws,
+                     size_t ws_bytes, void *stream)
 {
     rad_grid *g = const_cast<rad_grid *>(grid);
     rad_status rs = check_grid(g);
@@ -1059,8 +1059,13 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     }
     const int comps = kind == RAD_SPINHALF ? 3 : 2;
     CellsPlan C;
-    rs = cells_plan(g, segs, n_segs, kind, cx, cy, mask, true, C, comps);
+    if (dev_mask && !mask) return fail(RAD_EINVAL, "mask is NULL");
+    rs = cells_plan(g, segs, n_segs, kind, cx, cy, dev_mask ? nullptr : mask, true, C, comps, dev_mask);
     if (rs != RAD_OK) return rs;
+    if (dev_mask) {
+        rs = check_dev_range(mask, (size_t)n_segs * g->n_w * C.n_cells, "mask");
+        if (rs != RAD_OK) return rs;
+    }
     if (!ws) return fail(RAD_EINVAL, "workspace is NULL");
     if (ws_bytes < C.total) return fail(RAD_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, C.total);
     rs = check_dev_range(ws, C.total, "workspace");
@@ -1091,6 +1096,24 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
         L.part = part;
         L.part_len = (int64_t)((C.total - C.off_part) / sizeof(double2));
         L.counter = nullptr;
+        if (dev_mask) {
+            // the items whose block has a mask bit set, compacted to the front in launch
+            // order; the launch keeps every item's block and the rest return at once
+            CellCompact K{};
+            K.items = L.items;
+            K.n_items = C.n_items;
+            K.mask = mask;
+            K.n_cells = C.n_cells;
+            K.n_w = g->n_w;
+            K.wg = kCellWg;
+            K.flags = (int *)(wsb + C.off_flags);
+            K.live = (int4 *)(wsb + C.off_live);
+            K.n_live = (int *)(wsb + C.off_nlive);
+            hipError_t ec = launch_cell_compact(K, st);
+            if (ec != hipSuccess) return hip_fail(ec, "cell compaction launch");
+            L.items = K.live;
+            L.n_live = K.n_live;
+        }
         const bool mixed = prec == RAD_MIXED;
         const bool prof = profiling_on();
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1110,7 +1133,7 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     CellsFin F{};
     F.segs = (const SegDesc *)(wsb + C.off_ps);
     F.psof = (const int *)(wsb + C.off_psof);
-    F.mask = (const uint8_t *)(wsb + C.off_mask);
+    F.mask = dev_mask ? mask : (const uint8_t *)(wsb + C.off_mask);
     F.part = part;
     F.part_len = (int64_t)((C.total - C.off_part) / sizeof(double2));
     F.comps = comps;
@@ -1129,6 +1152,44 @@ rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     hipError_t e = launch_cells_fin(F, st);
     if (e != hipSuccess) return hip_fail(e, "cell finalize launch");
     return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rad_cells_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int kind,
+                                 rad_precision prec, int cx, int cy, const uint8_t *mask)
+{
+    if (!valid_prec(prec)) return 0;
+    CellsPlan C;
+    if (cells_plan(g, segs, n_segs, kind, cx, cy, mask, false, C, kind == RAD_SPINHALF ? 3 : 2) != RAD_OK)
+        return 0;
+    return C.total;
+}
+
+rad_status rad_cells(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                     rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
+                     void *ws, size_t ws_bytes, void *stream)
+{
+    return cells_run(grid, segs, n_segs, kind, prec, cx, cy, mask, false, cell_out, ws, ws_bytes, stream);
+}
+
+size_t rad_cells_device_workspace_bytes(const rad_grid *g, const rad_segment *segs, int n_segs, int kind,
+                                        rad_precision prec, int cx, int cy)
+{
+    if (!valid_prec(prec)) return 0;
+    CellsPlan C;
+    if (cells_plan(g, segs, n_segs, kind, cx, cy, nullptr, false, C, kind == RAD_SPINHALF ? 3 : 2, true) != RAD_OK)
+        return 0;
+    return C.total;
+}
+
+rad_status rad_cells_device(const rad_grid *grid, const rad_segment *segs, int n_segs, int kind,
+                            rad_precision prec, int cx, int cy, const uint8_t *mask, double *cell_out,
+                            void *ws, size_t ws_bytes, void *stream)
+{
+    return cells_run(grid, segs, n_segs, kind, prec, cx, cy, mask, true, cell_out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

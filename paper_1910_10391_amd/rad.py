@@ -78,6 +78,8 @@ def load(path):
         "rad_plan_free": (None, [P]),
         "rad_cells_workspace_bytes": (S, [P, SP, I, I, I, I, I, P]),
         "rad_cells": (I, [P, SP, I, I, I, I, I, P, P, P, S, P]),
+        "rad_cells_device_workspace_bytes": (S, [P, SP, I, I, I, I, I]),
+        "rad_cells_device": (I, [P, SP, I, I, I, I, I, P, P, P, S, P]),
         "rad_tune_num_variants": (I, []),
         "rad_profile_enable": (I, [I]),
         "rad_profile_read": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]),
@@ -313,11 +315,28 @@ def angle_integrate(grid, cubes, out=None, stream=None):
 def cells(grid, segs, kind, mask, precision=FP64, cx=8, cy=8, out=None, workspace=None,
           stream=None):
     """Exact cell integrals [n_segs, n_w, n_cells] where ``mask`` (uint8, same shape) is set
-    (rad_cells): the ``kind`` spectrum summed over each cx x cy cell times dthx dthy."""
+    (rad_cells): the ``kind`` spectrum summed over each cx x cy cell times dthx dthy.  A
+    mask that is a device tensor stays on the device (rad_cells_device)."""
     import torch
     ds = _as_segments(segs)
     n_w, n_y, n_x = grid.shape
     n_cells = (n_x // cx) * (n_y // cy)
+    if isinstance(mask, torch.Tensor) and mask.is_cuda:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != (len(ds), n_w, n_cells) or not mask.is_contiguous():
+            raise ValueError("mask must be a contiguous uint8 tensor of shape %s" % ((len(ds), n_w, n_cells),))
+        nb = int(lib().rad_cells_device_workspace_bytes(grid.handle, ds.structs, len(ds), int(kind),
+                                                        int(precision), cx, cy))
+        if nb == 0:
+            raise RadError(1, "rad_cells_device_workspace_bytes: invalid arguments: %s"
+                           % lib().rad_last_error().decode())
+        ws = _workspace(nb, workspace, ds.data.device)
+        if out is None:
+            out = torch.empty((len(ds), n_w, n_cells), dtype=torch.float64, device=ds.data.device)
+        _check_out(out, (len(ds), n_w, n_cells))
+        _check(lib().rad_cells_device(grid.handle, ds.structs, len(ds), int(kind), int(precision), cx, cy,
+                                      _dptr(mask), _dptr(out), _dptr(ws), _nbytes(ws), _stream(stream)),
+               "rad_cells_device")
+        return out
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     if m.shape != (len(ds), n_w, n_cells):
         raise ValueError("mask must have shape %s" % ((len(ds), n_w, n_cells),))

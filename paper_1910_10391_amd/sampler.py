@@ -189,7 +189,7 @@ class Sampler:
                    "rad_sampler_combine")
         return out
 
-    def estimate(self, dsegs, precision=rad.MIXED, rule="learned"):
+    def estimate(self, dsegs, precision=rad.MIXED, rule="learned", phases=False):
         """dI/d hw [n_traj, n_w] and what it cost.
 
         rule "learned": cells chosen with the network's prediction (the sampler): by
@@ -198,14 +198,23 @@ class Sampler:
                         corrected estimate);
         rule "coarse":  cells ranked by the coarse centre value x area, with the same
                         coverage and cap and no fallback (refinement without a network,
-                        the comparison the sampler has to beat)."""
+                        the comparison the sampler has to beat).
+
+        Where no photon energy can fall back (the error-driven selection, the coarse
+        ranking, or a check tolerance tau = inf) the mask stays on the device
+        (rad_cells_device) and nothing waits for the GPU between the coarse step and
+        the combination; the selection by predicted mass with a finite tau copies the
+        fallback flags to the host, which decides which trajectories take the full
+        grid.  phases=True synchronises after every step to time it."""
         import torch
-        phases = {}
+        times = {}
 
         def mark(name, t_prev):
+            if not phases:
+                return t_prev
             torch.cuda.synchronize()
             t = time.perf_counter()
-            phases[name] = t - t_prev
+            times[name] = t - t_prev
             return t
 
         t0 = time.perf_counter()
@@ -230,14 +239,26 @@ class Sampler:
             fill = None
         else:
             raise ValueError("rule must be 'learned' or 'coarse'")
+        n_t = np.array(dsegs.n, dtype=np.float64)
+        n_w = g.hw.size
+        can_fall_back = rule == "learned" and self.select_rule != "error" and self.tau != float("inf")
+        if not can_fall_back:
+            t = mark("select", t)
+            cells = rad.cells(g.fine, dsegs, KIND, mask, precision)
+            t = mark("cells", t)
+            dIdw = self.combine(cells, mask, coarse, fill, None, None)
+            mark("combine", t)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            mask_h = mask.cpu().numpy()
+            fb_h = np.zeros(mask_h.shape[:2], dtype=np.uint8)
+            return self._result(dIdw, mask_h, fb_h, dt, times, n_t, n_w, 0.0)
         mask_h = mask.cpu().numpy()
         fb_h = fb.cpu().numpy()
         t = mark("select", t)
         # energies that fell back take the full-grid value itself: the trajectories that
         # have any run through the full-grid path (the same call as full_grid for the same
         # segments), and their cells are not integrated
-        n_t = np.array(dsegs.n, dtype=np.float64)
-        n_w = g.hw.size
         full = None
         fb_rows = np.flatnonzero(fb_h.any(axis=1))
         evals_fb = 0.0
@@ -257,13 +278,18 @@ class Sampler:
         t = mark("cells", t)
         dIdw = self.combine(cells, mask, coarse, fill, fb if full is not None else None, full)
         mark("combine", t)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        return self._result(dIdw, mask_h, fb_h, dt, times, n_t, n_w, evals_fb)
+
+    def _result(self, dIdw, mask_h, fb_h, dt, times, n_t, n_w, evals_fb):
         # evaluations: coarse centres + every direction of the refined cells (the selection
         # covers whole 64-energy blocks, and rad_cells evaluates exactly those) + the full
         # grid of trajectories with a fallback
-        evals_refine = float(np.sum(n_t * mask_h.reshape(len(dsegs), -1).sum(axis=1)) * CELL * CELL)
+        g = self.grids
+        evals_refine = float(np.sum(n_t * mask_h.reshape(len(n_t), -1).sum(axis=1)) * CELL * CELL)
         evals_coarse = float(np.sum(n_t) * n_w * g.n_cells)
-        return dict(dIdw=dIdw, mask=mask_h, fallback=fb_h, seconds=dt, phases=phases,
+        return dict(dIdw=dIdw, mask=mask_h, fallback=fb_h, seconds=dt, phases=times,
                     evals=evals_coarse + evals_refine + evals_fb, evals_full=float(np.sum(n_t) * n_w * g.n ** 2),
                     refined_cells_mean=float(mask_h.sum(axis=2).mean()))
 

@@ -54,10 +54,11 @@ def evaluate(smp, ds, full, precision, rule="learned", reps=1):
         r = smp.estimate(ds, precision=precision, rule=rule)
         if best is None or r["seconds"] < best["seconds"]:
             best = r
+    steps = smp.estimate(ds, precision=precision, rule=rule, phases=True)["phases"]   # synchronised, per step
     rel, peak = errors(best["dIdw"].cpu().numpy(), full)
     return dict(rule=rule, max_rel_err=float(rel.max()), p95_rel_err=float(np.percentile(rel, 95)),
                 max_peak_err=float(peak.max()), fallback_frac=float(best["fallback"].mean()),
-                refined_cells_mean=best["refined_cells_mean"], evals=best["evals"], phases=best["phases"],
+                refined_cells_mean=best["refined_cells_mean"], evals=best["evals"], phases=steps,
                 evals_full=best["evals_full"], seconds=best["seconds"])
 
 

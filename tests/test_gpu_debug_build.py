@@ -59,6 +59,10 @@ def test_debug_build_parity_without_index_violations(dbg):
     fine = oracle.spectrum(segs[4], hw, th, th, 4)[4]
     want = np.einsum("wyx,y,x->w", fine.reshape(70, 2, 8, 2, 8)[:, 1, :, 0, :], w[8:], w[:8])
     assert np.allclose(cells[4, 40:, 2], want[40:], rtol=1e-9, atol=0)
+    # the same cells with the mask on the device: the kernels read it, skipping blocks
+    import torch
+    cells_d = rad.cells(grid, segs, rad.SPINHALF, torch.from_numpy(mask).cuda()).cpu().numpy()
+    assert np.abs(cells_d - cells).max() <= 1e-12 * np.abs(cells).max() and not cells_d[mask == 0].any()
     plan.close()
     grid.close()
     n = D.rad_debug_violations(0)
