@@ -104,6 +104,17 @@ rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy,
                                const uint8_t *fallback, const double *full, double *dIdw, void *stream);
 
 /*
+ * Refinement without a network, the comparison the sampler has to beat: a stand-in
+ * prediction that ranks cells by their exact centre values.  pred (DEVICE float
+ * [n_traj][n_w][n_y][n_x]) = log(coarse[t][w][cell of the direction]) computed in FP64
+ * (-inf where the value is not positive); coarse: DEVICE double [n_traj][n_w][n_cells].
+ * With mu = 0, sigma = 1, rad_sampler_select then ranks cells by centre value x area.
+ * Errors: RAD_EINVAL for sizes or buffers out of range, cells that do not tile the grid.
+ */
+rad_status rad_sampler_coarse_pred(const rad_grid *fine, int n_traj, const double *coarse, int cx, int cy,
+                                   float *pred, void *stream);
+
+/*
  * Training data of the network (spectra the method itself computes).
  *
  * rad_sampler_targets: the angular shape of each of n_maps spectra S (DEVICE double

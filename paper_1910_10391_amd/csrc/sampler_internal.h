@@ -72,6 +72,8 @@ hipError_t launch_minibatch(const BatchLaunch &L, hipStream_t st);
 hipError_t launch_select(const SelectLaunch &L, hipStream_t st);
 hipError_t launch_select_error(const SelectLaunch &L, hipStream_t st);
 hipError_t launch_widen(uint8_t *mask, int n_traj, int n_w, int n_cells, hipStream_t st);
+hipError_t launch_coarse_pred(const double *coarse, int64_t n_maps, int n_x, int n_y, int cx, int cy, float *pred,
+                              hipStream_t st);
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t st);
 
 }  // namespace radsmp

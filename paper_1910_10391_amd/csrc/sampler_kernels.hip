@@ -395,6 +395,30 @@ __global__ __launch_bounds__(256) void minibatch_kernel(BatchLaunch L)
     L.target[b] = (float)(((double)v - L.moments[0]) / L.moments[1]);
 }
 
+// pred[m][y][x] = log(coarse[m][cell of (y, x)]) in FP64, stored as FP32 (-inf where the
+// value is not positive): one thread per fine direction.
+__global__ __launch_bounds__(256) void coarse_pred_kernel(const double *__restrict__ coarse, int64_t n, int n_x,
+                                                          int n_y, int cx, int cy, float *__restrict__ pred)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t dirs = (int64_t)n_x * n_y;
+    const int64_t m = i / dirs;
+    const int d = (int)(i % dirs), y = d / n_x, x = d % n_x;
+    const int ncx = n_x / cx, n_cells = ncx * (n_y / cy);
+    const double v = coarse[m * n_cells + (y / cy) * ncx + x / cx];
+    pred[i] = v > 0.0 ? (float)log(v) : -__builtin_huge_valf();
+}
+
+hipError_t launch_coarse_pred(const double *coarse, int64_t n_maps, int n_x, int n_y, int cx, int cy, float *pred,
+                              hipStream_t st)
+{
+    const int64_t n = n_maps * n_x * n_y;
+    hipLaunchKernelGGL(coarse_pred_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, coarse, n, n_x, n_y,
+                       cx, cy, pred);
+    return hipGetLastError();
+}
+
 hipError_t launch_targets(const double *S, int64_t n_maps, int n_dirs, float floor_rel, float *y, hipStream_t st)
 {
     hipLaunchKernelGGL(targets_kernel, dim3((unsigned)n_maps), dim3(256), 0, st, S, n_dirs, floor_rel, y);

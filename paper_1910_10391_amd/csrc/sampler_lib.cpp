@@ -149,6 +149,22 @@ rad_status rad_sampler_select_error(const rad_grid *fine, int n_traj, const floa
     return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "select_error: %s", hipGetErrorString(e));
 }
 
+rad_status rad_sampler_coarse_pred(const rad_grid *fine, int n_traj, const double *coarse, int cx, int cy, float *pred,
+                                   void *stream)
+{
+    rad::GridView v;
+    rad_status rs = view_of(fine, v);
+    if (rs != RAD_OK) return rs;
+    int n_cells = 0;
+    if ((rs = cells_shape(v, cx, cy, n_cells)) != RAD_OK) return rs;
+    if (n_traj <= 0) return sfail(RAD_EINVAL, "n_traj must be > 0");
+    const size_t maps = (size_t)n_traj * v.n_w;
+    if ((rs = srange(coarse, maps * n_cells * sizeof(double), "coarse")) != RAD_OK) return rs;
+    if ((rs = srange(pred, maps * v.n_x * v.n_y * sizeof(float), "pred")) != RAD_OK) return rs;
+    hipError_t e = launch_coarse_pred(coarse, (int64_t)maps, v.n_x, v.n_y, cx, cy, pred, (hipStream_t)stream);
+    return e == hipSuccess ? RAD_OK : sfail(RAD_EDEVICE, "coarse_pred: %s", hipGetErrorString(e));
+}
+
 rad_status rad_sampler_combine(const rad_grid *fine, int n_traj, int cx, int cy, const double *cells,
                                const uint8_t *mask, const double *coarse, const double *cell_pred,
                                const uint8_t *fallback, const double *full, double *dIdw, void *stream)

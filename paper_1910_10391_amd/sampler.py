@@ -53,6 +53,7 @@ def _lib():
             "rad_sampler_select": (I, [P, I, P, F, F, P, I, I, F, I, F, P, P, P, P]),
             "rad_sampler_select_error": (I, [P, I, P, F, F, P, I, I, F, I, P, P, P]),
             "rad_sampler_combine": (I, [P, I, I, I, P, P, P, P, P, P, P, P]),
+            "rad_sampler_coarse_pred": (I, [P, I, P, I, I, P, P]),
             "rad_sampler_targets": (I, [P, ctypes.c_int64, I, F, P, P]),
             "rad_sampler_moments_workspace_bytes": (S, []),
             "rad_sampler_moments": (I, [P, ctypes.c_int64, P, P, S, P]),
@@ -232,9 +233,9 @@ class Sampler:
                 mask, fb, pm = self.select(pred, coarse)
                 fill = pm if self.fill == "pred" else None
         elif rule == "coarse":
-            k = g.n // CELL
-            lc = torch.log(coarse.float()).view(len(dsegs), g.hw.size, k, k)
-            pred = lc.repeat_interleave(CELL, dim=2).repeat_interleave(CELL, dim=3).contiguous()
+            pred = torch.empty((len(dsegs), g.hw.size, g.n, g.n), dtype=torch.float32, device="cuda")
+            rad._check(_lib().rad_sampler_coarse_pred(g.fine.handle, len(dsegs), rad._dptr(coarse), CELL, CELL,
+                                                      rad._dptr(pred), rad._stream(None)), "rad_sampler_coarse_pred")
             mask, fb, _ = self.select(pred, coarse, tau=float("inf"), mu=0.0, sigma=1.0)
             fill = None
         else:

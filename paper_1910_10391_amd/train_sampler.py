@@ -174,7 +174,7 @@ def main(argv=None):
     # the coarse grid alone: every cell at its centre value x area
     c = smp.coarse(dt_, prec)
     area = float((2 * 5.0 / gamma / 8) ** 2)
-    rel, peak = errors((c.sum(dim=2) * area).cpu().numpy(), full)
+    rel, peak = errors(c.cpu().numpy().sum(axis=2) * area, full)
     res["coarse_only"] = dict(max_rel_err=float(rel.max()), max_peak_err=float(peak.max()))
     res["full_grid_seconds"] = min(t_full)
     for k in searches:

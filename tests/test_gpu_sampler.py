@@ -353,3 +353,28 @@ def test_training_data_kernels(S):
     tr = ((yn[ti, ei, pi] - mm[0]) / mm[1]).astype(np.float32)
     assert np.abs(t.cpu().numpy() - tr).max() < 1e-5
     assert len(np.unique(ti)) == 6 and len(np.unique(pi)) == 10
+
+
+def test_coarse_pred(S):
+    """The stand-in prediction of refinement without a network: log of each cell's exact
+    centre value at every fine direction of the cell (-inf where it is 0), against NumPy."""
+    import torch
+    from paper_1910_10391_amd import rad
+    rng = np.random.default_rng(43)
+    grid, th = _fine()
+    n_w = grid.shape[0]
+    coarse = rng.exponential(size=(2, n_w, 64)) * 10.0 ** rng.uniform(-20, 5, size=(2, n_w, 1))
+    coarse[1, 3, 5] = 0.0
+    cd = torch.from_numpy(coarse).cuda()
+    pred = torch.empty((2, n_w, 64, 64), dtype=torch.float32, device="cuda")
+    L = S._lib()
+    assert L.rad_sampler_coarse_pred(grid.handle, 2, rad._dptr(cd), 8, 8, rad._dptr(pred), None) == 0
+    with np.errstate(divide="ignore"):
+        want = np.log(coarse).reshape(2, n_w, 8, 1, 8, 1)
+    want = np.broadcast_to(want, (2, n_w, 8, 8, 8, 8)).reshape(2, n_w, 64, 64).astype(np.float32)
+    got = pred.cpu().numpy()
+    assert np.array_equal(np.isinf(got), np.isinf(want)) and np.isinf(got).sum() == 64
+    fin = np.isfinite(want)
+    assert np.allclose(got[fin], want[fin], rtol=2e-7, atol=0)
+    assert L.rad_sampler_coarse_pred(grid.handle, 2, rad._dptr(cd), 3, 8, rad._dptr(pred), None) == 1
+    assert L.rad_sampler_coarse_pred(grid.handle, 0, rad._dptr(cd), 8, 8, rad._dptr(pred), None) == 1
