@@ -181,7 +181,7 @@ def bench_sections(args):
                                "16x16 within 4/gamma; mixed precision, persistent plan replayed "
                                "from a hipGraph, autotuned" % (n, min(ds.n), max(ds.n)),
                    "segments": len(segs), "grid": list(grid.shape),
-                   "autotune": {k: v["variant"] for k, v in tune_p.items()}},
+                   "autotune": autotune.choices(tune_p)},
         "trajectories_per_s": n / dt_mx,
         "fp64_plain": {"value": evals / dt_64, "ms_per_step": dt_64 * 1e3},
         "speedup_vs_fp64_plain": dt_64 / dt_mx,
@@ -687,7 +687,7 @@ def leg_sections():
             "evals": evals,
             "mixed_graph": {"value": evals / dt_mx, "unit": "evals/s", "ms_per_step": dt_mx * 1e3,
                             "trajectories_per_s": n / dt_mx, "form": "persistent plan, hipGraph replay",
-                            "autotune": {k: v["variant"] for k, v in tune.items()}},
+                            "autotune": autotune.choices(tune)},
             "fp64_plain": {"value": evals / dt_64, "unit": "evals/s", "ms_per_step": dt_64 * 1e3,
                            "form": "rad_batch"},
             "speedup_mixed_graph_vs_fp64_plain": dt_64 / dt_mx,
@@ -779,7 +779,7 @@ def main():
                                           t_gen), file=sys.stderr, flush=True)
 
     tuned = autotune.tune(grid, ds, kinds, rad.FP64, persistent=True, sample=8)
-    print("bench: autotuned variants %s" % {k: v["variant"] for k, v in tuned.items()},
+    print("bench: autotuned %s (sample ms %s)" % (autotune.choices(tuned), {k: v["ms"] for k, v in tuned.items()}),
           file=sys.stderr, flush=True)
 
     if args.copy_calibration:
@@ -905,7 +905,7 @@ def main():
                                % (len(segs), min(ds.n), max(ds.n)),
                    "trajectories": len(segs), "samples": n_samples, "grid": list(grid.shape),
                    "kinds": "spin-1/2", "precision": "fp64", "form": "persistent plan (rad_plan_*)",
-                   "autotune": {k: v["variant"] for k, v in tuned.items()}},
+                   "autotune": autotune.choices(tuned)},
         "trajectories_per_s": len(segs) / dt,
         "mixed": mixed,
         "parity": parity,

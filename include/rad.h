@@ -290,6 +290,23 @@ rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *vari
 int rad_tune_num_variants(void);
 
 /*
+ * Launch-shape knobs (process-wide), also set by the autotuner.
+ * rad_tune_set_shape: the waves of a block spread over photon energies, wg = 1, 2 or 4
+ * (the block's other waves take further direction tiles: 4 / wg of them), per form and
+ * precision; 0 (the default) chooses by the grid: 4 above 128 energies, 2 above 64, else
+ * 1.  Every wg computes the same sums in the same order (the same bits).
+ * rad_tune_set_chunk_target: segments are cut into time chunks until a launch has this
+ * many work items (0, the default: 2048); the chunk sums then come in another order, so
+ * results change by rounding only.  It applies to every form, and changes the workspace
+ * sizes: query them after setting it.  RAD_EINVAL for wg outside {0, 1, 2, 4} or a target
+ * outside [0, 2^24].  rad_tune_get_chunk_target returns the target in force.
+ */
+rad_status rad_tune_set_shape(int persistent, int mixed, int wg);
+rad_status rad_tune_get_shape(int persistent, int mixed, int *wg);
+rad_status rad_tune_set_chunk_target(int64_t target_blocks);
+int64_t rad_tune_get_chunk_target(void);
+
+/*
  * Index checks of the debug build (compiled with -DRAD_DEBUG=1, librad_debug.so): the
  * kernels check descriptor, time-chunk and partial-amplitude indices against the
  * launch's bounds, count each violation and skip that access.  Returns the count since

@@ -1,13 +1,21 @@
-"""Autotuner of the amplitude kernel's variant (direction tile x occupancy).
+"""Autotuner of the amplitude kernel's launch shape.
 
-For a workload it times every variant the library offers on a sample of the
-longest segments (they dominate a batch), separately for each integral set the
-kinds need (with and without J) and for the form that will run (the
-one-block-per-item calls or the persistent plan), keeps the fastest, sets it in
-the library (``rad_tune_set_variant``) and records the choice in a JSON cache
-keyed by (form, precision, set, grid shape, length bucket), so that later runs
-on the same shape skip the search.  Timing is the amplitude kernel alone, from
-HIP events the library records on its stream.
+For a workload it times, on a sample of the longest segments (they dominate a
+batch) and for the form that will run (the one-block-per-item calls or the
+persistent plan):
+
+1. every variant the library offers (direction tile per lane x resident blocks),
+   separately for each integral set the kinds need (with and without J);
+2. the block's spread over photon energies (1, 2 or 4 of its 4 waves over
+   energies, the rest over further direction tiles) for the whole call;
+3. when the sample is the whole workload (so that its time chunking is the
+   workload's), the work-item target that sets the chunk length.
+
+It keeps the fastest of each, sets it in the library (``rad_tune_set_variant``,
+``rad_tune_set_shape``, ``rad_tune_set_chunk_target``) and records the choices in a
+JSON cache keyed by (form, precision, set or kinds, grid shape, length bucket), so
+that later runs on the same shape skip the search.  Timing is the amplitude kernel
+alone, from HIP events the library records on its stream.
 """
 from __future__ import annotations
 
@@ -61,6 +69,54 @@ def key(persistent, precision, with_j, grid, max_n):
                                       "j" if with_j else "noj", *grid.shape, bucket)
 
 
+def shape_key(persistent, precision, kinds, grid, max_n, what):
+    bucket = int(math.log2(max(int(max_n), 2)))
+    return "%s-%s-%s-k%d-%dx%dx%d-L%d" % (what, "plan" if persistent else "batch",
+                                          "mixed" if precision == rad.MIXED else "fp64", int(kinds),
+                                          *grid.shape, bucket)
+
+
+WG_CHOICES = (1, 2, 4)
+TARGET_CHOICES = (512, 1024, 2048, 4096, 8192, 16384)
+# A launch-shape choice other than the planner's own must beat it by this much on the
+# sample: the sample is the longest segments only, and a small gain on it need not hold
+# for the whole workload (measured: a 2-wave spread that timed marginally faster on the
+# benchmark's 8 longest segments ran the full launch 4 % slower).
+MARGIN = 0.03
+
+
+def default_wg(n_w):
+    """The planner's own spread over photon energies."""
+    return 4 if n_w > 128 else (2 if n_w > 64 else 1)
+
+
+def _search(cache, k, set_fn, choices, time_fn, result, verbose, field, default=None):
+    """Time every choice, keep and set the fastest (or the cached one); a choice other
+    than ``default`` must be MARGIN faster than it."""
+    if k in cache:
+        set_fn(cache[k][field])
+        result[k] = dict(cache[k], cached=True)
+        return False
+    times = {}
+    for c in choices:
+        set_fn(c)
+        times[c] = time_fn()
+        if verbose:
+            print("autotune %s %s %s: %.3f ms" % (k, field, c, times[c]), flush=True)
+    best = min(times, key=times.get)
+    if default in times and times[best] > (1.0 - MARGIN) * times[default]:
+        best = default
+    set_fn(best)
+    cache[k] = {field: best, "ms": {str(c): t for c, t in times.items()}}
+    result[k] = dict(cache[k], cached=False)
+    return True
+
+
+def choices(result):
+    """{cache key: the chosen variant, energy spread or chunk target} of a tune() result."""
+    return {k: next(r[f] for f in ("variant", "wg", "target") if f in r) for k, r in result.items()}
+
+
 def _time_variant(grid, sample, kinds, precision, persistent, reps):
     import torch
     n = len(sample)
@@ -104,12 +160,15 @@ def pick_sample(dsegs, grid, min_segments=8, min_evals=3e11):
 
 
 def tune(grid, dsegs, kinds, precision=rad.FP64, persistent=False, sample=8, min_evals=3e11,
-         reps=1, use_cache=True, verbose=False):
-    """Pick and set the fastest variant for every integral set of ``kinds``.
+         reps=1, use_cache=True, verbose=False, shape=True):
+    """Pick and set the fastest variant for every integral set of ``kinds``, then (with
+    ``shape``) the fastest spread over photon energies and, when the sample is the whole
+    workload, the fastest chunk target.
 
     ``dsegs`` is a ``rad.DeviceSegments``; the longest segments are timed: at least
     ``sample`` of them and at least ``min_evals`` terms.
-    Returns {cache key: {"variant": v, "ms": {variant: ms}, "cached": bool}}.
+    Returns {cache key: {"variant" | "wg" | "target": choice, "ms": {choice: ms},
+    "cached": bool}}.
     """
     path = cache_path()
     cache = _load(path) if use_cache else {}
@@ -144,6 +203,17 @@ def tune(grid, dsegs, kinds, precision=rad.FP64, persistent=False, sample=8, min
         cache[k] = {"variant": best, "ms": {str(v): t for v, t in times.items()}}
         result[k] = dict(cache[k], cached=False)
         changed = True
+    if shape:
+        time_call = lambda: _time_variant(grid, sub, kinds, precision, persistent, reps)   # noqa: E731
+        n_w = grid.shape[0]
+        wgs = [w for w in WG_CHOICES if w == 1 or n_w > 32 * w]     # at least half the block's energies exist
+        changed |= _search(cache, shape_key(persistent, precision, kinds, grid, max_n, "wg"),
+                           lambda w: rad.tune_set_shape(persistent, mixed, w), wgs, time_call, result, verbose,
+                           "wg", default=default_wg(n_w))
+        if len(order) == len(dsegs):
+            changed |= _search(cache, shape_key(persistent, precision, kinds, grid, max_n, "chunk"),
+                               rad.tune_set_chunk_target, TARGET_CHOICES, time_call, result, verbose, "target",
+                               default=2048)
     if changed and use_cache:
         _store(path, cache)
     return result

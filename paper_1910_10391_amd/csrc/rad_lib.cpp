@@ -126,6 +126,24 @@ int variant_for(bool persistent, bool mixed, bool withj)
     return g_variant[persistent ? 1 : 0][mixed ? 1 : 0][withj ? 1 : 0];
 }
 
+// Launch-shape knobs, also set by the autotuner: waves of a block over photon energies
+// per [persistent][mixed] (0: chosen by the grid), and the work-item target of the time
+// chunking (0: kTargetBlocks), one for every form so that a workspace size holds for both.
+int g_wg[2][2] = {{0, 0}, {0, 0}};
+int64_t g_target = 0;
+
+int wg_for(bool persistent, bool mixed)
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    return g_wg[persistent ? 1 : 0][mixed ? 1 : 0];
+}
+
+int64_t target_blocks()
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    return g_target > 0 ? g_target : radplan::kTargetBlocks;
+}
+
 using radplan::chunk_factor;
 using radplan::kMaxChunk;
 using radplan::kMinChunk;
@@ -141,9 +159,9 @@ static_assert(sizeof(double2) == 16, "complex FP64 partials");
 
 // Block shape for a grid and kernel variant; both integral sets of a call use
 // the same chunking, so the tile counts of the larger direction tile decide it.
-Tile plan_tile(const rad_grid *g, int variant)
+Tile plan_tile(const rad_grid *g, int variant, int wg = 0)
 {
-    return radplan::plan_tile(g->n_w, g->n_x, g->n_y, variant, kVarTX[variant], kVarTY[variant]);
+    return radplan::plan_tile(g->n_w, g->n_x, g->n_y, variant, kVarTX[variant], kVarTY[variant], wg);
 }
 
 Layout layout(const rad_grid *g, int n_segs, int n_out, int kinds, int64_t sum_chunks)
@@ -237,9 +255,12 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
     P.mixed = prec == RAD_MIXED;
     P.quantum = quantum;
     P.withj = (kinds & RAD_SPINHALF) != 0;
-    P.tile_c = plan_tile(g, variant_for(persistent, P.mixed, false));
-    P.tile_q = plan_tile(g, variant_for(persistent, P.mixed, P.withj));
-    int64_t cf = chunk_factor(plan_tile(g, kVar44x2), n_segs);   // variant-independent chunking
+    const int wg = wg_for(persistent, P.mixed);
+    P.tile_c = plan_tile(g, variant_for(persistent, P.mixed, false), wg);
+    P.tile_q = plan_tile(g, variant_for(persistent, P.mixed, P.withj), wg);
+    // chunking independent of the variant and of the energy spread (the 4x4 tile at the
+    // grid's own spread), so that a workspace size holds for every form
+    int64_t cf = chunk_factor(plan_tile(g, kVar44x2), n_segs, target_blocks());
     std::vector<int32_t> nch(n_segs), clen(n_segs);
     auto chunk_all = [&](int64_t c) {
         int64_t sum = 0;
@@ -552,7 +573,7 @@ namespace {
 size_t workspace_for(const rad_grid *g, const std::vector<int64_t> &ns, int n_out, int kinds, bool bound)
 {
     const Tile tile = plan_tile(g, kVar44x2);
-    const int64_t cf = chunk_factor(tile, (int64_t)ns.size());
+    const int64_t cf = chunk_factor(tile, (int64_t)ns.size(), target_blocks());
     int64_t sum = 0;
     for (int64_t n : ns) {
         if (bound) {
@@ -1214,6 +1235,32 @@ rad_status rad_tune_get_variant(int persistent, int mixed, int with_j, int *vari
 }
 
 int rad_tune_num_variants(void) { return kNumVariants; }
+
+rad_status rad_tune_set_shape(int persistent, int mixed, int wg)
+{
+    if (wg != 0 && wg != 1 && wg != 2 && wg != 4) return fail(RAD_EINVAL, "wg %d: 0 (by the grid), 1, 2 or 4", wg);
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_wg[persistent ? 1 : 0][mixed ? 1 : 0] = wg;
+    return RAD_OK;
+}
+
+rad_status rad_tune_get_shape(int persistent, int mixed, int *wg)
+{
+    if (!wg) return fail(RAD_EINVAL, "wg is NULL");
+    *wg = wg_for(persistent != 0, mixed != 0);
+    return RAD_OK;
+}
+
+rad_status rad_tune_set_chunk_target(int64_t target_blocks)
+{
+    if (target_blocks < 0 || target_blocks > radplan::kMaxTargetBlocks)
+        return fail(RAD_EINVAL, "chunk target %lld outside [0, 2^24]", (long long)target_blocks);
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_target = target_blocks;
+    return RAD_OK;
+}
+
+int64_t rad_tune_get_chunk_target(void) { return target_blocks(); }
 
 rad_status rad_profile_enable(int on)
 {

@@ -24,11 +24,12 @@ struct Tile {
 // Block shape for a grid of n_w photon energies and n_x x n_y directions, with a
 // direction tile of tx x ty per lane: wg waves of a block spread over photon energies,
 // nt = 4 / wg direction tiles per block.
-inline Tile plan_tile(int n_w, int n_x, int n_y, int variant, int tx, int ty)
+// wg_pref: 1, 2 or 4 waves over photon energies; anything else chooses by n_w.
+inline Tile plan_tile(int n_w, int n_x, int n_y, int variant, int tx, int ty, int wg_pref = 0)
 {
     Tile t;
     t.variant = variant;
-    t.wg = n_w > 128 ? 4 : (n_w > 64 ? 2 : 1);
+    t.wg = (wg_pref == 1 || wg_pref == 2 || wg_pref == 4) ? wg_pref : (n_w > 128 ? 4 : (n_w > 64 ? 2 : 1));
     t.nt = kWavesPerBlock / t.wg;
     t.n_tx = (n_x + tx - 1) / tx;
     t.n_ty = (n_y + ty - 1) / ty;
@@ -49,12 +50,16 @@ constexpr int64_t kMinChunk = 16;
 // up to 2^40 samples.
 constexpr int64_t kMaxChunk = (int64_t)1 << 30;
 
-// chunks per segment when the launch has `n_segs` segments
-inline int64_t chunk_factor(const Tile &t, int64_t n_segs)
+// Largest work-item target the tuning accepts.
+constexpr int64_t kMaxTargetBlocks = (int64_t)1 << 24;
+
+// chunks per segment when the launch has `n_segs` segments: enough for `target` work
+// items (kTargetBlocks unless tuned)
+inline int64_t chunk_factor(const Tile &t, int64_t n_segs, int64_t target = kTargetBlocks)
 {
     const int64_t have = n_segs * t.base_blocks;
-    if (have >= kTargetBlocks) return 1;
-    return (kTargetBlocks + have - 1) / have;
+    if (have >= target) return 1;
+    return (target + have - 1) / have;
 }
 
 // A segment of n samples cut for chunk factor c: chunk_len a multiple of kMinChunk (or

@@ -71,6 +71,10 @@ def load(path):
         "rad_last_error": (ctypes.c_char_p, []),
         "rad_tune_set_variant": (I, [I, I, I, I]),
         "rad_tune_get_variant": (I, [I, I, I, ctypes.POINTER(I)]),
+        "rad_tune_set_shape": (I, [I, I, I]),
+        "rad_tune_get_shape": (I, [I, I, ctypes.POINTER(I)]),
+        "rad_tune_set_chunk_target": (I, [I64]),
+        "rad_tune_get_chunk_target": (I64, []),
         "rad_plan_create": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, S, P,
                                 ctypes.POINTER(P)]),
         "rad_plan_launch": (I, [P, P, P]),
@@ -365,6 +369,26 @@ def tune_get_variant(persistent, mixed, with_j):
     _check(lib().rad_tune_get_variant(int(bool(persistent)), int(bool(mixed)), int(bool(with_j)),
                                       ctypes.byref(v)), "rad_tune_get_variant")
     return v.value
+
+
+def tune_set_shape(persistent, mixed, wg):
+    """Waves of a block over photon energies (1, 2, 4; 0: chosen by the grid)."""
+    _check(lib().rad_tune_set_shape(int(bool(persistent)), int(bool(mixed)), int(wg)), "rad_tune_set_shape")
+
+
+def tune_get_shape(persistent, mixed):
+    v = ctypes.c_int()
+    _check(lib().rad_tune_get_shape(int(bool(persistent)), int(bool(mixed)), ctypes.byref(v)), "rad_tune_get_shape")
+    return v.value
+
+
+def tune_set_chunk_target(target_blocks):
+    """Work items the time chunking aims for (0: the default 2048)."""
+    _check(lib().rad_tune_set_chunk_target(int(target_blocks)), "rad_tune_set_chunk_target")
+
+
+def tune_get_chunk_target():
+    return int(lib().rad_tune_get_chunk_target())
 
 
 class Plan:

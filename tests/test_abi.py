@@ -80,3 +80,24 @@ def test_validation_before_device(lib):
     d = ctypes.c_double(5.0)
     assert lib.rad_grid_step(None, ctypes.byref(d)) == 1 and d.value == 5.0
     assert b"NULL" in lib.rad_last_error()
+
+
+def test_shape_knobs(lib):
+    """The launch-shape knobs: energy spread per form and precision, the chunk target."""
+    from paper_1910_10391_amd import rad
+    rad.lib()                                           # argument types
+    assert lib.rad_tune_set_shape(0, 1, 3) == 1 and b"wg 3" in lib.rad_last_error()
+    assert lib.rad_tune_set_shape(0, 1, -1) == 1
+    assert lib.rad_tune_get_shape(0, 1, None) == 1
+    for persistent in (0, 1):
+        for mixed in (0, 1):
+            assert rad.tune_get_shape(persistent, mixed) == 0          # chosen by the grid
+    rad.tune_set_shape(1, 0, 2)
+    assert rad.tune_get_shape(1, 0) == 2 and rad.tune_get_shape(0, 0) == 0 and rad.tune_get_shape(1, 1) == 0
+    rad.tune_set_shape(1, 0, 0)
+    assert rad.tune_get_chunk_target() == 2048
+    assert lib.rad_tune_set_chunk_target(-1) == 1 and lib.rad_tune_set_chunk_target((1 << 24) + 1) == 1
+    rad.tune_set_chunk_target(8192)
+    assert rad.tune_get_chunk_target() == 8192
+    rad.tune_set_chunk_target(0)
+    assert rad.tune_get_chunk_target() == 2048

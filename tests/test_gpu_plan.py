@@ -110,12 +110,23 @@ def test_autotune_picks_and_caches(rad, tmp_path, monkeypatch):
         for persistent in (False, True):
             res = autotune.tune(grid, ds, 7, rad.MIXED, persistent=persistent, sample=4, min_evals=0,
                                 verbose=True)
-            assert len(res) == 2
+            fields = sorted(f for r in res.values() for f in ("variant", "wg", "target") if f in r)
+            assert fields == ["variant", "variant", "wg"], res      # two integral sets, then the spread
             for k, r in res.items():
                 assert not r["cached"]
-                assert r["variant"] == min(r["ms"], key=lambda v: r["ms"][v]) or str(r["variant"]) in r["ms"]
+                f = [f for f in ("variant", "wg", "target") if f in r][0]
+                if f == "variant":
+                    assert r["ms"][str(r[f])] == min(r["ms"].values())
+                else:                                     # the planner's own unless clearly beaten
+                    assert r["ms"][str(r[f])] <= min(r["ms"].values()) / (1.0 - autotune.MARGIN)
+            assert res[[k for k in res if k.startswith("wg-")][0]]["wg"] == rad.tune_get_shape(persistent, True)
             again = autotune.tune(grid, ds, 7, rad.MIXED, persistent=persistent, sample=4, min_evals=0)
-            assert all(r["cached"] for r in again.values())
+            assert all(r["cached"] for r in again.values()) and len(again) == len(res)
+        # a sample that is the whole workload also tunes the chunk target
+        whole = autotune.tune(grid, ds, 7, rad.MIXED, persistent=True, sample=len(segs), min_evals=0,
+                              use_cache=False)
+        tgt = [r for k, r in whole.items() if k.startswith("chunk-")]
+        assert len(tgt) == 1 and tgt[0]["target"] == rad.tune_get_chunk_target()
         assert os.path.exists(tmp_path / "tune.json")
         out = rad.batch(grid, ds, idx, 3, 7, precision=rad.MIXED).cpu().numpy()
         ref = oracle.batch(segs, idx, 3, hw, th, th, 7)
@@ -124,6 +135,49 @@ def test_autotune_picks_and_caches(rad, tmp_path, monkeypatch):
     finally:
         for k in keys:
             rad.tune_set_variant(*k, keep[k])
+        for p in (0, 1):
+            for m in (0, 1):
+                rad.tune_set_shape(p, m, 0)
+        rad.tune_set_chunk_target(0)
+
+
+def test_shape_knobs_keep_results(rad):
+    """The spread over photon energies changes no bit of the spectra, in either form and
+    precision; the chunk target changes them by rounding only (the chunk sums come in
+    another order)."""
+    segs, idx = _sections(3, seed=53)
+    g = segs[0]["gamma"]
+    hw = analytic.log_omega(200, 1e6, 20e9)       # 4 blocks of 64 energies at wg = 1, ragged
+    th = analytic.cell_centred(12, 4.0 / g)
+    grid = rad.Grid(hw, th, th)
+    ds = rad.DeviceSegments(segs)
+    try:
+        for prec in (rad.FP64, rad.MIXED):
+            mixed = prec == rad.MIXED
+            ref = rad.batch(grid, ds, idx, 3, 7, precision=prec).cpu().numpy()
+            for persistent in (False, True):
+                for wg in (1, 2, 4):
+                    rad.tune_set_shape(persistent, mixed, wg)
+                    if persistent:
+                        plan = rad.Plan(grid, ds, idx, 3, 7, precision=prec)
+                        out = plan.launch().cpu().numpy()
+                        plan.close()
+                    else:
+                        out = rad.batch(grid, ds, idx, 3, 7, precision=prec).cpu().numpy()
+                    assert np.array_equal(out, ref), (prec, persistent, wg)
+                rad.tune_set_shape(persistent, mixed, 0)
+            for target in (64, 20000):
+                rad.tune_set_chunk_target(target)
+                out = rad.batch(grid, ds, idx, 3, 7, precision=prec).cpu().numpy()
+                err = np.abs(out - ref).max() / np.abs(ref).max()
+                print("prec %d chunk target %d: max diff %.2e" % (prec, target, err), flush=True)
+                assert err < (1e-12 if prec == rad.FP64 else 1e-6)
+            rad.tune_set_chunk_target(0)
+    finally:
+        for p in (0, 1):
+            for m in (0, 1):
+                rad.tune_set_shape(p, m, 0)
+        rad.tune_set_chunk_target(0)
 
 
 def test_cells_match_full_grid(rad):

@@ -220,8 +220,9 @@ def test_estimate_matches_oracle(S):
         assert np.array_equal(res["dIdw"].cpu().numpy(), ref_full.cpu().numpy()), "fallback is not bitwise"
         smp.tau = 1e30
     # the error-driven rule: cells left out at their corrected estimates
-    smp.select_rule, smp.eps, smp.cap = "error", 0.05, 3
-    rm, rest = osm.select_error(pred, -8.0, 2.0, coarse, w, w, 8, 8, 0.05, 3)
+    smp.select_rule, smp.eps, smp.cap = "error", 1e-3, 3
+    rm, rest = osm.select_error(pred, -8.0, 2.0, coarse, w, w, 8, 8, 1e-3, 3)
+    assert 0 < rm.sum() < rm.size                         # some cells refined, some left out
     for prec, tol in ((rad.FP64, 1e-9), (rad.MIXED, 1e-4)):
         res = smp.estimate(ds, precision=prec)
         assert np.array_equal(res["mask"], rm)
