@@ -6,10 +6,13 @@ persistent plan):
 
 1. every variant the library offers (direction tile per lane x resident blocks),
    separately for each integral set the kinds need (with and without J);
-2. the block's spread over photon energies (1, 2 or 4 of its 4 waves over
-   energies, the rest over further direction tiles) for the whole call;
-3. when the sample is the whole workload (so that its time chunking is the
-   workload's), the work-item target that sets the chunk length.
+2. when the sample is the whole workload, for the whole call: the block's spread
+   over photon energies (1, 2 or 4 of its 4 waves over energies, the rest over
+   further direction tiles) and the work-item target that sets the chunk length.
+   Both act on the launch's schedule as a whole (how many items, how long each),
+   which a sample of the longest segments does not reproduce: on the 256-trajectory
+   benchmark, two energy groups timed 3 % faster than four on its 8 longest
+   segments and ran the full launch 4.6 % slower.
 
 It keeps the fastest of each, sets it in the library (``rad_tune_set_variant``,
 ``rad_tune_set_shape``, ``rad_tune_set_chunk_target``) and records the choices in a
@@ -78,10 +81,8 @@ def shape_key(persistent, precision, kinds, grid, max_n, what):
 
 WG_CHOICES = (1, 2, 4)
 TARGET_CHOICES = (512, 1024, 2048, 4096, 8192, 16384)
-# A launch-shape choice other than the planner's own must beat it by this much on the
-# sample: the sample is the longest segments only, and a small gain on it need not hold
-# for the whole workload (measured: a 2-wave spread that timed marginally faster on the
-# benchmark's 8 longest segments ran the full launch 4 % slower).
+# A launch-shape choice other than the planner's own must beat it by this much: timing
+# noise alone should not move a workload off the planner's choice.
 MARGIN = 0.03
 
 
@@ -162,8 +163,8 @@ def pick_sample(dsegs, grid, min_segments=8, min_evals=3e11):
 def tune(grid, dsegs, kinds, precision=rad.FP64, persistent=False, sample=8, min_evals=3e11,
          reps=1, use_cache=True, verbose=False, shape=True):
     """Pick and set the fastest variant for every integral set of ``kinds``, then (with
-    ``shape``) the fastest spread over photon energies and, when the sample is the whole
-    workload, the fastest chunk target.
+    ``shape``, when the sample is the whole workload) the fastest spread over photon
+    energies and chunk target.
 
     ``dsegs`` is a ``rad.DeviceSegments``; the longest segments are timed: at least
     ``sample`` of them and at least ``min_evals`` terms.
@@ -203,17 +204,16 @@ def tune(grid, dsegs, kinds, precision=rad.FP64, persistent=False, sample=8, min
         cache[k] = {"variant": best, "ms": {str(v): t for v, t in times.items()}}
         result[k] = dict(cache[k], cached=False)
         changed = True
-    if shape:
+    if shape and len(order) == len(dsegs):
         time_call = lambda: _time_variant(grid, sub, kinds, precision, persistent, reps)   # noqa: E731
         n_w = grid.shape[0]
         wgs = [w for w in WG_CHOICES if w == 1 or n_w > 32 * w]     # at least half the block's energies exist
         changed |= _search(cache, shape_key(persistent, precision, kinds, grid, max_n, "wg"),
                            lambda w: rad.tune_set_shape(persistent, mixed, w), wgs, time_call, result, verbose,
                            "wg", default=default_wg(n_w))
-        if len(order) == len(dsegs):
-            changed |= _search(cache, shape_key(persistent, precision, kinds, grid, max_n, "chunk"),
-                               rad.tune_set_chunk_target, TARGET_CHOICES, time_call, result, verbose, "target",
-                               default=2048)
+        changed |= _search(cache, shape_key(persistent, precision, kinds, grid, max_n, "chunk"),
+                           rad.tune_set_chunk_target, TARGET_CHOICES, time_call, result, verbose, "target",
+                           default=2048)
     if changed and use_cache:
         _store(path, cache)
     return result

@@ -111,7 +111,7 @@ def test_autotune_picks_and_caches(rad, tmp_path, monkeypatch):
             res = autotune.tune(grid, ds, 7, rad.MIXED, persistent=persistent, sample=4, min_evals=0,
                                 verbose=True)
             fields = sorted(f for r in res.values() for f in ("variant", "wg", "target") if f in r)
-            assert fields == ["variant", "variant", "wg"], res      # two integral sets, then the spread
+            assert fields == ["variant", "variant"], res            # two integral sets; a sample: no shape
             for k, r in res.items():
                 assert not r["cached"]
                 f = [f for f in ("variant", "wg", "target") if f in r][0]
@@ -119,13 +119,14 @@ def test_autotune_picks_and_caches(rad, tmp_path, monkeypatch):
                     assert r["ms"][str(r[f])] == min(r["ms"].values())
                 else:                                     # the planner's own unless clearly beaten
                     assert r["ms"][str(r[f])] <= min(r["ms"].values()) / (1.0 - autotune.MARGIN)
-            assert res[[k for k in res if k.startswith("wg-")][0]]["wg"] == rad.tune_get_shape(persistent, True)
             again = autotune.tune(grid, ds, 7, rad.MIXED, persistent=persistent, sample=4, min_evals=0)
             assert all(r["cached"] for r in again.values()) and len(again) == len(res)
-        # a sample that is the whole workload also tunes the chunk target
+        # a sample that is the whole workload also tunes the spread and the chunk target
         whole = autotune.tune(grid, ds, 7, rad.MIXED, persistent=True, sample=len(segs), min_evals=0,
-                              use_cache=False)
+                              use_cache=False, verbose=True)
+        wg = [r for k, r in whole.items() if k.startswith("wg-")]
         tgt = [r for k, r in whole.items() if k.startswith("chunk-")]
+        assert len(wg) == 1 and wg[0]["wg"] == rad.tune_get_shape(True, True)
         assert len(tgt) == 1 and tgt[0]["target"] == rad.tune_get_chunk_target()
         assert os.path.exists(tmp_path / "tune.json")
         out = rad.batch(grid, ds, idx, 3, 7, precision=rad.MIXED).cpu().numpy()
