@@ -47,6 +47,63 @@ __host__ __device__ inline Stream particle_stream(uint64_t seed, int64_t particl
     return r;
 }
 
+// Normal draws: Box-Muller with a logarithm and a cosine evaluated from IEEE operations
+// only (+ - * / sqrt, exact bit manipulation, no FMA contraction), in the same order as the CPU generator's, so that both draw the same
+// bits (the host's and the device's library log and cos differ in the last bit now and
+// then, and one such bit can decide on which side of a plane's kink a step lands).
+//
+// log u, u in (0, 1]: u = m 2^e, m in [sqrt(1/2), sqrt(2)): e ln 2 + 2 atanh(s),
+// s = (m - 1) / (m + 1), |s| <= 0.172, the atanh series to s^23.
+__host__ __device__ inline double det_log(double u)
+{
+#pragma clang fp contract(off)
+    uint64_t b = (uint64_t)__builtin_bit_cast(uint64_t, u);
+    int e = (int)((b >> 52) & 0x7ff) - 1023;
+    b = (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
+    double m = __builtin_bit_cast(double, b);
+    if (m > 1.4142135623730951) {
+        m = 0.5 * m;
+        e = e + 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    return (double)e * 0.6931471805599453 + (2.0 * s + 2.0 * s * (z * p));
+}
+
+// cos(2 pi u), u in [0, 1]: v = min(u, 1 - u), w = v - 1/4 (exact on the 2^-53 grid),
+// -sin(x) at x = 2 pi w, |x| <= pi/2, the sine's Taylor series to x^23.
+__host__ __device__ inline double det_cos2pi(double u)
+{
+#pragma clang fp contract(off)
+    const double v = u <= 0.5 ? u : 1.0 - u;
+    const double w = v - 0.25;
+    const double x = w * 6.283185307179586;
+    const double z = x * x;
+    double p = -1.0 / 25852016738884976640000.0;
+    p = p * z + 1.0 / 51090942171709440000.0;
+    p = p * z - 1.0 / 121645100408832000.0;
+    p = p * z + 1.0 / 355687428096000.0;
+    p = p * z - 1.0 / 1307674368000.0;
+    p = p * z + 1.0 / 6227020800.0;
+    p = p * z - 1.0 / 39916800.0;
+    p = p * z + 1.0 / 362880.0;
+    p = p * z - 1.0 / 5040.0;
+    p = p * z + 1.0 / 120.0;
+    p = p * z - 1.0 / 6.0;
+    return -(x + x * (z * p));
+}
+
 // the first draw of a particle's stream: its step count, uniform in [n_min, n_max]
 __host__ __device__ inline int64_t draw_steps(const rad_traj_params &p, Stream &r)
 {

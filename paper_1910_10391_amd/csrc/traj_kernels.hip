@@ -3,8 +3,8 @@
 // The transverse motion is sequential in time, so the parallelism is across
 // particles; a thread keeps its state in registers and streams its samples to
 // HBM (88 bytes per step).  Arithmetic is kept in program order (no FMA
-// contraction), so that a host build of the same steps gives the same numbers
-// except where the device and host libraries round log and cos differently.
+// contraction) and the normal draws use no library transcendental (traj_internal.h),
+// so that the CPU generator, which takes the same steps, gives the same bits.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -28,7 +28,7 @@ __device__ inline double slope(const rad_traj_params &p, double x)
 __device__ inline double gaussian(Stream &r)
 {
     const double u1 = r.uniform(), u2 = r.uniform();
-    return sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+    return sqrt(-2.0 * det_log(u1)) * det_cos2pi(u2);
 }
 
 // The unit normals of every scattering kick, in parallel over (step, particle): the
@@ -46,8 +46,8 @@ __global__ __launch_bounds__(256) void kicks_kernel(TrajLaunch L)
         const uint64_t j = first_kick_draw(L.p) + 4u * (uint64_t)k;
         const double u1 = uniform_at(s, j), u2 = uniform_at(s, j + 1);
         const double u3 = uniform_at(s, j + 2), u4 = uniform_at(s, j + 3);
-        L.kicks[2 * i] = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
-        L.kicks[2 * i + 1] = sqrt(-2.0 * log(u3)) * cos(2.0 * kPi * u4);
+        L.kicks[2 * i] = sqrt(-2.0 * det_log(u1)) * det_cos2pi(u2);
+        L.kicks[2 * i + 1] = sqrt(-2.0 * det_log(u3)) * det_cos2pi(u4);
     }
 }
 

@@ -24,7 +24,7 @@
  * (vx^2+vy^2)/2, dz = int dvz dt (trapezoid).
  *
  * Random numbers: splitmix64 (Steele, Lea, Flood 2014) keyed by (seed,
- * particle), normals by Box-Muller.
+ * particle), normals by Box-Muller with the logarithm and cosine below.
  */
 #include <math.h>
 #include <stdint.h>
@@ -70,10 +70,74 @@ static double u01(rng_t *r) /* (0, 1] */
     return ((double)(splitmix64(r) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
 }
 
+/*
+ * log and cos for the normal draws, from IEEE operations only (+ - * / sqrt and exact
+ * bit manipulation; this file is built without FMA contraction), so that another
+ * implementation that evaluates the same series in the same order -- the GPU
+ * generator's -- draws the same bits; the C library's log and cos and a device's round
+ * differently in the last bit now and then.
+ *
+ * log u, u in (0, 1]: u = m 2^e with m in [sqrt(1/2), sqrt(2)), log u = e ln 2 +
+ * 2 atanh s, s = (m - 1) / (m + 1), |s| <= 0.172, by the atanh series to s^23 (the next
+ * term is below 2^-60 of the sum).
+ */
+double syn_log(double u)
+{
+    uint64_t b;
+    memcpy(&b, &u, sizeof b);
+    int e = (int)((b >> 52) & 0x7ff) - 1023;
+    b = (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
+    double m;
+    memcpy(&m, &b, sizeof m);
+    if (m > 1.4142135623730951) {
+        m = 0.5 * m;
+        e = e + 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    return (double)e * 0.6931471805599453 + (2.0 * s + 2.0 * s * (z * p));
+}
+
+/*
+ * cos(2 pi u), u in [0, 1]: v = min(u, 1 - u) in [0, 1/2] and w = v - 1/4 (both exact
+ * for u on the 2^-53 grid), cos(2 pi u) = -sin(x) with x = 2 pi w, |x| <= pi/2, by the
+ * sine's Taylor series to x^23.
+ */
+double syn_cos2pi(double u)
+{
+    const double v = u <= 0.5 ? u : 1.0 - u;
+    const double w = v - 0.25;
+    const double x = w * 6.283185307179586;
+    const double z = x * x;
+    double p = -1.0 / 25852016738884976640000.0;
+    p = p * z + 1.0 / 51090942171709440000.0;
+    p = p * z - 1.0 / 121645100408832000.0;
+    p = p * z + 1.0 / 355687428096000.0;
+    p = p * z - 1.0 / 1307674368000.0;
+    p = p * z + 1.0 / 6227020800.0;
+    p = p * z - 1.0 / 39916800.0;
+    p = p * z + 1.0 / 362880.0;
+    p = p * z - 1.0 / 5040.0;
+    p = p * z + 1.0 / 120.0;
+    p = p * z - 1.0 / 6.0;
+    return -(x + x * (z * p));
+}
+
 static double normal(rng_t *r)
 {
     const double u1 = u01(r), u2 = u01(r);
-    return sqrt(-2.0 * log(u1)) * cos(2.0 * SYN_PI * u2);
+    return sqrt(-2.0 * syn_log(u1)) * syn_cos2pi(u2);
 }
 
 static rng_t particle_rng(uint64_t seed, int64_t particle)

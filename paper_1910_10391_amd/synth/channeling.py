@@ -68,7 +68,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-fopenmp", _SRC, "-o", tmp,
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-fopenmp", _SRC, "-o", tmp,
                     "-lm"], check=True)
     os.replace(tmp, _LIB)
     return _LIB

@@ -113,3 +113,28 @@ def test_longitudinal_bookkeeping_and_accelerations():
     ax = np.gradient(tr["vx"], tr["t"], edge_order=1)
     assert np.allclose(tr["ax"][1:-1], (tr["vx"][2:] - tr["vx"][:-2]) / (tr["t"][2:] - tr["t"][:-2]), rtol=1e-14)
     assert np.allclose(tr["ax"], ax, rtol=1e-9, atol=1e-9 * np.abs(ax).max())
+
+
+def test_normal_draw_functions():
+    """The generator's own log u and cos(2 pi u) for the Box-Muller draws (IEEE operations
+    only, so that the GPU generator can draw the same bits) against the C library, on the
+    generator's 2^-53 grid of uniforms and at the reduction's edges."""
+    import ctypes
+    lib = channeling._load()
+    for name in ("syn_log", "syn_cos2pi"):
+        getattr(lib, name).argtypes = [ctypes.c_double]
+        getattr(lib, name).restype = ctypes.c_double
+    rng = np.random.default_rng(3)
+    u = (rng.integers(0, 2 ** 53, 20000, dtype=np.uint64).astype(np.float64) + 1.0) * 2.0 ** -53
+    u = np.concatenate([u, [1.0, 0.5, 0.25, 0.75, 0.125, 2.0 ** -53, 1.0 - 2.0 ** -53, 0.5 + 2.0 ** -53,
+                            math.sqrt(0.5), math.sqrt(0.5) * (1 + 2.0 ** -52), 1e-10]])
+    lg = np.array([lib.syn_log(x) for x in u])
+    cs = np.array([lib.syn_cos2pi(x) for x in u])
+    assert lib.syn_log(1.0) == 0.0 and lib.syn_cos2pi(0.25) == 0.0 and lib.syn_cos2pi(1.0) == 1.0
+    err_log = np.abs(lg - np.log(u)) / np.maximum(1.0, np.abs(np.log(u)))
+    err_cos = np.abs(cs - np.cos(2 * np.pi * u))
+    print("log: max rel err %.2e; cos(2 pi u): max abs err %.2e" % (err_log.max(), err_cos.max()))
+    assert err_log.max() <= 4e-16 and err_cos.max() <= 2e-15
+    # Box-Muller on independent pairs of them gives unit normals
+    n = np.sqrt(-2.0 * lg[:10000]) * cs[10000:20000]
+    assert abs(n.mean()) < 0.04 and abs(n.std() - 1.0) < 0.03
