@@ -864,7 +864,8 @@ __global__ __launch_bounds__(1024) void cell_compact_kernel(CellCompact C)
 
 hipError_t launch_cell_compact(const CellCompact &C, hipStream_t st)
 {
-    if (C.n_items < 1 || C.n_cells < 1 || C.wg < 1) return hipErrorInvalidValue;
+    // the live count and offsets are 32-bit
+    if (C.n_items < 1 || C.n_items > 0x7fffffff || C.n_cells < 1 || C.wg < 1) return hipErrorInvalidValue;
     const int64_t threads = C.n_items * kWave;
     hipLaunchKernelGGL(cell_flags_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, C);
     hipError_t e = hipGetLastError();
