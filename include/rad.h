@@ -302,6 +302,16 @@ int rad_tune_num_variants(void);
  * outside [0, 2^24].  rad_tune_get_chunk_target returns the target in force.
  */
 rad_status rad_tune_set_shape(int persistent, int mixed, int wg);
+/*
+ * The cell integrals' block shape (rad_cells, rad_cells_device): wg = 1, 2 or 4 of a
+ * block's 4 waves over photon energies, the others over the cell's 4 x 4 direction
+ * tiles (0 or 1, the default: a whole 8 x 8 cell for 64 energies).  A larger wg shares
+ * each staged direction among more energies, and evaluates a cell for whole blocks of
+ * 64 wg energies.  The sums are those of wg = 1, to rounding (the time chunking follows
+ * the item count).  RAD_EINVAL for other values.
+ */
+rad_status rad_tune_set_cell_spread(int wg);
+int rad_tune_get_cell_spread(void);
 rad_status rad_tune_get_shape(int persistent, int mixed, int *wg);
 rad_status rad_tune_set_chunk_target(int64_t target_blocks);
 int64_t rad_tune_get_chunk_target(void);

@@ -936,12 +936,22 @@ struct CellsPlan {
     int n_ps = 0;                 // active (segment, cell) pseudo-segments
     int64_t n_items = 0;
     bool dense = false;           // device mask: every (segment, cell) pair, p = s * n_cells + c
+    int wg = 1, n_groups = 1;     // waves over photon energies; direction-tile groups per cell
     size_t off_ps, off_items, off_psof, off_mask, off_part, desc_bytes, total;
     size_t off_flags = 0, off_live = 0, off_nlive = 0;   // device-mask compaction (dense plans)
     std::vector<char> host;
 };
 
-constexpr int kCellWg = 1;        // 64 photon energies per block, 4 direction tiles (one 8x8 cell)
+// Cell items: a block spreads its 4 waves over wg groups of 64 photon energies and
+// 4 / wg of the cell's four 4 x 4 direction tiles (wg = 1: the whole 8 x 8 cell for 64
+// energies; the default).
+int g_cell_wg = 1;
+
+int cell_wg()
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    return g_cell_wg;
+}
 
 // The work of rad_cells for a host mask (only the selected (segment, cell, photon-energy
 // block) items), or, with mask == nullptr and dense set, for a device mask read by the
@@ -962,7 +972,9 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     C.ncx = g->n_x / cx;
     C.ncy = g->n_y / cy;
     C.n_cells = C.ncx * C.ncy;
-    C.n_wb = (g->n_w + kWave * kCellWg - 1) / (kWave * kCellWg);
+    C.wg = cell_wg();
+    C.n_groups = ((cx / 4) * (cy / 4)) / (kWavesPerBlock / C.wg);
+    C.n_wb = (g->n_w + kWave * C.wg - 1) / (kWave * C.wg);
     const int n_w = g->n_w;
     // active (segment, cell) pairs and their photon-energy blocks
     std::vector<int> psof((size_t)n_segs * C.n_cells, -1);
@@ -973,7 +985,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
             std::vector<int> blocks;
             for (int b = 0; b < C.n_wb; ++b) {
                 bool any = dense;
-                for (int w = b * kWave * kCellWg; w < std::min(n_w, (b + 1) * kWave * kCellWg) && !any; ++w)
+                for (int w = b * kWave * C.wg; w < std::min(n_w, (b + 1) * kWave * C.wg) && !any; ++w)
                     any = mask[((size_t)s * n_w + w) * C.n_cells + c] != 0;
                 if (any) blocks.push_back(b);
             }
@@ -987,7 +999,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     const int64_t base_items = 0;
     (void)base_items;
     int64_t items = 0;
-    for (auto &v : wbs) items += (int64_t)v.size();
+    for (auto &v : wbs) items += (int64_t)v.size() * C.n_groups;
     // time chunks: enough items to fill the GPU
     const int64_t cf = items >= kTargetBlocks ? 1 : (kTargetBlocks + std::max<int64_t>(items, 1) - 1) / std::max<int64_t>(items, 1);
     std::vector<int32_t> nch(std::max(C.n_ps, 1)), clen(std::max(C.n_ps, 1));
@@ -995,7 +1007,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     for (int p = 0; p < C.n_ps; ++p) {
         plan_chunks(segs[ps[p].first].n, cf, nch[p], clen[p]);
         sum_chunks += nch[p];
-        items += (int64_t)(nch[p] - 1) * (int64_t)wbs[p].size();
+        items += (int64_t)(nch[p] - 1) * (int64_t)wbs[p].size() * C.n_groups;
     }
     C.n_items = items;
     const size_t cell_dirs = (size_t)cx * cy;
@@ -1052,14 +1064,15 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
         d.n_y = cy;
         d.n_tx = cx / 4;
         d.n_ty = cy / 4;
-        d.n_groups = 1;
+        d.n_groups = C.n_groups;
         d.n_wblocks = C.n_wb;
         D[p] = d;
     }
     for (int r = 0; r < C.n_ps; ++r) {
         const int p = order[r];
         for (int ch = 0; ch < nch[p]; ++ch)
-            for (int b : wbs[p]) I[it++] = make_int4(p, ch, 0, b);
+            for (int grp = 0; grp < C.n_groups; ++grp)
+                for (int b : wbs[p]) I[it++] = make_int4(p, ch, grp, b);
     }
     return RAD_OK;
 }
@@ -1109,8 +1122,8 @@ rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, 
         L.items = (const int4 *)(wsb + C.off_items);
         L.n_segs = C.n_ps;
         L.n_blocks = C.n_items;
-        L.wg = kCellWg;
-        L.nt = kWavesPerBlock / kCellWg;
+        L.wg = C.wg;
+        L.nt = kWavesPerBlock / C.wg;
         L.quantum = quantum ? 1 : 0;
         L.rec = g->dth != 0.0 ? 1 : 0;
         L.comps = comps;
@@ -1126,7 +1139,7 @@ rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, 
             K.mask = mask;
             K.n_cells = C.n_cells;
             K.n_w = g->n_w;
-            K.wg = kCellWg;
+            K.wg = C.wg;
             K.flags = (int *)(wsb + C.off_flags);
             K.live = (int4 *)(wsb + C.off_live);
             K.n_live = (int *)(wsb + C.off_nlive);
@@ -1261,6 +1274,16 @@ rad_status rad_tune_set_chunk_target(int64_t target_blocks)
 }
 
 int64_t rad_tune_get_chunk_target(void) { return target_blocks(); }
+
+rad_status rad_tune_set_cell_spread(int wg)
+{
+    if (wg != 0 && wg != 1 && wg != 2 && wg != 4) return fail(RAD_EINVAL, "wg %d: 0 (default), 1, 2 or 4", wg);
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_cell_wg = wg == 0 ? 1 : wg;
+    return RAD_OK;
+}
+
+int rad_tune_get_cell_spread(void) { return cell_wg(); }
 
 rad_status rad_profile_enable(int on)
 {

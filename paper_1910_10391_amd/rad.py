@@ -75,6 +75,8 @@ def load(path):
         "rad_tune_get_shape": (I, [I, I, ctypes.POINTER(I)]),
         "rad_tune_set_chunk_target": (I, [I64]),
         "rad_tune_get_chunk_target": (I64, []),
+        "rad_tune_set_cell_spread": (I, [I]),
+        "rad_tune_get_cell_spread": (I, []),
         "rad_plan_create": (I, [P, SP, I, ctypes.POINTER(I), I, I, I, P, S, P,
                                 ctypes.POINTER(P)]),
         "rad_plan_launch": (I, [P, P, P]),
@@ -389,6 +391,15 @@ def tune_set_chunk_target(target_blocks):
 
 def tune_get_chunk_target():
     return int(lib().rad_tune_get_chunk_target())
+
+
+def tune_set_cell_spread(wg):
+    """Waves of a cell block over photon energies (1, 2, 4; 0: the default 1)."""
+    _check(lib().rad_tune_set_cell_spread(int(wg)), "rad_tune_set_cell_spread")
+
+
+def tune_get_cell_spread():
+    return int(lib().rad_tune_get_cell_spread())
 
 
 class Plan:

@@ -66,6 +66,25 @@ def test_device_mask_matches_host_mask(R):
                 assert err <= 1e-12, (name, kind, prec)
                 if name == "full":
                     assert np.array_equal(a, b), (name, kind, prec)
+    # the cell blocks' spread over photon energies: the same sums (to rounding; the time
+    # chunking follows the item count), in both mask forms
+    try:
+        for wg in (2, 4):
+            rad.tune_set_cell_spread(wg)
+            for name, m in _masks(rng, 3, 150, 4):
+                if name == "empty":
+                    continue
+                for form in (m, torch.from_numpy(m).cuda()):
+                    ref = None
+                    b = rad.cells(grid, ds, rad.SPINHALF, form, rad.MIXED).cpu().numpy()
+                    rad.tune_set_cell_spread(1)
+                    ref = rad.cells(grid, ds, rad.SPINHALF, form, rad.MIXED).cpu().numpy()
+                    rad.tune_set_cell_spread(wg)
+                    err = np.abs(b - ref).max() / np.abs(ref).max()
+                    assert err <= 1e-12 and not b[m == 0].any(), (wg, name, err)
+            print("cell spread %d: the same cells" % wg, flush=True)
+    finally:
+        rad.tune_set_cell_spread(0)
     # FP64 cells of the full mask against the direct-sum oracle
     b = rad.cells(grid, ds, rad.SPINHALF, torch.ones((3, 150, 4), dtype=torch.uint8, device="cuda"),
                   rad.FP64).cpu().numpy()
