@@ -11,13 +11,14 @@ constexpr int kIn1 = 64;      // layer-1 inputs padded to one MFMA-friendly widt
 
 enum { kEpiFwd = 0, kEpiBwd = 1 };
 
-constexpr int kRowBlock = 128;   // rows per block of the row products; batches are padded to it
+constexpr int kRowBlock = 128;   // batches are padded to a multiple of this many rows
+constexpr int kRowTile = 64;     // rows per block of the row products
 
 // C[M][256] = A[M][K] W^T (A, W BF16, K = 64 or 256 contiguous) with an epilogue:
 // forward: z = C + bias, h = bf16(silu(z)) and, in training, ds = bf16(silu'(z)) (the
 // factor the backward pass needs, computed here from the FP32 z); backward: dz = C dsin
 // (dsin the ds of the layer below), h = bf16(dz) and the per-block column sums of dz
-// (col_part [M / 128][256]).  h goes row-major to out_h and, if out_k8 is given, to the k8
+// (col_part [M / 64][256]).  h goes row-major to out_h and, if out_k8 is given, to the k8
 // layout [M / 8][256][8].
 struct RowsArgs {
     const uint16_t *A, *W;
@@ -27,7 +28,7 @@ struct RowsArgs {
     uint16_t *out_ds;     // forward, training: silu'(z) (BF16) [M][256] (or null)
     uint16_t *out_h;      // [M][256]
     uint16_t *out_k8;     // [M / 8][256][8] or null
-    float *col_part;      // backward: [M / 128][256]
+    float *col_part;      // backward: [M / 64][256]
 };
 
 // Weight gradients, C[M][N] = sum over the batch of A8[k/8][m][k%8] B8[k/8][n][k%8] (k8

@@ -43,10 +43,12 @@ __device__ __forceinline__ float dsilu_s(float z, float s) { return s * (1.0f + 
 //
 // Two product shapes cover the network:
 // * gemm_rows_kernel: C[Bp][256] = A[Bp][K] W^T (W [256][K], both K contiguous; the
-//   layers' forward products and the backward data products).  A block computes 128
+//   layers' forward products and the backward data products).  A block computes 64
 //   rows x all 256 columns; K runs in slices of 32 staged through LDS (double buffered,
 //   one barrier per slice), so that each A and W element is fetched once per block and
-//   shared by the block's four waves; each wave computes 64 x 128 (2 x 4 MFMA tiles).
+//   shared by the block's four waves; each wave computes 32 x 128 (4 MFMA tiles).  Three
+//   blocks fit a CU (at most 168 VGPRs, 53 kB of LDS), so that the blocks' load phases and
+//   their store-heavy epilogues overlap.
 //   The epilogue applies the layer (bias + SiLU, or times SiLU' of the layer below),
 //   stores the results row-major and in the k8 layout below, and, in the backward form,
 //   the block's column sums of dz (bias gradients) in a fixed order.
@@ -58,47 +60,45 @@ __device__ __forceinline__ float dsilu_s(float z, float s) { return s * (1.0f + 
 typedef uint16_t bf16x8u __attribute__((ext_vector_type(8)));
 
 template <int EPI, int K>
-__global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
+__global__ __launch_bounds__(256, 3) void gemm_rows_kernel(RowsArgs g)
 {
     constexpr int KS = 32;                // K slice
     constexpr int LD = KS + 8;            // LDS row stride (elements): 80 bytes
     constexpr int NS = K / KS;
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][kRowBlock * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][kWidth * LD];
+    // one LDS region: the K loop's A and W stages, reused by the epilogue
+    constexpr int kStageA = kRowTile * LD, kStageB = kWidth * LD;
+    __shared__ __attribute__((aligned(16))) uint16_t smem[2 * kStageA + 2 * kStageB];
+    uint16_t (*sA)[kStageA] = reinterpret_cast<uint16_t (*)[kStageA]>(smem);
+    uint16_t (*sB)[kStageB] = reinterpret_cast<uint16_t (*)[kStageB]>(smem + 2 * kStageA);
     __shared__ float sCol[2][kWidth];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int r = lane & 31, hs = lane >> 5;
-    const int64_t row0 = (int64_t)blockIdx.x * kRowBlock;
-    // global -> register staging of one slice: A 128 x 32 (2 chunks of 8 per thread),
+    const int64_t row0 = (int64_t)blockIdx.x * kRowTile;
+    // global -> register staging of one slice: A 64 x 32 (one chunk of 8 per thread),
     // W 256 x 32 (4 chunks per thread)
-    uint4 ra0, ra1, rb0, rb1, rb2, rb3;
+    uint4 ra0, rb0, rb1, rb2, rb3;
     const int srr = tid >> 2, skc = (tid & 3) * 8;   // this thread's row (and row + 64 q) and k chunk
     auto load = [&](int s) __attribute__((always_inline)) {
         const uint16_t *a = g.A + (row0 + srr) * K + s * KS + skc;
         const uint16_t *w = g.W + (int64_t)srr * K + s * KS + skc;
         ra0 = *reinterpret_cast<const uint4 *>(a);
-        ra1 = *reinterpret_cast<const uint4 *>(a + 64 * K);
         rb0 = *reinterpret_cast<const uint4 *>(w);
         rb1 = *reinterpret_cast<const uint4 *>(w + 64 * K);
         rb2 = *reinterpret_cast<const uint4 *>(w + 128 * K);
         rb3 = *reinterpret_cast<const uint4 *>(w + 192 * K);
     };
     auto store = [&](int buf) __attribute__((always_inline)) {
-        uint16_t *a = &sA[buf][srr * LD + skc];
         uint16_t *w = &sB[buf][srr * LD + skc];
-        *reinterpret_cast<uint4 *>(a) = ra0;
-        *reinterpret_cast<uint4 *>(a + 64 * LD) = ra1;
+        *reinterpret_cast<uint4 *>(&sA[buf][srr * LD + skc]) = ra0;
         *reinterpret_cast<uint4 *>(w) = rb0;
         *reinterpret_cast<uint4 *>(w + 64 * LD) = rb1;
         *reinterpret_cast<uint4 *>(w + 128 * LD) = rb2;
         *reinterpret_cast<uint4 *>(w + 192 * LD) = rb3;
     };
-    floatx16 acc[2][4];
+    floatx16 acc[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = floatx16{};
+    for (int b = 0; b < 4; ++b) acc[b] = floatx16{};
     load(0);
     store(0);
     __syncthreads();
@@ -108,18 +108,13 @@ __global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
         if (s + 1 < NS) load(s + 1);
 #pragma unroll
         for (int ks = 0; ks < KS / 16; ++ks) {
-            bf16x8 av[2], bv[4];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-                av[a] = *reinterpret_cast<const bf16x8 *>(&sA[buf][(wm * 64 + a * 32 + r) * LD + ks * 16 + 8 * hs]);
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sA[buf][(wm * 32 + r) * LD + ks * 16 + 8 * hs]);
+            bf16x8 bv[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 bv[b] = *reinterpret_cast<const bf16x8 *>(&sB[buf][(wn * 128 + b * 32 + r) * LD + ks * 16 + 8 * hs]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[b], acc[b], 0, 0, 0);
         }
         if (s + 1 < NS) store(buf ^ 1);
         __syncthreads();
@@ -128,75 +123,114 @@ __global__ __launch_bounds__(256, 2) void gemm_rows_kernel(RowsArgs g)
     // column (the MFMA result layout); the row-major outputs go through a per-wave LDS
     // stage (the K loop's buffers, free after its last barrier) so that every global store
     // is 16 contiguous bytes per lane; the k8 layout takes the 4 rows directly.
-    constexpr int HLD = 40;                      // stage row stride (bf16), 16-byte aligned
-    uint16_t *hst = &sB[0][0] + wave * (2 * 32 * HLD);
-    uint16_t *dst = hst + 32 * HLD;
+    // The wave's 32 x 128 results go through a per-wave LDS stage (the K loop's buffers,
+    // free after its last barrier), so that stored row segments are whole 128-byte lines or
+    // longer (16 bytes per lane); the k8 copy is written directly (4 consecutive rows of a
+    // column are 8 contiguous bytes).  Forward: h and silu'(z) of two 32 x 32 tiles per
+    // round (storing the two outputs in separate rounds of whole rows measured slower).
+    // Backward: the block's silu' rows are first staged in LDS with 16-byte loads and read
+    // into registers; then dz of the wave's 32 x 128 in one round of 256-byte rows.
+    const int64_t trow = row0 + wm * 32;        // first row of the wave's tiles
+    auto store_k8 = [&](int col, int rt, const uint16_t (&hv)[4]) __attribute__((always_inline)) {
+        const int64_t rb = trow + rt;
+        const int64_t k8 = ((rb >> 3) * kWidth + col) * 8 + (rb & 7);
+        uint2 pk;
+        pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+        pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+        *reinterpret_cast<uint2 *>(g.out_k8 + k8) = pk;
+    };
     float csum[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // backward: this lane's column sums of dz
+    if constexpr (EPI == kEpiFwd) {
+        constexpr int HLD = 64 + 8;              // stage row stride (bf16), 16-byte aligned
+        uint16_t *hst = smem + wave * (2 * 32 * HLD);
+        uint16_t *dst = hst + 32 * HLD;
+        static_assert(4 * 2 * 32 * HLD <= 2 * kStageA + 2 * kStageB, "epilogue stage fits");
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int bp = 0; bp < 2; ++bp) {
+#pragma unroll
+            for (int bt = 0; bt < 2; ++bt) {
+                const int b = 2 * bp + bt;
+                const int col = wn * 128 + b * 32 + r;
+                const float bias = g.bias[col];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {    // rows 8 q + 4 hs + (0..3) of the tile
+                    const int rt = 8 * q + 4 * hs;
+                    uint16_t hv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float z = acc[b][4 * q + j] + bias;
+                        const float sg = sigmoidf_(z);
+                        hv[j] = f2bf(z * sg);
+                        hst[(rt + j) * HLD + bt * 32 + r] = hv[j];
+                        dst[(rt + j) * HLD + bt * 32 + r] = f2bf(dsilu_s(z, sg));
+                    }
+                    if (g.out_k8) store_k8(col, rt, hv);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();     // the wave's stage writes before its reads
+            const int c0 = wn * 128 + bp * 64;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {        // 32 rows x 8 chunks of 16 bytes
+                const int c = lane + 64 * k, rr = c >> 3, cc = c & 7;
+                *reinterpret_cast<uint4 *>(g.out_h + (trow + rr) * kWidth + c0 + cc * 8) =
+                    *reinterpret_cast<const uint4 *>(&hst[rr * HLD + cc * 8]);
+                if (g.out_ds)
+                    *reinterpret_cast<uint4 *>(g.out_ds + (trow + rr) * kWidth + c0 + cc * 8) =
+                        *reinterpret_cast<const uint4 *>(&dst[rr * HLD + cc * 8]);
+            }
+            __builtin_amdgcn_wave_barrier();     // reads done before the next round's writes
+        }
+    } else {
+        // rows padded to 264 elements: the two row halves a wave reads fall in disjoint banks
+        constexpr int DLD = kWidth + 8;
+        uint16_t *sds = smem;
+        static_assert(kRowTile * DLD <= 2 * kStageA + 2 * kStageB, "silu' stage fits");
+#pragma unroll
+        for (int k = 0; k < kRowTile * kWidth / 8 / 256; ++k) {
+            const int c = tid + 256 * k, rr = c >> 5, cc = c & 31;
+            *reinterpret_cast<uint4 *>(&sds[rr * DLD + cc * 8]) =
+                *reinterpret_cast<const uint4 *>(g.dsin + (row0 + rr) * kWidth + cc * 8);
+        }
+        __syncthreads();
+        float dsin[4][16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                dsin[b][i] = bf2f(sds[(wm * 32 + 8 * (i >> 2) + 4 * hs + (i & 3)) * DLD + wn * 128 + b * 32 + r]);
+        __syncthreads();                         // every wave has its values: the stage may overwrite
+        constexpr int HLD = 128 + 8;             // stage row stride (bf16), 16-byte aligned
+        uint16_t *stg = smem + wave * 32 * HLD;
+        static_assert(4 * 32 * HLD <= 2 * kStageA + 2 * kStageB, "epilogue stage fits");
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int col = wn * 128 + b * 32 + r;
-            const int64_t trow = row0 + wm * 64 + a * 32;   // first row of the tile
-            const float bias = EPI == kEpiFwd ? g.bias[col] : 0.0f;
-            float dsin[16];
-            if constexpr (EPI == kEpiBwd) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    dsin[i] = bf2f(g.dsin[(trow + 8 * (i >> 2) + 4 * hs + (i & 3)) * kWidth + col]);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {            // rows 8 q + 4 hs + (0..3) of the tile
+            for (int q = 0; q < 4; ++q) {
                 const int rt = 8 * q + 4 * hs;
                 uint16_t hv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float v = acc[a][b][4 * q + j];
-                    float out;
-                    if constexpr (EPI == kEpiFwd) {
-                        const float z = v + bias;
-                        const float s = sigmoidf_(z);
-                        out = z * s;
-                        dst[(rt + j) * HLD + r] = f2bf(dsilu_s(z, s));
-                    } else {
-                        out = v * dsin[4 * q + j];
-                        csum[b] += out;
-                    }
+                    const float out = acc[b][4 * q + j] * dsin[b][4 * q + j];
+                    csum[b] += out;
                     hv[j] = f2bf(out);
-                    hst[(rt + j) * HLD + r] = hv[j];
+                    stg[(rt + j) * HLD + b * 32 + r] = hv[j];
                 }
-                if (g.out_k8) {
-                    // k8 layout: rows rt .. rt + 3 of column col are 4 consecutive entries
-                    const int64_t rb = trow + rt;
-                    const int64_t k8 = ((rb >> 3) * kWidth + col) * 8 + (rb & 7);
-                    uint2 pk;
-                    pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
-                    pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
-                    *reinterpret_cast<uint2 *>(g.out_k8 + k8) = pk;
-                }
+                if (g.out_k8) store_k8(col, rt, hv);
             }
-            __builtin_amdgcn_wave_barrier();     // the wave's stage writes before its reads
-            const int c0 = wn * 128 + b * 32;
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {        // h: 32 rows x 4 chunks of 8
-                const int c = lane + 64 * k, rr = c >> 2, cc = c & 3;
-                *reinterpret_cast<uint4 *>(g.out_h + (trow + rr) * kWidth + c0 + cc * 8) =
-                    *reinterpret_cast<const uint4 *>(&hst[rr * HLD + cc * 8]);
-            }
-            if (EPI == kEpiFwd && g.out_ds) {
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int c = lane + 64 * k, rr = c >> 2, cc = c & 3;
-                    *reinterpret_cast<uint4 *>(g.out_ds + (trow + rr) * kWidth + c0 + cc * 8) =
-                        *reinterpret_cast<const uint4 *>(&dst[rr * HLD + cc * 8]);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();     // reads done before the next tile's writes
         }
+        __builtin_amdgcn_wave_barrier();        // the wave's stage writes before its reads
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {           // 32 rows x 16 chunks of 16 bytes
+            const int c = lane + 64 * k, rr = c >> 4, cc = c & 15;
+            *reinterpret_cast<uint4 *>(g.out_h + (trow + rr) * kWidth + wn * 128 + cc * 8) =
+                *reinterpret_cast<const uint4 *>(&stg[rr * HLD + cc * 8]);
+        }
+    }
     if constexpr (EPI == kEpiBwd) {
-        // column sums over the block's 128 rows in a fixed order: the two row halves of a
-        // tile (lanes l and l ^ 32), the wave's two row tiles (already in csum), then the
-        // two row-halves of the block (waves wm = 0, 1) through LDS
+        // column sums over the block's 64 rows in a fixed order: the two row halves of a
+        // tile (lanes l and l ^ 32), then the two row-halves of the block (waves wm = 0, 1)
+        // through LDS
 #pragma unroll
         for (int b = 0; b < 4; ++b) csum[b] += __shfl_xor(csum[b], 32, 64);
         if (hs == 0)
@@ -753,9 +787,9 @@ __global__ __launch_bounds__(kFusedThreads, 1) void infer_fused_kernel(FusedArgs
 // ---------------------------------------------------------------- launchers
 hipError_t launch_rows(int epi, const RowsArgs &g, hipStream_t st)
 {
-    if (g.M % kRowBlock || (g.K != kIn1 && g.K != kWidth) || (epi != kEpiFwd && epi != kEpiBwd))
+    if (g.M % kRowTile || (g.K != kIn1 && g.K != kWidth) || (epi != kEpiFwd && epi != kEpiBwd))
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(g.M / kRowBlock));
+    const dim3 grid((unsigned)(g.M / kRowTile));
     if (epi == kEpiFwd) {
         if (g.K == kIn1) hipLaunchKernelGGL((gemm_rows_kernel<kEpiFwd, kIn1>), grid, dim3(256), 0, st, g);
         else hipLaunchKernelGGL((gemm_rows_kernel<kEpiFwd, kWidth>), grid, dim3(256), 0, st, g);

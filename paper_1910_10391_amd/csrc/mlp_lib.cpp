@@ -77,7 +77,7 @@ struct MWs {
     float *y, *cb;
     float *part[3];      // split-K partials of the W3, W2, W1 gradients
     float *opart;        // output-layer partials [Bp / 64][514]
-    float *colpart[2];   // column partials of dz2, dz1 [Bp / 128][256]
+    float *colpart[2];   // column partials of dz2, dz1 [Bp / 64][256]
     size_t total;
 };
 
@@ -126,7 +126,7 @@ MWs carve(char *base, int64_t Bp, int n_traj)
     w.y = (float *)take((size_t)Bp * 4);
     for (int l = 0; l < 3; ++l) w.part[l] = (float *)take((size_t)kSplits * kWidth * (l == 2 ? kIn1 : kWidth) * 4);
     w.opart = (float *)take((size_t)(Bp / kOutPointsHost) * kOutPartHost * 4);
-    for (int l = 0; l < 2; ++l) w.colpart[l] = (float *)take((size_t)(Bp / kRowBlock) * kWidth * 4);
+    for (int l = 0; l < 2; ++l) w.colpart[l] = (float *)take((size_t)(Bp / kRowTile) * kWidth * 4);
     w.cb = (float *)take((size_t)std::max(n_traj, 1) * kWidth * 4);
     w.total = o;
     return w;
@@ -372,8 +372,8 @@ rad_status rad_mlp_grad(const rad_mlp *m, const float *feat, int n_traj, const i
     const int64_t woff[3] = {L.w3, L.w2, L.w1};
     for (int l = 0; l < 3; ++l) f.w[l] = FinishW{w.part[l], splits, nprev[l], l == 2 ? L.n_in : kWidth, grad + woff[l], 0};
     f.c[0] = FinishC{w.opart, kOutPartHost, Bp / kOutPointsHost, 2 * kWidth + 2, 2 * kWidth + 1, grad + L.b3, loss_sum, 0};
-    f.c[1] = FinishC{w.colpart[0], kWidth, Bp / kRowBlock, kWidth, kWidth, grad + L.b2, nullptr, 0};
-    f.c[2] = FinishC{w.colpart[1], kWidth, Bp / kRowBlock, kWidth, kWidth, grad + L.b1, nullptr, 0};
+    f.c[1] = FinishC{w.colpart[0], kWidth, Bp / kRowTile, kWidth, kWidth, grad + L.b2, nullptr, 0};
+    f.c[2] = FinishC{w.colpart[1], kWidth, Bp / kRowTile, kWidth, kWidth, grad + L.b1, nullptr, 0};
     CK(launch_finish_grad(f, st));
 #undef CK
     return RAD_OK;
