@@ -308,7 +308,8 @@ rad_status rad_tune_set_shape(int persistent, int mixed, int wg);
  * tiles (0 or 1, the default: a whole 8 x 8 cell for 64 energies).  A larger wg shares
  * each staged direction among more energies, and evaluates a cell for whole blocks of
  * 64 wg energies.  The sums are those of wg = 1, to rounding (the time chunking follows
- * the item count).  RAD_EINVAL for other values.
+ * the item count, and so may the workspace sizes: query them after setting it).
+ * RAD_EINVAL for other values.
  */
 rad_status rad_tune_set_cell_spread(int wg);
 int rad_tune_get_cell_spread(void);
