@@ -331,11 +331,6 @@ __global__ __launch_bounds__(512) void gemm_k8_kernel(K8Args g)
 }
 
 // ---------------------------------------------------------------- reductions
-// Column sums, out[n] = sum over rows m of X[m][n] (row stride ld), X FP32, in two passes
-// of one kernel: pass 1 over `slices` row slices writes part[s][n], pass 2 sums the
-// slices.  A block of 256 threads takes nb columns x (256 / nb) row lanes: lane j of a
-// column sums rows m0 + j, m0 + j + lanes, ... of its slice in order, then the lanes are
-// added in a fixed LDS tree, so the result is deterministic.
 // The gradient's reductions, one launch at the end of the backward pass (none of the
 // step's other kernels reads them).  Tasks, by block range:
 // * W tasks: out[r][c] = sum over the split-K slices s of part[s][r][src_cols r + c]
