@@ -137,3 +137,27 @@ def test_checkpoint_resume_is_bitwise(M, tmp_path):
         b.train_step(*dev, lr=1e-3)
     assert np.array_equal(a.get_params(), b.get_params())
     assert a.get_adam()[2] == b.get_adam()[2] == 7
+
+
+@pytest.mark.parametrize("B,n_traj", [(300, 3), (1000, 5), (65536, 64)])
+def test_gradients_at_training_sizes_are_reproducible(M, B, n_traj):
+    """The gradient at the training batch (65 536 points: 64 split-K slices of the weight
+    gradients placed by XCD, the final reductions over 1024 output-layer and 1024 bias
+    partial rows) and at ragged batches that pad to 384 rows (one slice) and 1024 rows
+    (8 slices): against the CPU reference with BF16 rounding, and bit for bit the same
+    on a second call (every reduction has a fixed order)."""
+    import torch
+    net = M.MLP(38, 3, seed=11)
+    (feat, traj, x, target), dev = _data(17 + B, nf=38, npnt=3, B=B, n_traj=n_traj)
+    g1, l1 = net.grad(*dev)
+    g2, l2 = net.grad(*dev)
+    assert torch.equal(g1, g2) and torch.equal(l1, l2), "gradient not reproducible"
+    g = g1.cpu().numpy().astype(np.float64)
+    theta = net.get_params().astype(np.float64)
+    loss, gr = ref.loss_and_grad(theta, feat, traj, x, target, bf=True)
+    assert abs(l1.item() / B - loss) <= 1e-4 * loss
+    for name, o, n in _blocks(41):
+        a, b = g[o:o + n], gr[o:o + n]
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print("B %d grad %s: rel err %.2e" % (B, name, err), flush=True)
+        assert err < 5e-3, (B, name)
