@@ -371,8 +371,14 @@ rad_status plan_build(rad_grid *g, const rad_segment *segs, int n_segs, const in
         std::vector<int> fill(cnt.begin(), cnt.end() - 1);
         for (int s = 0; s < n_segs; ++s) list[fill[out_index[s]]++] = s;
     }
-    P.persistent = persistent;
-    if (persistent) {
+    // A one-block-per-item launch holds at most 2^32 - 1 work-items (2^24 - 1 blocks of
+    // 256).  Its partial amplitudes take 128 kB per block on a full direction tile, so only
+    // a grid of very many energies over few directions gets there within device memory;
+    // such a launch runs its items on the persistent kernel with the same tile (the same
+    // sums per item, bit for bit).
+    const int64_t max_item_blocks = (int64_t)(0xffffffffu / kBlock);
+    P.persistent = persistent || std::max(blocks_c, blocks_q) > max_item_blocks;
+    if (P.persistent) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
@@ -996,8 +1002,6 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
             }
         }
     C.n_ps = (int)ps.size();
-    const int64_t base_items = 0;
-    (void)base_items;
     int64_t items = 0;
     for (auto &v : wbs) items += (int64_t)v.size() * C.n_groups;
     // time chunks: enough items to fill the GPU
@@ -1096,6 +1100,10 @@ rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, 
     if (dev_mask && !mask) return fail(RAD_EINVAL, "mask is NULL");
     rs = cells_plan(g, segs, n_segs, kind, cx, cy, dev_mask ? nullptr : mask, true, C, comps, dev_mask);
     if (rs != RAD_OK) return rs;
+    // one block per item, at most 2^32 - 1 work-items (the partial amplitudes of that many
+    // items, 128 kB each, would not fit in device memory anyway)
+    if (C.n_items > (int64_t)(0xffffffffu / kBlock))
+        return fail(RAD_EUNSUPPORTED, "cell launch of %lld blocks", (long long)C.n_items);
     if (dev_mask) {
         rs = check_dev_range(mask, (size_t)n_segs * g->n_w * C.n_cells, "mask");
         if (rs != RAD_OK) return rs;
