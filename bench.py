@@ -93,8 +93,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one device copy of known size first (counter scale factor)")
     p.add_argument("--no-legs", action="store_true",
-                   help="skip the secondary legs of the default line (mixed-precision and sections "
-                        "workloads, learned sampler, issue-rate ceilings)")
+                   help="skip the secondary legs of the default line (mixed-precision, sections, sweep "
+                        "and trajectory-generator workloads, learned sampler, issue-rate ceilings)")
     return p.parse_args()
 
 
@@ -232,25 +232,25 @@ def bench_pm(args):
     }
 
 
-def bench_sweep(args):
-    """Timing against the number of integrals (the axis of the paper's Sec. V timing
-    figure): one 3000-sample trajectory, FP64 classical spectrum, 10^2 .. 10^8
-    integrals (10 x 10 directions x 1 .. 10^6 photon energies).  GPU time with the
-    inputs resident, GPU time including the host copies (trajectory in, cube out), and
-    the CPU oracle on the host's cores up to 10^6 integrals; the crossover is the
-    smallest count where the GPU with copies beats the CPU."""
+SWEEP_WORKLOAD = ("sweep: 3000-sample undulator trajectory (gamma 2e4, K 0.5), FP64 classical, 10x10 "
+                  "directions within 1/gamma x 1..1e6 linear hw up to 1.5 x the first harmonic")
+
+
+def sweep_rows(counts, cpu_max):
+    """One 3000-sample trajectory, FP64 classical spectrum, N integrals (10 x 10 directions x
+    N / 100 photon energies) for each N in `counts`: GPU time with the inputs resident, as a
+    plan replayed from a hipGraph, and including the host copies (trajectory in, cube out);
+    the CPU oracle on the host's cores up to `cpu_max` integrals, and the GPU result's error
+    against it."""
     import torch
     import oracle
     from paper_1910_10391_amd import rad
     from paper_1910_10391_amd.synth import analytic
     seg = analytic.undulator(2e4, 0.5, 20e-6, 20, n_steps=2999)
     ds = rad.DeviceSegments([seg])
-    g = 2e4
-    th = analytic.cell_centred(10, 1.0 / g)
+    th = analytic.cell_centred(10, 1.0 / 2e4)
     fund = analytic.undulator_fundamental_eV(2e4, 0.5, 20e-6)
-    counts = [10 ** e for e in range(2, 9)]
     rows = []
-    threads = oracle.max_threads()
     for N in counts:
         n_w = N // 100
         hw = analytic.linear_omega(n_w, 1.5 * fund)
@@ -289,31 +289,51 @@ def bench_sweep(args):
         gdiff = float((pout[0, 0] - out).abs().max() / out.abs().max().clamp_min(1e-300))
         assert gdiff < 1e-12, "graph replay differs from the direct call: %.3e" % gdiff
         plan.close()
-        cpu = None
-        if N <= 10 ** 6:
+        cpu, err = None, None
+        if N <= cpu_max:
             t0 = time.perf_counter()
             ref = oracle.spectrum(seg, hw, th, th, oracle.KIND_CLASSICAL)[oracle.KIND_CLASSICAL]
             cpu = time.perf_counter() - t0
             err = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
-        else:
-            err = None
         rows.append({"integrals": N, "gpu_s": dt, "gpu_graph_s": dtg, "gpu_with_copies_s": dtc,
                      "cpu_oracle_s": cpu, "evals_per_s": 3000.0 * N / dt, "rel_err_vs_oracle_M1": err})
         print("bench sweep: %9d integrals  gpu %.3e s  graph replay %.3e s  with copies %.3e s  cpu %s" % (
             N, dt, dtg, dtc, "%.3e s" % cpu if cpu else "-"), file=sys.stderr, flush=True)
+        del ws, out, host, pout
         grid.close()
-    cross = next((r["integrals"] for r in rows if r["cpu_oracle_s"] and r["gpu_with_copies_s"] < r["cpu_oracle_s"]),
-                 None)
+    return rows
+
+
+def sweep_crossover(rows):
+    """The smallest count where the GPU with its copies beats the CPU oracle."""
+    return next((r["integrals"] for r in rows if r["cpu_oracle_s"] and r["gpu_with_copies_s"] < r["cpu_oracle_s"]),
+                None)
+
+
+def bench_sweep(args):
+    """Timing against the number of integrals (the axis of the paper's Sec. V timing
+    figure): 10^2 .. 10^8 integrals, the CPU oracle up to 10^6; the crossover is the
+    smallest count where the GPU with copies beats the CPU."""
+    import oracle
+    rows = sweep_rows([10 ** e for e in range(2, 9)], 10 ** 6)
     top = rows[-1]
     return {
         "metric": METRIC, "value": top["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": top["gpu_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "sweep: 3000-sample undulator trajectory (gamma 2e4, K 0.5), FP64 classical, "
-                               "10x10 directions within 1/gamma x 1..1e6 linear hw up to 1.5 x the first "
-                               "harmonic; 1e2..1e8 integrals"},
-        "sweep": rows, "crossover_integrals_vs_cpu": cross, "cpu_cores": threads,
+        "config": {"workload": SWEEP_WORKLOAD + "; 1e2..1e8 integrals"},
+        "sweep": rows, "crossover_integrals_vs_cpu": sweep_crossover(rows), "cpu_cores": oracle.max_threads(),
     }
+
+
+def leg_sweep():
+    """The sweep at 10^2, 10^3, 10^4, 10^5, 10^6 and 10^8 integrals, the CPU oracle up to
+    10^5 (a few seconds in all)."""
+    import oracle
+    rows = sweep_rows([10 ** 2, 10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6, 10 ** 8], 10 ** 5)
+    return {"workload": SWEEP_WORKLOAD + "; 1e2..1e8 integrals (CPU up to 1e5)", "rows": rows,
+            "crossover_integrals_vs_cpu": sweep_crossover(rows), "cpu_cores": oracle.max_threads(),
+            "evals_per_s_at_1e8": rows[-1]["evals_per_s"]}
 
 
 def bench_traj(args):
@@ -696,6 +716,40 @@ def leg_sections():
                                   "sample": "trajectory 0 (10 sections), every 8th energy, 4x4 strided directions"}}
 
 
+def leg_traj():
+    """The GPU trajectory generator on the benchmark's 256 positrons against the CPU generator
+    on the host's cores (and the host-to-device copy the GPU generator saves); four of the
+    particles compared with the CPU generator's columns bit for bit."""
+    import torch
+    from paper_1910_10391_amd import rad, traj
+    from paper_1910_10391_amd.synth import channeling, presets
+    n = 256
+    cfg = presets.positron_config()
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    trs = channeling.generate(cfg, n, threads=threads)
+    cpu_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ds_host = rad.DeviceSegments([tr[0] for tr in trs])
+    torch.cuda.synchronize()
+    h2d = time.perf_counter() - t0
+    del ds_host, trs
+    traj.DeviceTrajectories(cfg, n)          # warm-up
+    torch.cuda.synchronize()
+    dt_gen = timed(lambda: traj.DeviceTrajectories(cfg, n), 2, torch.cuda.synchronize)
+    d = traj.DeviceTrajectories(cfg, n)
+    cols = ("t", "x", "y", "dz", "vx", "vy", "dvz", "ax", "ay", "az", "energy")
+    same = all(np.array_equal(d.host(i)[c], ref[c])
+               for i in (0, 85, 170, 255) for ref in [channeling.trajectory(cfg, i)] for c in cols)
+    samples = int(sum(d.n))
+    print("bench leg traj: gpu %.3f s, cpu generator %.3f s (%d threads), host->device copy %.3f s, "
+          "sampled particles bitwise equal: %s" % (dt_gen, cpu_gen, threads, h2d, same), file=sys.stderr, flush=True)
+    return {"workload": "traj: the benchmark's %d positrons (%d samples) generated on the GPU" % (n, samples),
+            "gpu_s": dt_gen, "cpu_generator_s": cpu_gen, "cpu_threads": threads, "host_to_device_copy_s": h2d,
+            "speedup_vs_cpu": cpu_gen / dt_gen, "speedup_vs_cpu_plus_copy": (cpu_gen + h2d) / dt_gen,
+            "gpu_samples_per_s": samples / dt_gen, "bitwise_equal_particles_0_85_170_255": bool(same)}
+
+
 SAMPLER_CKPT = os.path.join(ROOT, "paper_1910_10391_amd", "weights", "positron_spinhalf_sampler.npz")
 
 
@@ -894,6 +948,10 @@ def main():
         legs["pm_mixed"] = run_leg("pm_mixed", leg_pm_mixed)
         torch.cuda.empty_cache()
         legs["electron_50gev_sections"] = run_leg("sections", leg_sections)
+        torch.cuda.empty_cache()
+        legs["sweep"] = run_leg("sweep", leg_sweep)
+        torch.cuda.empty_cache()
+        legs["traj"] = run_leg("traj", leg_traj)
         torch.cuda.empty_cache()
     res = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
