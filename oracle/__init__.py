@@ -112,13 +112,21 @@ def _load(path=None):
             lib.oracle_spectrum.restype = cint
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = cint
+            # the OpenMP thread count before any call sets one
+            lib.default_threads = int(lib.oracle_max_threads())
             _libs[path] = lib
     return _libs[path]
 
 
+def _threads(lib, threads):
+    """threads > 0 as given; 0: the host's default count (a call with threads = 1 sets
+    OpenMP's count for later calls, so the default is passed explicitly)."""
+    return int(threads) if threads > 0 else lib.default_threads
+
+
 def max_threads() -> int:
     """OpenMP threads the oracle uses by default on this host."""
-    return int(_load().oracle_max_threads())
+    return _threads(_load(), 0)
 
 
 _COLS = ("t", "x", "y", "dz", "vx", "vy", "dvz", "ax", "ay", "az")
@@ -164,7 +172,7 @@ def amplitudes(seg, kappa, nx, ny, want_j=True, threads=0):
     rc = lib.oracle_amplitudes(*args, ctypes.c_double(float(seg["gamma"])),
                                ctypes.c_int64(kappa.size), _ptr(kappa), ctypes.c_int64(nx.size),
                                _ptr(nx), _ptr(ny), _ptr(A), _ptr(J) if want_j else None,
-                               ctypes.c_int(threads))
+                               ctypes.c_int(_threads(lib, threads)))
     if rc != 0:
         raise ValueError("oracle_amplitudes rejected its arguments")
     del keep
@@ -200,7 +208,7 @@ def spectrum(seg, hw_eV, thx, thy, kinds=KIND_CLASSICAL, threads=0):
                              ctypes.c_double(float(seg.get("energy_eV", np.inf))),
                              ctypes.c_int(hw.size), _ptr(hw), ctypes.c_int(thx.size), _ptr(thx),
                              ctypes.c_int(thy.size), _ptr(thy), ctypes.c_int(kinds), _ptr(out),
-                             ctypes.c_int(threads))
+                             ctypes.c_int(_threads(lib, threads)))
     if rc != 0:
         raise ValueError("oracle_spectrum rejected its arguments")
     del keep
