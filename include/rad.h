@@ -303,13 +303,18 @@ int rad_tune_num_variants(void);
  */
 rad_status rad_tune_set_shape(int persistent, int mixed, int wg);
 /*
- * The cell integrals' block shape (rad_cells, rad_cells_device): wg = 1, 2 or 4 of a
- * block's 4 waves over photon energies, the others over the cell's 4 x 4 direction
- * tiles (0 or 1, the default: a whole 8 x 8 cell for 64 energies).  A larger wg shares
- * each staged direction among more energies, and evaluates a cell for whole blocks of
- * 64 wg energies.  The sums are those of wg = 1, to rounding (the time chunking follows
- * the item count, and so may the workspace sizes: query them after setting it).
- * RAD_EINVAL for other values.
+ * The cell integrals' block shape (rad_cells, rad_cells_device).  A cell is evaluated
+ * for each block of 64 photon energies that holds a selected energy.  0, the default,
+ * groups these blocks: those of one (segment, cell, time chunk) are taken in order by
+ * four, then two, then one, and a group of k blocks runs as k work items, each of whose
+ * 4 waves takes one block and whose 4 / k direction tiles are among the cell's four
+ * 4 x 4 tiles, so that each staged direction serves up to 256 energies; the sums are
+ * those of wg = 1, bit for bit (grids of more than 256 blocks run as wg = 1).  wg = 1,
+ * 2 or 4 fixes a block's spread: wg adjacent energy blocks for 4 / wg tiles (wg = 1: the
+ * whole 8 x 8 cell for 64 energies), so wg > 1 evaluates a cell for whole groups of
+ * 64 wg energies; its sums are those of wg = 1 to rounding (the time chunking follows the
+ * item count, and so may the workspace sizes: query them after setting it).  RAD_EINVAL
+ * for other values.  rad_tune_get_cell_spread returns the setting (0: grouped).
  */
 rad_status rad_tune_set_cell_spread(int wg);
 int rad_tune_get_cell_spread(void);

@@ -76,12 +76,16 @@ struct AmpLaunch {
 
 // Device-side compaction of the cell refinement's items: items (in launch order) whose
 // photon-energy block has a mask bit set, for pseudo-segment p = (p / n_cells, p % n_cells)
-// = (segment, cell), keep their order in `live`, their number in *n_live.
+// = (segment, cell), keep their order in `live`, their number in *n_live.  wg = 0: the
+// grouped form, whose dense items come in rows of n_wb (one per (pseudo-segment, time
+// chunk), blocks 0 .. n_wb - 1) and are first regrouped row by row into `grouped`.
 struct CellCompact {
     const int4 *items;
     int64_t n_items;
     const uint8_t *mask;     // [n_segs][n_w][n_cells]
     int n_cells, n_w, wg;
+    int n_wb;                // 64-energy blocks per row (grouped form)
+    int4 *grouped;           // [n_items] (grouped form)
     int *flags;              // [n_items]
     int4 *live;              // [n_items]
     int *n_live;

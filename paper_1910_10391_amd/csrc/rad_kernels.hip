@@ -170,13 +170,27 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     int64_t k_end = uniform64(min(n, k_begin + (int64_t)S.chunk_len));
     if (!RAD_DEBUG_OK(chunk >= 0 && chunk < S.n_chunks && k_begin < n)) k_end = k_begin;
 
-    const int nt = L.nt, wg = L.wg;
+    int nt = L.nt, wg = L.wg;
+    // grouped cell items (a launch with wg = 0) carry their own shape: the item's waves
+    // over photon energies in bits 8..15 of its tile-group field, and its wg 64-energy
+    // blocks (not necessarily adjacent) one byte per wave in the block field
+    const bool grouped = CELLS && wg == 0;
+    if (grouped) {
+        wg = grp >> 8;
+        grp &= 0xff;
+        if (!(wg == 1 || wg == 2 || wg == 4)) {   // leaves before any barrier of the item
+            (void)RAD_DEBUG_OK(false);
+            return;
+        }
+        nt = kWavesPerBlock / wg;
+    }
     const int lnt = nt == 4 ? 2 : (nt == 2 ? 1 : 0);   // nt is 1, 2 or 4 (checked at launch)
     const int T = kSlots / nt;
     const int n_tiles = n_tx * S.n_ty;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int tl = wave / wg;
-    const int iw = (wb * wg + wave % wg) * kWave + lane;
+    const int wblock = grouped ? (int)(((unsigned)wb >> (8 * (wave % wg))) & 0xffu) : wb * wg + wave % wg;
+    const int iw = wblock * kWave + lane;
     const int gtile = grp * nt + tl;
 
     double kappa = 0.0;
@@ -800,6 +814,9 @@ hipError_t launch_amp(const AmpLaunch &L, int variant, bool withj, bool mixed, i
     if (!occupancy && L.nt != 1 && L.nt != 2 && L.nt != 4) return hipErrorInvalidValue;
     // compacted cell items need the item list and the one-block-per-item form
     if (L.n_live && (grid_blocks > 0 || !L.items)) return hipErrorInvalidValue;
+    // so do grouped cell items (wg = 0: each item carries its shape); else wg is 1, 2 or 4
+    if (!occupancy && L.wg == 0 && (grid_blocks > 0 || !L.items)) return hipErrorInvalidValue;
+    if (!occupancy && L.wg != 0 && L.wg != 1 && L.wg != 2 && L.wg != 4) return hipErrorInvalidValue;
     if (withj)
         return mixed ? launch_amp_v<true, true>(L, variant, grid_blocks, st, occupancy)
                      : launch_amp_v<true, false>(L, variant, grid_blocks, st, occupancy);
@@ -862,15 +879,68 @@ __global__ __launch_bounds__(1024) void cell_compact_kernel(CellCompact C)
     if (t == 0) *C.n_live = base;
 }
 
+// Pass 1 of the grouped form: one wave per row of n_wb dense items (p, chunk, 0, b).  The
+// row's blocks with a mask bit set are taken in order by four, then by two, then one by one
+// (the remainder of 3 as 2 + 1); a group of k blocks becomes k items, tile group
+// g = 0 .. k - 1 with k in bits 8..15 and the k block indices one byte each, written in
+// order to the row's first slots of `grouped` and flagged; the row's other slots are left
+// unflagged.  The items are as many as the selected blocks, as in the one-block form.
+__global__ __launch_bounds__(256) void cell_group_kernel(CellCompact C)
+{
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (r >= C.n_items / C.n_wb) return;
+    const int64_t i0 = r * C.n_wb;
+    const int4 it = C.items[i0];
+    const int s = it.x / C.n_cells, c = it.x % C.n_cells;
+    int j = 0;                      // items written so far (wave-uniform)
+    auto emit = [&](int k, uint32_t blocks) {
+        if (lane < k) {
+            C.grouped[i0 + j + lane] = make_int4(it.x, it.y, lane | (k << 8), (int)blocks);
+            C.flags[i0 + j + lane] = 1;
+        }
+        j += k;
+    };
+    uint32_t pend = 0;              // pending block indices, one byte each
+    int np = 0;
+    for (int b = 0; b < C.n_wb; ++b) {
+        const int w = b * kWave + lane;
+        if (__any(w < C.n_w && C.mask[((int64_t)s * C.n_w + w) * C.n_cells + c] != 0)) {
+            pend |= (uint32_t)b << (8 * np);
+            if (++np == 4) {
+                emit(4, pend);
+                pend = 0;
+                np = 0;
+            }
+        }
+    }
+    if (np >= 2) {
+        emit(2, pend & 0xffffu);
+        pend >>= 16;
+        np -= 2;
+    }
+    if (np == 1) emit(1, pend);
+    for (int k = j + lane; k < C.n_wb; k += kWave) C.flags[i0 + k] = 0;
+}
+
 hipError_t launch_cell_compact(const CellCompact &C, hipStream_t st)
 {
     // the live count and offsets are 32-bit
-    if (C.n_items < 1 || C.n_items > 0x7fffffff || C.n_cells < 1 || C.wg < 1) return hipErrorInvalidValue;
-    const int64_t threads = C.n_items * kWave;
-    hipLaunchKernelGGL(cell_flags_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, C);
+    if (C.n_items < 1 || C.n_items > 0x7fffffff || C.n_cells < 1 || C.wg < 0) return hipErrorInvalidValue;
+    CellCompact P = C;
+    if (C.wg == 0) {
+        // block indices are packed in bytes; rows are whole
+        if (C.n_wb < 1 || C.n_wb > 256 || C.n_items % C.n_wb || !C.grouped) return hipErrorInvalidValue;
+        const int64_t threads = C.n_items / C.n_wb * kWave;
+        hipLaunchKernelGGL(cell_group_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, C);
+        P.items = C.grouped;
+    } else {
+        const int64_t threads = C.n_items * kWave;
+        hipLaunchKernelGGL(cell_flags_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, C);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cell_compact_kernel, dim3(1), dim3(1024), 0, st, C);
+    hipLaunchKernelGGL(cell_compact_kernel, dim3(1), dim3(1024), 0, st, P);
     return hipGetLastError();
 }
 

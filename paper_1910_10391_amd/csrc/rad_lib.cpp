@@ -942,16 +942,23 @@ struct CellsPlan {
     int n_ps = 0;                 // active (segment, cell) pseudo-segments
     int64_t n_items = 0;
     bool dense = false;           // device mask: every (segment, cell) pair, p = s * n_cells + c
-    int wg = 1, n_groups = 1;     // waves over photon energies; direction-tile groups per cell
+    // waves over photon energies (the launch's wg; 0: grouped, each item carries its own)
+    // and direction-tile groups per cell
+    int wg = 1, n_groups = 1;
+    bool grouped = false;
     size_t off_ps, off_items, off_psof, off_mask, off_part, desc_bytes, total;
     size_t off_flags = 0, off_live = 0, off_nlive = 0;   // device-mask compaction (dense plans)
+    size_t off_grouped = 0;                               // its regrouped items (grouped form)
     std::vector<char> host;
 };
 
 // Cell items: a block spreads its 4 waves over wg groups of 64 photon energies and
 // 4 / wg of the cell's four 4 x 4 direction tiles (wg = 1: the whole 8 x 8 cell for 64
-// energies; the default).
-int g_cell_wg = 1;
+// energies).  0, the default, groups: the selected 64-energy blocks of a (segment, cell,
+// time chunk) are taken by four (wg = 4, one tile per item), then two, then one, so that a
+// staged direction serves up to 256 energies while a cell is still evaluated only for the
+// blocks that have a selected energy.
+int g_cell_wg = 0;
 
 int cell_wg()
 {
@@ -979,8 +986,13 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     C.ncy = g->n_y / cy;
     C.n_cells = C.ncx * C.ncy;
     C.wg = cell_wg();
-    C.n_groups = ((cx / 4) * (cy / 4)) / (kWavesPerBlock / C.wg);
-    C.n_wb = (g->n_w + kWave * C.wg - 1) / (kWave * C.wg);
+    // the grouped form plans as wg = 1 (one item per selected block and tile group of the
+    // whole cell); its block indices travel as bytes, so past 256 blocks it is wg = 1
+    C.grouped = C.wg == 0 && (g->n_w + kWave - 1) / kWave <= 256;
+    if (C.wg == 0 && !C.grouped) C.wg = 1;
+    const int wgp = C.grouped ? 1 : C.wg;
+    C.n_groups = ((cx / 4) * (cy / 4)) / (kWavesPerBlock / wgp);
+    C.n_wb = (g->n_w + kWave * wgp - 1) / (kWave * wgp);
     const int n_w = g->n_w;
     // active (segment, cell) pairs and their photon-energy blocks
     std::vector<int> psof((size_t)n_segs * C.n_cells, -1);
@@ -991,7 +1003,7 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
             std::vector<int> blocks;
             for (int b = 0; b < C.n_wb; ++b) {
                 bool any = dense;
-                for (int w = b * kWave * C.wg; w < std::min(n_w, (b + 1) * kWave * C.wg) && !any; ++w)
+                for (int w = b * kWave * wgp; w < std::min(n_w, (b + 1) * kWave * wgp) && !any; ++w)
                     any = mask[((size_t)s * n_w + w) * C.n_cells + c] != 0;
                 if (any) blocks.push_back(b);
             }
@@ -1025,6 +1037,10 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
         C.off_flags = o; o = align_up(o + sizeof(int) * (size_t)std::max<int64_t>(items, 1));
         C.off_live = o; o = align_up(o + sizeof(int4) * (size_t)std::max<int64_t>(items, 1));
         C.off_nlive = o; o = align_up(o + sizeof(int));
+        if (C.grouped) {
+            C.off_grouped = o;
+            o = align_up(o + sizeof(int4) * (size_t)std::max<int64_t>(items, 1));
+        }
     }
     C.off_part = o;
     o = align_up(o + (size_t)sum_chunks * comps * cell_dirs * n_w * sizeof(double2));
@@ -1074,9 +1090,26 @@ rad_status cells_plan(const rad_grid *g, const rad_segment *segs, int n_segs, in
     }
     for (int r = 0; r < C.n_ps; ++r) {
         const int p = order[r];
-        for (int ch = 0; ch < nch[p]; ++ch)
-            for (int grp = 0; grp < C.n_groups; ++grp)
-                for (int b : wbs[p]) I[it++] = make_int4(p, ch, grp, b);
+        const std::vector<int> &v = wbs[p];
+        for (int ch = 0; ch < nch[p]; ++ch) {
+            if (C.grouped && !dense) {
+                // k blocks -> k items: tile group g in bits 0..7, k in bits 8..15, the
+                // blocks one byte each (the device mask's compaction groups the same way)
+                size_t q = 0;
+                auto put = [&](int k) {
+                    uint32_t packed = 0;
+                    for (int u = 0; u < k; ++u) packed |= (uint32_t)v[q + u] << (8 * u);
+                    for (int g = 0; g < k; ++g) I[it++] = make_int4(p, ch, g | (k << 8), (int)packed);
+                    q += k;
+                };
+                while (v.size() - q >= 4) put(4);
+                if (v.size() - q >= 2) put(2);
+                if (v.size() - q == 1) put(1);
+            } else {
+                for (int grp = 0; grp < C.n_groups; ++grp)
+                    for (int b : v) I[it++] = make_int4(p, ch, grp, b);
+            }
+        }
     }
     return RAD_OK;
 }
@@ -1130,8 +1163,8 @@ rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, 
         L.items = (const int4 *)(wsb + C.off_items);
         L.n_segs = C.n_ps;
         L.n_blocks = C.n_items;
-        L.wg = C.wg;
-        L.nt = kWavesPerBlock / C.wg;
+        L.wg = C.grouped ? 0 : C.wg;
+        L.nt = C.grouped ? kWavesPerBlock : kWavesPerBlock / C.wg;
         L.quantum = quantum ? 1 : 0;
         L.rec = g->dth != 0.0 ? 1 : 0;
         L.comps = comps;
@@ -1147,7 +1180,9 @@ rad_status cells_run(const rad_grid *grid, const rad_segment *segs, int n_segs, 
             K.mask = mask;
             K.n_cells = C.n_cells;
             K.n_w = g->n_w;
-            K.wg = C.wg;
+            K.wg = C.grouped ? 0 : C.wg;
+            K.n_wb = C.n_wb;
+            K.grouped = C.grouped ? (int4 *)(wsb + C.off_grouped) : nullptr;
             K.flags = (int *)(wsb + C.off_flags);
             K.live = (int4 *)(wsb + C.off_live);
             K.n_live = (int *)(wsb + C.off_nlive);
@@ -1287,7 +1322,7 @@ rad_status rad_tune_set_cell_spread(int wg)
 {
     if (wg != 0 && wg != 1 && wg != 2 && wg != 4) return fail(RAD_EINVAL, "wg %d: 0 (default), 1, 2 or 4", wg);
     std::lock_guard<std::mutex> lk(g_var_mu);
-    g_cell_wg = wg == 0 ? 1 : wg;
+    g_cell_wg = wg;
     return RAD_OK;
 }
 

@@ -3,9 +3,10 @@ the same mask read on the host, for empty, sparse, block-shaped and full masks, 
 photon-energy count that is not a multiple of 64, both precisions and the classical and
 spin-1/2 kinds: zeros where the mask is 0, the same values to rounding elsewhere (the
 device form plans the time chunks for every cell, so the order of the chunk sums can
-differ), bitwise for the full mask (the same plan); the FP64 cells against the
-direct-sum oracle; and the sampler's estimate through the device-mask path against the
-host-mask one."""
+differ), bitwise for the full mask (the same plan); the default grouped items against the
+one-block items, bit for bit, in both mask forms; the FP64 cells against the direct-sum
+oracle; and the sampler's estimate through the device-mask path against the host-mask
+one."""
 import ctypes
 import dataclasses
 
@@ -99,6 +100,51 @@ def test_device_mask_matches_host_mask(R):
         err = np.abs(b[s] - cellsum).max() / np.abs(cellsum).max()
         print("device-mask cells vs oracle, segment %d: %.2e" % (s, err), flush=True)
         assert err < 1e-9
+    grid.close()
+
+
+def test_grouped_items_equal_one_block_items(R):
+    """The default cell form groups a (segment, cell, time chunk)'s selected 64-energy blocks
+    by four, two and one (each staged direction then serves up to 256 energies): with both
+    mask forms its cells equal the one-block form's bit for bit (the same sums in the same
+    order, the same chunking).  450 energies (7 full blocks and a ragged one); per (segment,
+    cell) anything from no block to all eight, so that every group size and remainder
+    occurs."""
+    import torch
+    rad = R
+    cfg, segs = _positrons(3, first=7)
+    g = segs[0]["gamma"]
+    hw = analytic.log_omega(450, 1e6, 200e6)
+    th = analytic.cell_centred(16, 5.0 / g)
+    grid = rad.Grid(hw, th, th)
+    ds = rad.DeviceSegments(segs)
+    rng = np.random.default_rng(11)
+    n_wb = 8
+    masks = []
+    for case in range(3):
+        blocks = rng.random((3, n_wb, 4)) < (0.35, 0.6, 0.9)[case]   # (segment, block, cell)
+        m = (rng.random((3, 450, 4)) < 0.3) & np.repeat(blocks, 64, axis=1)[:, :450]
+        masks.append(m.astype(np.uint8))
+    full = np.ones((3, 450, 4), dtype=np.uint8)
+    try:
+        for i, m in enumerate(masks + [full]):
+            per = [[int(m[s, b * 64:(b + 1) * 64, c].any()) for b in range(n_wb)] for s in range(3) for c in range(4)]
+            sizes = sorted({sum(r) for r in per})
+            for form in ("host", "device"):
+                mm = m if form == "host" else torch.from_numpy(m).cuda()
+                for kind in (rad.CLASSICAL, rad.SPINHALF):
+                    for prec in (rad.FP64, rad.MIXED):
+                        rad.tune_set_cell_spread(0)
+                        assert rad.tune_get_cell_spread() == 0
+                        a = rad.cells(grid, ds, kind, mm, prec).cpu().numpy()
+                        rad.tune_set_cell_spread(1)
+                        b = rad.cells(grid, ds, kind, mm, prec).cpu().numpy()
+                        assert np.array_equal(a, b), (i, form, kind, prec)
+                        assert not a[m == 0].any() and (a[m != 0] != 0).all()
+            print("mask %d (%d selected energies, blocks per (segment, cell) %s): grouped = one-block, bitwise"
+                  % (i, int(m.sum()), sizes), flush=True)
+    finally:
+        rad.tune_set_cell_spread(0)
     grid.close()
 
 
