@@ -16,13 +16,14 @@
 
 namespace radtraj {
 
-// dU/dx of the periodic well for unit positive charge [eV/m]
-__device__ inline double slope(const rad_traj_params &p, double x)
+// dU/dx of the periodic well for unit positive charge [eV/m]; inv_d = 1 / d (a step's
+// slopes are on its critical path, and an IEEE division is a long dependent sequence here)
+__device__ inline double slope(const rad_traj_params &p, double x, double inv_d)
 {
     const double d = p.d_m;
-    const double xr = x - d * floor(x / d + 0.5);
-    const double u = 2.0 * xr / d;
-    return p.U0_eV * ((1.0 - p.q) * 2.0 * u + p.q * 4.0 * u * u * u) * (2.0 / d);
+    const double xr = x - d * floor(x * inv_d + 0.5);
+    const double u = 2.0 * xr * inv_d;
+    return p.U0_eV * ((1.0 - p.q) * 2.0 * u + p.q * 4.0 * u * u * u) * (2.0 * inv_d);
 }
 
 __device__ inline double gaussian(Stream &r)
@@ -51,6 +52,9 @@ __global__ __launch_bounds__(256) void kicks_kernel(TrajLaunch L)
     }
 }
 
+// steps whose kicks are loaded ahead of use
+constexpr int kKickAhead = 8;
+
 __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,6 +73,7 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
     const double h = p.length_m / (double)n;
     const double g_ref = p.energy_eV / kMe_eV;
     const double inv2g2_ref = 0.5 / (g_ref * g_ref);
+    const double inv_me = 1.0 / kMe_eV, inv_d = 1.0 / p.d_m;
     const double s = p.charge;
     double E = p.energy_eV;
     double x = (r.uniform() - 0.5) * p.d_m;
@@ -77,8 +82,9 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
     double y = 0.0, dz = 0.0;
     // velocities of the two previous samples, for the central-difference accelerations
     double v1x = 0.0, v1y = 0.0, v1z = 0.0, v2x = 0.0, v2y = 0.0, v2z = 0.0;
-    for (int64_t k = 0; k <= n; ++k) {
-        const double g = E / kMe_eV;
+    // sample k and step k -> k + 1 (the kick's unit normals given); false after the last sample
+    auto step = [&](int64_t k, double2 kick) -> bool {
+        const double g = E * inv_me;
         const double dvz = inv2g2_ref - 0.5 / (g * g) - 0.5 * (vx * vx + vy * vy);
         ct[k] = h * (double)k;
         cx[k] = x;
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
             cax[n] = (vx - v1x) / dt;
             cay[n] = (vy - v1y) / dt;
             caz[n] = (dvz - v1z) / dt;
-            break;
+            return false;
         }
         v2x = v1x;
         v2y = v1y;
@@ -112,10 +118,10 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
         v1z = dvz;
         // RK4 on (x, vx) with E frozen over the step
         const double f = -s / E;
-        const double k1x = vx, k1v = f * slope(p, x);
-        const double k2x = vx + 0.5 * h * k1v, k2v = f * slope(p, x + 0.5 * h * k1x);
-        const double k3x = vx + 0.5 * h * k2v, k3v = f * slope(p, x + 0.5 * h * k2x);
-        const double k4x = vx + h * k3v, k4v = f * slope(p, x + h * k3x);
+        const double k1x = vx, k1v = f * slope(p, x, inv_d);
+        const double k2x = vx + 0.5 * h * k1v, k2v = f * slope(p, x + 0.5 * h * k1x, inv_d);
+        const double k3x = vx + 0.5 * h * k2v, k3v = f * slope(p, x + 0.5 * h * k2x, inv_d);
+        const double k4x = vx + h * k3v, k4v = f * slope(p, x + h * k3x, inv_d);
         x += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
         vx += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
         y += h * vy;
@@ -125,12 +131,8 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
         }
         if (p.ms_on) {
             const double sig = (p.eps_s_eV / E) * sqrt(h / p.X0_m);
-            double gx, gy;
-            if (L.kicks) {
-                const double *kk = L.kicks + 2 * (k * L.n_particles + i);
-                gx = kk[0];
-                gy = kk[1];
-            } else {
+            double gx = kick.x, gy = kick.y;
+            if (!L.kicks) {
                 gx = gaussian(r);
                 gy = gaussian(r);
             }
@@ -139,9 +141,35 @@ __global__ __launch_bounds__(64) void traj_kernel(TrajLaunch L)
             vy += dty;
             if (p.loss_on) E -= kMe_eV * kAlpha / (2.0 * kPi) * g * g * g * (dtx * dtx + dty * dty);
         }
-        const double g1 = E / kMe_eV;
+        const double g1 = E * inv_me;
         const double dvz1 = inv2g2_ref - 0.5 / (g1 * g1) - 0.5 * (vx * vx + vy * vy);
         dz += 0.5 * h * (dvz + dvz1);
+        return true;
+    };
+    // The kicks of a group of kKickAhead steps are loaded while the group before it runs:
+    // a step's own load from HBM would otherwise sit on the critical path of the sequence.
+    double2 cur[kKickAhead], nxt[kKickAhead];
+    auto load_group = [&](int64_t k0, double2 (&dst)[kKickAhead]) {
+#pragma unroll
+        for (int j = 0; j < kKickAhead; ++j) {
+            const int64_t k = k0 + j;
+            dst[j] = make_double2(0.0, 0.0);
+            if (L.kicks && k < n) {
+                const double *kk = L.kicks + 2 * (k * L.n_particles + i);
+                dst[j] = make_double2(kk[0], kk[1]);
+            }
+        }
+    };
+    load_group(0, cur);
+    for (int64_t k0 = 0;; k0 += kKickAhead) {
+        load_group(k0 + kKickAhead, nxt);
+        bool more = true;
+#pragma unroll
+        for (int j = 0; j < kKickAhead; ++j)
+            if (more) more = step(k0 + j, cur[j]);
+        if (!more) break;
+#pragma unroll
+        for (int j = 0; j < kKickAhead; ++j) cur[j] = nxt[j];
     }
 }
 

@@ -157,13 +157,15 @@ static int64_t draw_length(const chan_params *p, rng_t *r)
     return n;
 }
 
-/* dU/dx of the periodic well for unit positive charge */
-static double well_slope(const chan_params *p, double x)
+/* dU/dx of the periodic well for unit positive charge; inv_d = 1 / d (multiplications
+ * instead of divisions: the GPU generator, whose steps are latency-bound, takes the same
+ * operations) */
+static double well_slope(const chan_params *p, double x, double inv_d)
 {
     const double d = p->d_m;
-    const double xr = x - d * floor(x / d + 0.5);
-    const double u = 2.0 * xr / d;
-    return p->U0_eV * ((1.0 - p->q) * 2.0 * u + p->q * 4.0 * u * u * u) * (2.0 / d);
+    const double xr = x - d * floor(x * inv_d + 0.5);
+    const double u = 2.0 * xr * inv_d;
+    return p->U0_eV * ((1.0 - p->q) * 2.0 * u + p->q * 4.0 * u * u * u) * (2.0 * inv_d);
 }
 
 /* Number of steps of each particle (the first draw of its stream). */
@@ -190,6 +192,7 @@ int chan_generate(const chan_params *p, int64_t particle, int64_t n, double *t, 
     const double h = p->length_m / (double)n;
     const double g_ref = p->energy_eV / SYN_ME_EV;
     const double inv2g2_ref = 0.5 / (g_ref * g_ref);
+    const double inv_me = 1.0 / SYN_ME_EV, inv_d = 1.0 / p->d_m;
     const double s = p->charge;
     double E = p->energy_eV;
     double xc = (u01(&r) - 0.5) * p->d_m;
@@ -197,7 +200,7 @@ int chan_generate(const chan_params *p, int64_t particle, int64_t n, double *t, 
     double vyc = p->theta_sigma * normal(&r);
     double yc = 0.0, dzc = 0.0;
     for (int64_t k = 0; k <= n; ++k) {
-        const double g = E / SYN_ME_EV;
+        const double g = E * inv_me;
         const double dvzc = inv2g2_ref - 0.5 / (g * g) - 0.5 * (vxc * vxc + vyc * vyc);
         t[k] = h * (double)k;
         x[k] = xc; y[k] = yc; vx[k] = vxc; vy[k] = vyc; dvz[k] = dvzc; dz[k] = dzc;
@@ -205,10 +208,10 @@ int chan_generate(const chan_params *p, int64_t particle, int64_t n, double *t, 
         if (k == n) break;
         /* RK4 on (x, vx) with E frozen over the step */
         const double f = -s / E;
-        const double k1x = vxc, k1v = f * well_slope(p, xc);
-        const double k2x = vxc + 0.5 * h * k1v, k2v = f * well_slope(p, xc + 0.5 * h * k1x);
-        const double k3x = vxc + 0.5 * h * k2v, k3v = f * well_slope(p, xc + 0.5 * h * k2x);
-        const double k4x = vxc + h * k3v, k4v = f * well_slope(p, xc + h * k3x);
+        const double k1x = vxc, k1v = f * well_slope(p, xc, inv_d);
+        const double k2x = vxc + 0.5 * h * k1v, k2v = f * well_slope(p, xc + 0.5 * h * k1x, inv_d);
+        const double k3x = vxc + 0.5 * h * k2v, k3v = f * well_slope(p, xc + 0.5 * h * k2x, inv_d);
+        const double k4x = vxc + h * k3v, k4v = f * well_slope(p, xc + h * k3x, inv_d);
         xc += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
         vxc += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
         yc += h * vyc;
@@ -226,7 +229,7 @@ int chan_generate(const chan_params *p, int64_t particle, int64_t n, double *t, 
             if (p->loss_on)
                 E -= SYN_ME_EV * SYN_ALPHA / (2.0 * SYN_PI) * g * g * g * (dtx * dtx + dty * dty);
         }
-        const double g1 = E / SYN_ME_EV;
+        const double g1 = E * inv_me;
         const double dvz1 = inv2g2_ref - 0.5 / (g1 * g1) - 0.5 * (vxc * vxc + vyc * vyc);
         dzc += 0.5 * h * (dvzc + dvz1);
     }
