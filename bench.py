@@ -57,10 +57,10 @@ def flops_per_eval(variant, with_j=True, recurrence=False):
 
 # VALU instructions per eval in the compiled hot loop of the 4x4 FP64 kernels (the
 # persistent and the one-block-per-item kernel compile to the same loop), counted in the
-# gfx950 assembly of this build (tests/test_codegen.py): direct phase factors 310 per 16
-# evals with J (278 without), recurrence on a uniform grid 278 (245).
-VALU_PER_EVAL_44 = {(True, False): 310.0 / 16.0, (False, False): 278.0 / 16.0,
-                    (True, True): 278.0 / 16.0, (False, True): 245.0 / 16.0}
+# gfx950 assembly of this build (tests/test_codegen.py): direct phase factors 308 per 16
+# evals with J (276 without), recurrence on a uniform grid 275 (243).
+VALU_PER_EVAL_44 = {(True, False): 308.0 / 16.0, (False, False): 276.0 / 16.0,
+                    (True, True): 275.0 / 16.0, (False, True): 243.0 / 16.0}
 # HBM bytes per amp_persistent launch on this workload from two rocprofv3 PMC passes
 # (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after calibration on a 1 GiB copy), valid only
 # for the kernel sources they were measured on (sha256 prefix below; a source change
@@ -571,9 +571,9 @@ PAPER_CONTEXT = {
 }
 
 # gfx950 hot loop of the mixed-precision 4x4 kernel with J, per 16 evaluations (time
-# step x direction tile), counted in the assembly by tests/test_codegen.py: 203 VALU
+# step x direction tile), counted in the assembly by tests/test_codegen.py: 201 VALU
 # instructions, 14 of them transcendental (7 v_sin_f32 + 7 v_cos_f32).
-MIXED_VALU_PER_16 = 203
+MIXED_VALU_PER_16 = 201
 MIXED_TRANS_PER_16 = 14
 VALU_LANE_PEAK_T = 256 * 64 * 2.4e9 / 1e12   # lane-instructions per second at 2.4 GHz, 1e12
 

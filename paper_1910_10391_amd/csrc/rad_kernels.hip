@@ -89,16 +89,23 @@ __device__ __forceinline__ void lane_cis(double kh, double part, double &c, doub
 // step, direction tile) pairs and, in the mixed form, the trajectory columns of the
 // pass's time steps (the ten columns and the weight).
 constexpr int kRowCols = C_NCOL + 1;   // + the quadrature weight
+// One staged (time step, direction tile) slot: the integrand of the tile's directions and the
+// phase parts.  Kept together, so that a time step's reads in the hot loop all sit at fixed
+// offsets from one address, which advances once per step.
+template <int TX, int TY, bool WITHJ>
+struct AmpSlot {
+    double2 fxy[TX * TY];
+    double fq[WITHJ ? TX * TY : 1];
+    double px[TX];
+    double py[TY];
+};
 template <int TX, int TY, bool WITHJ, bool ROWS>
 struct AmpSmem {
     double row[ROWS ? kRowCols : 1][ROWS ? kSlots : 1];
     // mixed form: the block's direction tiles, thx then thy (0 outside), and which exist
     double th[ROWS ? kWavesPerBlock : 1][TX + TY];
     unsigned char thok[ROWS ? kWavesPerBlock : 1][TX + TY];
-    double2 fxy[kSlots * TX * TY];
-    double fq[WITHJ ? kSlots * TX * TY : 1];
-    double px[kSlots * TX];
-    double py[kSlots * TY];
+    AmpSlot<TX, TY, WITHJ> slot[kSlots];
     int seg;
 };
 
@@ -110,10 +117,7 @@ template <int TX, int TY, bool WITHJ, bool MIXED, bool REC, bool CELLS = true>
 __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<TX, TY, WITHJ, MIXED> &sm)
 {
     constexpr int NP = TX * TY;
-    double2 *const s_fxy = sm.fxy;
-    double *const s_fq = sm.fq;
-    double *const s_px = sm.px;
-    double *const s_py = sm.py;
+    AmpSlot<TX, TY, WITHJ> *const s_slot = sm.slot;
 
     // cell refinement with a device mask: the live items were compacted to the front
     // of the list, and the blocks past them leave at once
@@ -317,8 +321,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     fq = (thx * ax + thy * ay + az) * G;
                 }
             }
-            s_fxy[i] = make_double2(fx, fy);
-            if constexpr (WITHJ) s_fq[i] = fq;
+            s_slot[slot].fxy[p] = make_double2(fx, fy);
+            if constexpr (WITHJ) s_slot[slot].fq[p] = fq;
         }
         if constexpr (REC) {
             // uniform grids: per (time step, tile) the phase of the tile's first
@@ -344,7 +348,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     else
                         v = dth * ((thy0 + 0.5 * dth) * t - col(C_Y, tloc, k));
                 }
-                if (j < 3) s_px[slot * TX + j] = v; else s_py[slot * TY] = v;
+                if (j < 3) s_slot[slot].px[j] = v; else s_slot[slot].py[0] = v;
             }
         } else {
             for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
@@ -364,7 +368,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     else
                         v = (th - thy0) * (0.5 * (th + thy0) * t - y);
                 }
-                if (j < TX) s_px[slot * TX + j] = v; else s_py[slot * TY + (j - TX)] = v;
+                if (j < TX) s_slot[slot].px[j] = v; else s_slot[slot].py[j - TX] = v;
             }
         }
         __syncthreads();
@@ -377,12 +381,13 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             // phase part) before the X phase factors, so that their latency is hidden
             double2 fn[TX];
             double qn[TX];
-            double pyn = (MIXED && TY > 1) ? s_py[slot * TY + 1] : 0.0;
+            const AmpSlot<TX, TY, WITHJ> &S_ = s_slot[slot];
+            double pyn = (MIXED && TY > 1) ? S_.py[1] : 0.0;
             if constexpr (!REC) {
 #pragma unroll
                 for (int jx = 0; jx < TX; ++jx) {
-                    fn[jx] = s_fxy[slot * NP + jx];
-                    if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + jx];
+                    fn[jx] = S_.fxy[jx];
+                    if constexpr (WITHJ) qn[jx] = S_.fq[jx];
                 }
             }
             // uniform grids: the phase along x and along y is quadratic in the direction
@@ -393,9 +398,9 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             double br = 0.0, bi = 0.0, sr = 0.0, si = 0.0;
             if constexpr (REC) {
                 double rr, ri;
-                lane_cis<false>(kh, s_px[slot * TX], xr[0], xi[0]);
-                lane_cis<false>(kh, s_px[slot * TX + 1], rr, ri);
-                lane_cis<false>(kh, s_px[slot * TX + 2], br, bi);
+                lane_cis<false>(kh, S_.px[0], xr[0], xi[0]);
+                lane_cis<false>(kh, S_.px[1], rr, ri);
+                lane_cis<false>(kh, S_.px[2], br, bi);
 #pragma unroll
                 for (int jx = 1; jx < TX; ++jx) {
                     xr[jx] = xr[jx - 1] * rr - xi[jx - 1] * ri;
@@ -406,10 +411,10 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                         rr = t_;
                     }
                 }
-                lane_cis<false>(kh, s_py[slot * TY], sr, si);
+                lane_cis<false>(kh, S_.py[0], sr, si);
             } else {
 #pragma unroll
-                for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, s_px[slot * TX + jx], xr[jx], xi[jx]);
+                for (int jx = 0; jx < TX; ++jx) lane_cis<MIXED>(kh, S_.px[jx], xr[jx], xi[jx]);
             }
             double yr = 0.0, yi = 0.0;
 #pragma unroll
@@ -426,8 +431,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     // the recurrence form keeps its y state in the registers the next
                     // row's prefetched integrand values would take, so it reads them here
                     if constexpr (REC) {
-                        f[jx] = s_fxy[slot * NP + jy * TX + jx];
-                        if constexpr (WITHJ) q[jx] = s_fq[slot * NP + jy * TX + jx];
+                        f[jx] = S_.fxy[jy * TX + jx];
+                        if constexpr (WITHJ) q[jx] = S_.fq[jy * TX + jx];
                     } else {
                         f[jx] = fn[jx];
                         if constexpr (WITHJ) q[jx] = qn[jx];
@@ -454,8 +459,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                     // this row's phase part: the mixed form reads the next row's one region
                     // ahead; the FP64 direct form reads it here (with that prefetch the
                     // allocator spilled two accumulators in this loop)
-                    const double py = MIXED ? pyn : s_py[slot * TY + jy];
-                    if (MIXED && jy + 1 < TY) pyn = s_py[slot * TY + jy + 1];
+                    const double py = MIXED ? pyn : S_.py[jy];
+                    if (MIXED && jy + 1 < TY) pyn = S_.py[jy + 1];
                     lane_cis<MIXED>(kh, py, yr, yi);
                 }
 #pragma unroll
@@ -475,8 +480,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
                 if (!REC && jy + 1 < TY) {
 #pragma unroll
                     for (int jx = 0; jx < TX; ++jx) {
-                        fn[jx] = s_fxy[slot * NP + (jy + 1) * TX + jx];
-                        if constexpr (WITHJ) qn[jx] = s_fq[slot * NP + (jy + 1) * TX + jx];
+                        fn[jx] = S_.fxy[(jy + 1) * TX + jx];
+                        if constexpr (WITHJ) qn[jx] = S_.fq[(jy + 1) * TX + jx];
                     }
                 }
             }

@@ -17,16 +17,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (kernel symbol, VALU instructions in the hot loop per time step: 16 evaluations for a 4x4
 # tile)
 HOT = {
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 278,   # FP64, J, recurrence
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 310,   # FP64, J, direct
-    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 203,   # mixed, J
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 278,
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 310,
-    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 203,
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 275,   # FP64, J, recurrence
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 308,   # FP64, J, direct
+    "_ZN3rad10amp_kernelILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 201,   # mixed, J
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 275,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 308,
+    "_ZN3rad14amp_persistentILi4ELi4ELb1ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 201,
     # 4x6 tile without J: per 24 evaluations
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 326,   # FP64, recurrence
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 388,   # FP64, direct
-    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 251,   # mixed
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb1EEEvNS_9AmpLaunchE": 323,   # FP64, recurrence
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb0ELi2ELb0EEEvNS_9AmpLaunchE": 386,   # FP64, direct
+    "_ZN3rad10amp_kernelILi4ELi6ELb0ELb1ELi2ELb0EEEvNS_9AmpLaunchE": 249,   # mixed
 }
 
 
