@@ -86,8 +86,9 @@ __device__ __forceinline__ void lane_cis(double kh, double part, double &c, doub
 }
 
 // LDS of one work item: the staged integrand and phase parts of kSlots (time
-// step, direction tile) pairs and, in the mixed form, the trajectory columns of the
-// pass's time steps (the ten columns and the weight).
+// step, direction tile) pairs, the angles of the item's direction tiles and, in the
+// mixed form, the trajectory columns of the pass's time steps (the ten columns and the
+// weight).
 constexpr int kRowCols = C_NCOL + 1;   // + the quadrature weight
 // One staged (time step, direction tile) slot: the integrand of the tile's directions and the
 // phase parts.  Kept together, so that a time step's reads in the hot loop all sit at fixed
@@ -102,9 +103,9 @@ struct AmpSlot {
 template <int TX, int TY, bool WITHJ, bool ROWS>
 struct AmpSmem {
     double row[ROWS ? kRowCols : 1][ROWS ? kSlots : 1];
-    // mixed form: the block's direction tiles, thx then thy (0 outside), and which exist
-    double th[ROWS ? kWavesPerBlock : 1][TX + TY];
-    unsigned char thok[ROWS ? kWavesPerBlock : 1][TX + TY];
+    // the block's direction tiles, thx then thy (0 outside), and which exist
+    double th[kWavesPerBlock][TX + TY];
+    unsigned char thok[kWavesPerBlock][TX + TY];
     AmpSlot<TX, TY, WITHJ> slot[kSlots];
     int seg;
 };
@@ -209,12 +210,11 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     }
     const double kh = MIXED ? kappa * (0.5 / kPi) : kappa * (1.0 / kPi);
 
-    // mixed form: the angles of the block's nt direction tiles, once per item (the
-    // staging loops then index them instead of dividing by the grid's tile count); the
-    // first barrier of the time loop orders these writes before any read.  The FP64
-    // form measured slower with the table (one more accumulator spilled in the
-    // persistent kernel) and computes the directions in the staging loops.
-    for (int i = threadIdx.x; i < (MIXED ? nt * (TX + TY) : 0); i += kBlock) {
+    // the angles of the block's nt direction tiles, once per item: the staging loops then
+    // read them instead of dividing by the grid's tile count for every staged value (in
+    // the FP64 form that index arithmetic had been about half of a staged value's
+    // instructions); the first barrier of the time loop orders these writes before any read
+    for (int i = threadIdx.x; i < nt * (TX + TY); i += kBlock) {
         const int tile = i / (TX + TY), j = i % (TX + TY);
         const int gt = grp * nt + tile;
         double th = 0.0;
@@ -236,24 +236,8 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
     // direction j (thx for j < TX, else thy) of tile `tile`: its angle (0 outside the
     // grid) and whether it exists
     auto direction = [&](int tile, int j, double &th) -> bool {
-        if constexpr (MIXED) {
-            th = sm.th[tile][j];
-            return sm.thok[tile][j] != 0;
-        } else {
-            const int gt = grp * nt + tile;
-            th = 0.0;
-            if (gt >= n_tiles) return false;
-            if (j < TX) {
-                const int jx = (gt % n_tx) * TX + j;
-                if (jx >= n_x) return false;
-                th = g_thx[jx];
-            } else {
-                const int jy = (gt / n_tx) * TY + (j - TX);
-                if (jy >= n_y) return false;
-                th = g_thy[jy];
-            }
-            return true;
-        }
+        th = sm.th[tile][j];
+        return sm.thok[tile][j] != 0;
     };
 
     double axr[NP], axi[NP], ayr[NP], ayi[NP], jr[WITHJ ? NP : 1], ji[WITHJ ? NP : 1];
@@ -290,7 +274,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         // ---- stage: integrand and phase parts for kSlots (t, tile) pairs
         for (int i = threadIdx.x; i < kSlots * NP; i += kBlock) {
             const int slot = i / NP, p = i % NP;
-            const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
+            const int tloc = slot >> lnt, tile = slot & (nt - 1);
             const int64_t k = k0 + tloc;
             double fx = 0.0, fy = 0.0, fq = 0.0, thx, thy;
             const bool okx = direction(tile, p % TX, thx), oky = direction(tile, TX + p / TX, thy);
@@ -330,7 +314,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             const double dth = S.dth;
             for (int i = threadIdx.x; i < kSlots * 4; i += kBlock) {
                 const int slot = i >> 2, j = i & 3;
-                const int tloc = slot / nt, tile = slot % nt;
+                const int tloc = slot >> lnt, tile = slot & (nt - 1);
                 const int64_t k = k0 + tloc;
                 double v = 0.0;
                 if (k < k_end && grp * nt + tile < n_tiles) {
@@ -353,7 +337,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
         } else {
             for (int i = threadIdx.x; i < kSlots * (TX + TY); i += kBlock) {
                 const int slot = i / (TX + TY), j = i % (TX + TY);
-                const int tloc = MIXED ? slot >> lnt : slot / nt, tile = MIXED ? slot & (nt - 1) : slot % nt;
+                const int tloc = slot >> lnt, tile = slot & (nt - 1);
                 const int64_t k = k0 + tloc;
                 double v = 0.0;
                 if (k < k_end && grp * nt + tile < n_tiles) {
