@@ -67,7 +67,7 @@ VALU_PER_EVAL_44 = {(True, False): 308.0 / 16.0, (False, False): 276.0 / 16.0,
 # that leaves amp_persistent's gfx950 assembly identical is carried over after checking that).
 KERNEL_SOURCES = ["paper_1910_10391_amd/csrc/rad_kernels.hip", "paper_1910_10391_amd/csrc/rad_math.h",
                   "paper_1910_10391_amd/csrc/sincos_coeffs.h", "paper_1910_10391_amd/csrc/rad_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "14c2ca8f47f83a5c", "particles": 256, "kernel": "amp_persistent",
+MEASURED_TRAFFIC = {"sources_sha256": "2478343747b288b1", "particles": 256, "kernel": "amp_persistent",
                     "bytes_per_launch": 1.5467e10}
 
 

@@ -16,7 +16,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSlots = 128;  // time-steps x direction-tiles staged in LDS per pass
+constexpr int kLogSlots = 7;
+constexpr int kSlots = 1 << kLogSlots;  // time-steps x direction-tiles staged in LDS per pass
 
 // Amplitude-kernel variants: direction tile TX x TY and minimum resident blocks per CU.
 enum Variant { kVar44x2 = 0, kVar43x2 = 1, kVar44x1 = 2, kVar42x2 = 3, kVar46x2 = 4, kNumVariants = 5 };

@@ -258,7 +258,7 @@ __device__ __forceinline__ void amp_item(const AmpLaunch &L, int64_t b, AmpSmem<
             // instead of once per (time step, direction).  The FP64 form measured
             // faster reading the columns directly, so only the mixed form does this.
             for (int i = threadIdx.x; i < kRowCols * T; i += kBlock) {
-                const int c = i / T, tloc = i % T;
+                const int c = i >> (kLogSlots - lnt), tloc = i & (T - 1);   // T = kSlots / nt
                 const int64_t k = k0 + tloc;
                 double v = 0.0;
                 if (k < k_end) v = c < C_NCOL ? S.col[c][k] : weight(k);
