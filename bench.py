@@ -93,8 +93,9 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one device copy of known size first (counter scale factor)")
     p.add_argument("--no-legs", action="store_true",
-                   help="skip the secondary legs of the default line (mixed-precision, sections, sweep "
-                        "and trajectory-generator workloads, learned sampler, issue-rate ceilings)")
+                   help="skip the secondary legs of the default line (mixed-precision, sections, "
+                        "undulator, sweep and trajectory-generator workloads, learned sampler, "
+                        "issue-rate ceilings)")
     return p.parse_args()
 
 
@@ -716,6 +717,47 @@ def leg_sections():
                                   "sample": "trajectory 0 (10 sections), every 8th energy, 4x4 strided directions"}}
 
 
+def leg_undulator():
+    """The smallest configuration: one electron on the analytic undulator trajectory (gamma 2e4,
+    K 0.5, 20 periods of 20 um in 8192 steps), FP64 classical spectrum on 128 linear hw up to
+    1.5 x the first harmonic x 16 x 16 directions within 1/gamma; GPU time per call (median of
+    repeated calls, inputs resident) and the whole cube against the oracle."""
+    import torch
+    import oracle
+    from paper_1910_10391_amd import rad
+    from paper_1910_10391_amd.synth import presets
+    c = presets.undulator_fp64()
+    g = c["grid"]
+    seg = c["segments"][0]
+    ds = rad.DeviceSegments([seg])
+    grid = rad.Grid(g.hw_eV, g.thx, g.thy)
+    ws = torch.empty(rad.workspace_bytes(grid, ds.n[0], rad.CLASSICAL, rad.FP64), dtype=torch.uint8, device="cuda")
+    out = torch.empty(grid.shape, dtype=torch.float64, device="cuda")
+    run = lambda: rad.classical(grid, ds, out=out, workspace=ws)  # noqa: E731
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    evals = int(seg["t"].size) * int(np.prod(grid.shape))
+    t0 = time.perf_counter()
+    ref = oracle.spectrum(seg, g.hw_eV, g.thx, g.thy, oracle.KIND_CLASSICAL)[oracle.KIND_CLASSICAL]
+    cpu = time.perf_counter() - t0
+    m1, m2 = rel_metrics(out.cpu().numpy(), ref)
+    grid.close()
+    print("bench leg undulator: gpu %.3f ms per call, oracle %.3f s, M1 %.2e" % (dt * 1e3, cpu, m1),
+          file=sys.stderr, flush=True)
+    return {"workload": "undulator_fp64: 1 e- at gamma 2e4, K 0.5, 20 periods of 20 um in 8192 steps; FP64 "
+                        "classical, 128 linear hw up to 1.5 x the first harmonic x 16x16 within 1/gamma",
+            "evals": evals, "gpu_ms_per_call": dt * 1e3, "evals_per_s": evals / dt,
+            "cpu_oracle_s": cpu, "cpu_cores": oracle.max_threads(), "speedup_vs_oracle": cpu / dt,
+            "rel_err_vs_oracle": {"M1": m1, "M2": m2, "sample": "the whole cube"}}
+
+
 def leg_traj():
     """The GPU trajectory generator on the benchmark's 256 positrons against the CPU generator
     on the host's cores (and the host-to-device copy the GPU generator saves); four of the
@@ -949,6 +991,7 @@ def main():
         torch.cuda.empty_cache()
         legs["electron_50gev_sections"] = run_leg("sections", leg_sections)
         torch.cuda.empty_cache()
+        legs["undulator"] = run_leg("undulator", leg_undulator)
         legs["sweep"] = run_leg("sweep", leg_sweep)
         torch.cuda.empty_cache()
         legs["traj"] = run_leg("traj", leg_traj)
