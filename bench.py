@@ -798,7 +798,7 @@ SAMPLER_CKPT = os.path.join(ROOT, "paper_1910_10391_amd", "weights", "positron_s
 def leg_sampler(n_test=32):
     """The learned angular sampler (committed network) on held-out positrons: spin-1/2 on
     512 log hw x 64 x 64 directions within 5/gamma, 8 x 8 cells; against the full grid in
-    mixed precision (the judge of its error) and in plain FP64."""
+    mixed precision (the reference for its error) and in plain FP64."""
     import torch
     from paper_1910_10391_amd import rad, sampler
     from paper_1910_10391_amd.synth import channeling, presets

@@ -5,8 +5,8 @@
  * FP64 kernel; it is not in the paper) predicts the log-intensity
  * log d2I/(d hw dOmega) over (hw, thx, thy) from trajectory features, and decides
  * where the angular grid is refined; the exact integrals of include/rad.h
- * (rad_batch on a coarse grid, rad_cells on the refined cells) stay the judge of
- * its error.  The network: inputs [n_feat trajectory features, n_point point
+ * (rad_batch on a coarse grid, rad_cells on the refined cells) stay the reference
+ * for its error.  The network: inputs [n_feat trajectory features, n_point point
  * inputs] (n_feat + n_point <= 64) -> 256 -> 256 -> 256 -> 1, SiLU activations,
  * BF16 weights and activations, FP32 accumulation (the dense products run on
  * the MFMA units), mean-squared-error loss, Adam with FP32 master weights.

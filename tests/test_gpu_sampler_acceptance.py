@@ -5,7 +5,7 @@
 The network is the committed checkpoint written by ``python -m
 paper_1910_10391_amd.train_sampler`` (trained on the GPU by the library's own BF16
 kernels on spectra the library computed; loaded without pickle).  Against the full-grid
-angle integral of the same trajectories (the judge of the sampler's error):
+angle integral of the same trajectories (the reference for the sampler's error):
 
 * acceptance: the largest relative error of dI/d hw (energies above 1e-3 of the peak)
   is at most 1 %;
